@@ -1,0 +1,281 @@
+"""Python front end of the FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the
+benchmark's CPU-baseline leg, never by the product package.  It shares no code
+with the HIP path.  Inputs are the float32 arrays of the seeded scene generator,
+promoted to float64 here; every arithmetic step of the method runs in oracle.c
+(in double precision) except the tile binning reference below, which is the
+plain definition written with numpy.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+OPTS_DEFAULT = dict(step1=1, step2=2, lambda_=0.5, orient_sign=1, prune_Tk=0.0, eps_n=1e-9)
+
+NS_BORDER, NS_ZERO, NS_VALID = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (-O2, no fast-math, OpenMP) into liboracle.so."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
+                           "-shared", "-std=c11", "-Wall", "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class _Cam(C.Structure):
+    _fields_ = [("W", C.c_int), ("H", C.c_int), ("fx", C.c_double), ("fy", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double), ("R", C.c_double * 9), ("t", C.c_double * 3),
+                ("z_near", C.c_double)]
+
+
+class _Gs(C.Structure):
+    _fields_ = [("N", C.c_int64), ("sh_deg", C.c_int), ("C_o", C.c_int),
+                ("mean", C.c_void_p), ("quat", C.c_void_p), ("log_scale", C.c_void_p),
+                ("opacity_logit", C.c_void_p), ("mask_logit", C.c_void_p), ("sh", C.c_void_p),
+                ("sem", C.c_void_p)]
+
+
+class _Opt(C.Structure):
+    _fields_ = [("step1", C.c_int), ("step2", C.c_int), ("lambda_", C.c_double),
+                ("orient_sign", C.c_int), ("prune_Tk", C.c_double), ("eps_n", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        _lib = C.CDLL(LIB)
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class _Scene:
+    """Holds float64 copies of the Gaussian arrays and the ctypes struct."""
+
+    def __init__(self, g):
+        self.arrs = {k: np.ascontiguousarray(g[k], dtype=np.float64)
+                     for k in ("mean", "quat", "log_scale", "opacity_logit", "mask_logit", "sh", "sem")}
+        self.N, self.sh_deg, self.C_o = int(g["N"]), int(g["sh_deg"]), int(g["C_o"])
+        a = self.arrs
+        self.s = _Gs(self.N, self.sh_deg, self.C_o, _p(a["mean"]), _p(a["quat"]), _p(a["log_scale"]),
+                     _p(a["opacity_logit"]), _p(a["mask_logit"]), _p(a["sh"]), _p(a["sem"]))
+
+
+def _cam(cam):
+    c = _Cam()
+    c.W, c.H = int(cam["W"]), int(cam["H"])
+    c.fx, c.fy, c.cx, c.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
+    R = np.asarray(cam["R"], dtype=np.float64).reshape(9)
+    t = np.asarray(cam["t"], dtype=np.float64).reshape(3)
+    for i in range(9):
+        c.R[i] = float(R[i])
+    for i in range(3):
+        c.t[i] = float(t[i])
+    c.z_near = float(cam.get("z_near", 0.2))
+    return c
+
+
+def _opt(opts=None):
+    o = dict(OPTS_DEFAULT)
+    if opts:
+        for k, v in opts.items():
+            o["lambda_" if k == "lambda" else k] = v
+    return _Opt(int(o["step1"]), int(o["step2"]), float(o["lambda_"]), int(o["orient_sign"]),
+                float(o["prune_Tk"]), float(o["eps_n"]))
+
+
+def _scene(g):
+    return g if isinstance(g, _Scene) else _Scene(g)
+
+
+def project(g, cam, opts=None):
+    """Per-Gaussian projection of one view (EWA footprint, colour, depth key)."""
+    S = _scene(g)
+    N = S.N
+    out = dict(visible=np.zeros(N, np.int32), ambiguous=np.zeros(N, np.int32),
+               mean2d=np.zeros((N, 2)), conic=np.zeros((N, 3)), cov2d=np.zeros((N, 3)),
+               opacity=np.zeros(N), k=np.zeros(N), rgb=np.zeros((N, 3)), rgb_raw=np.zeros((N, 3)),
+               depth=np.zeros(N), radius=np.zeros((N, 2)))
+    L = lib()
+    L.orc_project(C.byref(S.s), C.byref(_cam(cam)), C.byref(_opt(opts)),
+                  *[_p(out[k]) for k in ("visible", "ambiguous", "mean2d", "conic", "cov2d", "opacity", "k",
+                                         "rgb", "rgb_raw", "depth", "radius")])
+    return out
+
+
+def render(g, cam, opts=None, path=1, pixmask=None):
+    """Forward maps of one view: rgb [3][H][W], depth, kmap, sem [C_o][H][W],
+    T_final, last_id (id of the last contributor, -1 if none), n_frag,
+    n_clamped, and the per-pixel decision margins."""
+    S = _scene(g)
+    H, W = int(cam["H"]), int(cam["W"])
+    out = dict(rgb=np.zeros((3, H, W)), depth=np.zeros((H, W)), kmap=np.zeros((H, W)),
+               sem=np.zeros((S.C_o, H, W)), T_final=np.ones((H, W)), last_id=np.full((H, W), -1, np.int32),
+               n_frag=np.zeros((H, W), np.int32), n_clamped=np.zeros((H, W), np.int32),
+               margin=np.full((H, W), np.inf), grad_margin=np.full((H, W), np.inf))
+    pm = None if pixmask is None else np.ascontiguousarray(pixmask, dtype=np.uint8)
+    rc = lib().orc_render(C.byref(S.s), C.byref(_cam(cam)), C.byref(_opt(opts)), int(path), _p(pm),
+                          *[_p(out[k]) for k in ("rgb", "depth", "kmap", "sem", "T_final", "last_id",
+                                                 "n_frag", "n_clamped", "margin", "grad_margin")])
+    if rc != 0:
+        raise RuntimeError(f"orc_render failed ({rc})")
+    return out
+
+
+def normals(depth, cam, opts=None, pixmask=None):
+    """Alg. normal_estimation on a depth image: normal [3][H][W] (world frame),
+    state per pixel (low 2 bits: 0 border, 1 degenerate, 2 valid; bit 2: the
+    view-facing flip was applied; bit 3: n2 was sign-flipped for consistency)
+    and decision margins."""
+    H, W = int(cam["H"]), int(cam["W"])
+    d = np.ascontiguousarray(depth, dtype=np.float64).reshape(H, W)
+    out = dict(normal=np.zeros((3, H, W)), state=np.zeros((H, W), np.int32), margin=np.full((H, W), np.inf))
+    pm = None if pixmask is None else np.ascontiguousarray(pixmask, dtype=np.uint8)
+    lib().orc_normals(_p(d), C.byref(_cam(cam)), C.byref(_opt(opts)), _p(pm),
+                      _p(out["normal"]), _p(out["state"]), _p(out["margin"]))
+    return out
+
+
+def normal_backward(depth, cam, dnormal, opts=None):
+    """Alg. normal_gradient: dL/dN [3][H][W] -> dL/dD [H][W] at the given depth."""
+    H, W = int(cam["H"]), int(cam["W"])
+    d = np.ascontiguousarray(depth, dtype=np.float64).reshape(H, W)
+    dn = np.ascontiguousarray(dnormal, dtype=np.float64).reshape(3, H, W)
+    gD = np.zeros((H, W))
+    lib().orc_normal_backward(_p(d), C.byref(_cam(cam)), C.byref(_opt(opts)), _p(dn), _p(gD))
+    return gD
+
+
+def zero_grads(g):
+    N, C_o = int(g["N"]), int(g["C_o"])
+    nc = (int(g["sh_deg"]) + 1) ** 2
+    return dict(mean=np.zeros((3, N)), quat=np.zeros((4, N)), log_scale=np.zeros((3, N)),
+                opacity_logit=np.zeros(N), mask_logit=np.zeros(N), sh=np.zeros((nc, 3, N)),
+                sem=np.zeros((N, C_o)))
+
+
+def backward(g, cam, up, depth, opts=None, path=1, pixmask=None, grads=None):
+    """Gradients of L = <up, outputs> for one view, ADDED to `grads` (created if
+    None).  `up` holds planar upstream maps rgb/depth/kmap/normal/sem; `depth` is
+    the forward depth image.  Returns (grads, gD) where gD = dL/dD + normal branch."""
+    S = _scene(g)
+    H, W = int(cam["H"]), int(cam["W"])
+    gr = zero_grads(g) if grads is None else grads
+    f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    d = f64(depth).reshape(H, W)
+    ups = dict(rgb=f64(up["rgb"]).reshape(3, H, W), depth=f64(up["depth"]).reshape(H, W),
+               kmap=f64(up["kmap"]).reshape(H, W), normal=f64(up["normal"]).reshape(3, H, W),
+               sem=f64(up["sem"]).reshape(S.C_o, H, W))
+    gD = np.zeros((H, W))
+    pm = None if pixmask is None else np.ascontiguousarray(pixmask, dtype=np.uint8)
+    rc = lib().orc_backward(C.byref(S.s), C.byref(_cam(cam)), C.byref(_opt(opts)), int(path), _p(pm), _p(d),
+                            _p(ups["rgb"]), _p(ups["depth"]), _p(ups["kmap"]), _p(ups["normal"]), _p(ups["sem"]),
+                            *[_p(gr[k]) for k in ("mean", "quat", "log_scale", "opacity_logit", "mask_logit",
+                                                  "sh", "sem")], _p(gD))
+    if rc != 0:
+        raise RuntimeError(f"orc_backward failed ({rc})")
+    return gr, gD
+
+
+def forward_all(g, cams, opts=None, path=1):
+    """Every output of every view: render + normals."""
+    S = _scene(g)
+    outs = []
+    for cam in cams:
+        o = render(S, cam, opts, path)
+        n = normals(o["depth"], cam, opts)
+        o["normal"], o["nstate"], o["nmargin"] = n["normal"], n["state"], n["margin"]
+        outs.append(o)
+    return outs
+
+
+def backward_all(g, cams, ups, outs, opts=None, path=1):
+    """Parameter gradients of L = sum over views of <up_v, outputs_v>."""
+    S = _scene(g)
+    gr = zero_grads(g)
+    gDs = []
+    for cam, up, o in zip(cams, ups, outs):
+        _, gD = backward(S, cam, up, o["depth"], opts, path, grads=gr)
+        gDs.append(gD)
+    return gr, gDs
+
+
+def loss(g, cams, ups, opts=None, path=1):
+    """L = sum_v <up_v, (rgb, depth, kmap, normal, sem)_v> in float64."""
+    outs = forward_all(g, cams, opts, path)
+    L = 0.0
+    for up, o in zip(ups, outs):
+        for k in ("rgb", "depth", "kmap", "normal", "sem"):
+            L += float(np.sum(np.asarray(up[k], np.float64).reshape(o[k].shape) * o[k]))
+    return L, outs
+
+
+def sh_basis(deg, d):
+    Y = np.zeros(16)
+    dY = np.zeros(48)
+    dd = np.ascontiguousarray(d, dtype=np.float64)
+    lib().orc_sh_basis(int(deg), _p(dd), _p(Y), _p(dY))
+    return Y, dY.reshape(16, 3)
+
+
+def fragment_depth(g, cam, i, u, v, opts=None):
+    """Literal ray-ellipsoid midpoint depth of Gaussian i at (u, v): returns
+    (d, t_mid, a, b, c) of the unit-sphere quadratic."""
+    S = _scene(g)
+    out = np.zeros(5)
+    lib().orc_fragment_depth(C.byref(S.s), C.byref(_cam(cam)), C.byref(_opt(opts)), C.c_int64(int(i)),
+                             C.c_double(float(u)), C.c_double(float(v)), _p(out))
+    return out
+
+
+def max_threads():
+    return int(lib().orc_max_threads())
+
+
+# ------------------------------------------------------------------ binning
+def bin_sort(rect, depth_f32, tiles_x, tile_base, N):
+    """Reference tile binning: for every (view, Gaussian) and every tile of its
+    rectangle emit (global tile, float bits of the depth key, Gaussian id) and
+    sort lexicographically.  rect is [V*N][4] = (tx0, ty0, tx1, ty1), half-open;
+    depth_f32 the float32 depth keys [V*N]; tiles_x[v] the tile-grid width of
+    view v and tile_base[v] its first global tile.  Returns (keys u64, vals u32,
+    per-(view,Gaussian) tile counts)."""
+    rect = np.asarray(rect, dtype=np.int64).reshape(-1, 4)
+    VN = rect.shape[0]
+    w = np.maximum(rect[:, 2] - rect[:, 0], 0)
+    h = np.maximum(rect[:, 3] - rect[:, 1], 0)
+    counts = (w * h).astype(np.int64)
+    total = int(counts.sum())
+    idx = np.repeat(np.arange(VN), counts)
+    start = np.repeat(np.cumsum(counts) - counts, counts)
+    k = np.arange(total) - start
+    wi = np.maximum(w[idx], 1)
+    tx = rect[idx, 0] + k % wi
+    ty = rect[idx, 1] + k // wi
+    view = idx // N
+    gid = (idx % N).astype(np.uint32)
+    tile = np.asarray(tile_base, np.int64)[view] + ty * np.asarray(tiles_x, np.int64)[view] + tx
+    dbits = np.asarray(depth_f32, dtype=np.float32).reshape(-1).view(np.uint32)[idx].astype(np.uint64)
+    keys = (tile.astype(np.uint64) << np.uint64(32)) | dbits
+    order = np.lexsort((gid, dbits, tile))
+    return keys[order], gid[order], counts
