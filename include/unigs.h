@@ -1,0 +1,226 @@
+/*
+ * unigs.h -- C ABI of the MI355X (gfx950) multimodal Gaussian rasterizer.
+ *
+ * The library implements the rendering hot path of UniGS (arXiv 2510.12174):
+ * tile-based differentiable rasterization of 3D Gaussians that renders, in one
+ * pass, RGB, ray-ellipsoid midpoint depth, world-frame normals estimated from
+ * depth, semantic logits and the gradient-factor map (section 3.2 "Geometry-
+ * Aware Rasterization", section 3.3 "Differentiable Pruning", section 3.4 and
+ * Alg. forward_render), and the analytic backward of all of them into the
+ * Gaussian parameters (supplementary S1.2, S1.4, S1.6; Alg. normal_gradient,
+ * Alg. backward_render).
+ *
+ * Conventions shared by every entry point
+ *  - All tensor pointers are DEVICE pointers owned by the caller, FP32 unless
+ *    stated, contiguous, at least 16-byte aligned.  Struct arguments and camera
+ *    arrays are HOST memory, read during the call only.
+ *  - Layouts are planar.  Gaussian parameters (structure of arrays):
+ *      mean [3][N], quat [4][N] as (w,x,y,z) (need not be normalised),
+ *      log_scale [3][N], opacity_logit [N], mask_logit [N] (gradient factor
+ *      k = sigmoid(mask_logit)), sh [(sh_deg+1)^2][3][N], sem [N][C_o].
+ *    Image maps of view v are [C][H_v][W_v]; several views are stored one after
+ *    the other, so view v's plane set starts at element C * pix_off(v) with
+ *    pix_off(v) = sum over u < v of W_u * H_u.
+ *  - Every call is asynchronous on `stream` (a hipStream_t, NULL = the legacy
+ *    default stream) unless stated.  No call allocates device memory: scratch
+ *    space is one caller-allocated workspace sized by ugs_workspace_size().
+ *  - Errors are returned as negative status codes (never thrown, never a trap).
+ *    Invalid arguments are rejected before anything is launched.
+ *  - Inputs are never modified.  Gradient outputs are ACCUMULATED (+=): the
+ *    caller zero-fills them before the first backward.
+ */
+#ifndef UNIGS_H
+#define UNIGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define UGS_OK 0
+#define UGS_ERR_INVALID_ARG (-1)  /* null/misaligned pointer, bad size or option      */
+#define UGS_ERR_UNSUPPORTED (-2)  /* C_o > UGS_MAX_CHANNELS, sh_deg > 3, tile shape   */
+#define UGS_ERR_CAPACITY (-3)     /* more (tile, Gaussian) pairs than pair_capacity   */
+#define UGS_ERR_HIP (-4)          /* a HIP runtime call failed (see ugs_last_hip_error) */
+#define UGS_ERR_NOT_CAPTURED (-5) /* ugs_step_replay without a captured step          */
+#define UGS_ERR_STATE (-6)        /* calls out of order (e.g. render before bin_sort)  */
+
+#define UGS_MAX_CHANNELS 128 /* semantic channels C_o supported */
+#define UGS_MAX_VIEWS 64
+
+/* Pinhole camera (supplementary S1.3): x_cam = R x_world + t, pixel
+ * (u, v) = (fx x/z + cx, fy y/z + cy).  R is row-major.  The ray of pixel (u,v)
+ * is C + s * normalize(R^T ((u-cx)/fx, (v-cy)/fy, 1)) with C = -R^T t (Eq.
+ * computeRay).  Gaussians with camera depth <= z_near are culled. */
+typedef struct {
+    int W, H;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float z_near;
+} ugs_camera;
+
+/* Gaussian parameters G = {mu, q, s, alpha, h, o, k} (Eq. gs_representation),
+ * stored as the raw (pre-activation) values: s = exp(log_scale),
+ * opacity = sigmoid(opacity_logit), k = sigmoid(mask_logit). */
+typedef struct {
+    int64_t N;
+    int sh_deg; /* 0..3 */
+    int C_o;    /* 0..UGS_MAX_CHANNELS */
+    const float *mean, *quat, *log_scale, *opacity_logit, *mask_logit, *sh, *sem;
+} ugs_gaussians;
+
+/* Gradients with respect to the same parameters, same layouts (accumulated). */
+typedef struct {
+    float *mean, *quat, *log_scale, *opacity_logit, *mask_logit, *sh, *sem;
+} ugs_gaussian_grads;
+
+/* Forward outputs, all views (layout above).  rgb [3], depth [1] (alpha-blended
+ * midpoint depth, Eq. depth_render, background 0), kmap [1] (gradient-factor map,
+ * Eq. t_render), normal [3] (world frame, Alg. normal_estimation; 0 where the
+ * stencil leaves the image or is degenerate), sem [C_o] (Eq. semantic_render),
+ * T_final [1] (transmittance after the last contributor, saved for the backward
+ * as in Alg. forward_render), n_contrib [1] uint32 (one past the position, in the
+ * pixel's tile list, of its last contributor). */
+typedef struct {
+    float *rgb, *depth, *kmap, *normal, *sem, *T_final;
+    uint32_t *n_contrib;
+} ugs_outputs;
+
+/* Upstream gradients dL/d(output), same layouts as ugs_outputs.  A NULL map
+ * means zero.  These are the loss gradients Alg. backward_render takes. */
+typedef struct {
+    const float *rgb, *depth, *kmap, *normal, *sem;
+} ugs_upstream;
+
+/* Options.  Zero-initialise and call ugs_default_options() to get the defaults. */
+typedef struct {
+    int tile_w, tile_h;  /* 16x16 (default), 8x8 or 32x8 */
+    int batch;           /* Gaussians staged per LDS batch (render kernels), 0 = auto */
+    int step1, step2;    /* finite-difference steps of Alg. normal_estimation (1, 2) */
+    float lambda;        /* fusion weight of the two normals (0.5) */
+    int orient_sign;     /* +1: flip normals to face the camera; -1: the literal
+                            Eq. direction_correction (keep if N . d_view <= 0) */
+    float prune_Tk;      /* > 0: skip Gaussians with |k - 1| > prune_Tk (section 3.3) */
+} ugs_options;
+
+typedef struct ugs_ctx ugs_ctx;
+
+/* Fills `opt` with the defaults listed above. */
+void ugs_default_options(ugs_options *opt);
+
+/* Creates a context holding host-side state only (options, last problem shape,
+ * captured graph, tuning).  One context per stream; not thread-safe. */
+int ugs_create(ugs_ctx **out, const ugs_options *opt);
+void ugs_destroy(ugs_ctx *ctx);
+/* Replaces the options (tile shape, batch, normal parameters); invalidates a
+ * captured step. */
+int ugs_set_options(ugs_ctx *ctx, const ugs_options *opt);
+
+/* Workspace bytes for N Gaussians, C_o channels, V views (cameras on the host)
+ * and room for pair_capacity (tile, Gaussian) pairs (< 2^31). */
+int ugs_workspace_size(const ugs_ctx *ctx, int64_t N, int C_o, int sh_deg, const ugs_camera *cams, int V,
+                       int64_t pair_capacity, size_t *bytes);
+
+/* Stage S1, projection (the 3DGS preprocessing the paper extends, section 3.4
+ * "Tile-based Forward Rasterization"): for every view and Gaussian, EWA footprint
+ * (conic, 2D mean), SH colour, opacity, gradient factor, the depth coefficients
+ * of the ray-ellipsoid midpoint (section 3.2), the sort depth and the tile
+ * rectangle of the alpha >= 1/255 region.  Parameters are read once for all V
+ * views.  Writes only into `ws`.  Also zeroes the per-view gradient records used
+ * by ugs_render_bwd. */
+int ugs_project(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, int V, void *ws, size_t ws_bytes,
+                void *stream);
+
+/* Stages S2-S4: pair emission (one pair per tile a Gaussian's rectangle covers,
+ * key = (global tile << 32) | float bits of the camera depth, value = Gaussian
+ * index), a stable radix sort so that each tile's list is ordered by (depth,
+ * index), and the per-tile [start, end) ranges.  When P_out is non-NULL the call
+ * synchronises the stream and stores the pair count P.  When P exceeds the
+ * capacity the sort is skipped, nothing is written out of bounds, the call
+ * returns UGS_ERR_CAPACITY (only detectable when P_out is non-NULL; otherwise a
+ * device flag makes the following render calls produce zero outputs and
+ * ugs_check_overflow reports it). */
+int ugs_bin_sort(ugs_ctx *ctx, void *ws, void *stream, int64_t *P_out);
+
+/* Synchronises `stream` and returns UGS_ERR_CAPACITY if the last bin_sort
+ * overflowed (and the required P in *P_required), UGS_OK otherwise. */
+int ugs_check_overflow(ugs_ctx *ctx, void *ws, void *stream, int64_t *P_required);
+
+/* Stages S5-S6: Alg. forward_render over every tile of every view (front-to-back
+ * compositing of RGB, depth, gradient factor and semantics, saving T_final and
+ * the last contributor) followed by Alg. normal_estimation on the depth. */
+int ugs_render_fwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs *out, void *stream);
+
+/* Stages S7-S9: Alg. normal_gradient (dL/dN -> dL/dD), Alg. backward_render
+ * (reverse traversal from T_final, gradients of colour, depth, gradient factor,
+ * semantics and alpha), and the chain into the parameters (supplementary S1.2
+ * for depth -> (mu, s, R), R -> q by the tangent projection, EWA and SH
+ * adjoints).  `out` must hold the outputs of the matching ugs_render_fwd.
+ * Gradients are summed over views and ADDED to `dg`. */
+int ugs_render_bwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs *out,
+                   const ugs_upstream *dout, const ugs_gaussian_grads *dg, void *stream);
+
+/* Batched training step: captures project -> bin_sort -> render_fwd ->
+ * render_bwd for all V views into one HIP graph (no host synchronisation inside;
+ * the pair count stays on the device and is bounded by the workspace capacity).
+ * ugs_step_replay launches it; a replay whose pair count overflowed returns
+ * UGS_ERR_CAPACITY at the NEXT replay (outputs of the overflowing replay are
+ * zero) and the step must be re-captured with a larger workspace.  The buffers
+ * passed at capture are the ones every replay reads and writes. */
+int ugs_step_capture(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, int V, void *ws,
+                     size_t ws_bytes, const ugs_outputs *out, const ugs_upstream *dout,
+                     const ugs_gaussian_grads *dg, void *stream);
+int ugs_step_replay(ugs_ctx *ctx, void *stream);
+
+/* Times the candidate (tile shape, batch) configurations on the given problem
+ * (one forward+backward each, after a warm-up), checks that every candidate's
+ * forward outputs are bit-identical to the first one's, keeps the fastest in the
+ * context options and returns it in *chosen (and its time in *ms if non-NULL).
+ * Synchronous.  Uses `out` and `dg` as scratch (dg is zeroed afterwards).
+ * Returns UGS_ERR_STATE if the candidates' outputs differ. */
+int ugs_autotune(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, int V, void *ws, size_t ws_bytes,
+                 const ugs_outputs *out, const ugs_upstream *dout, const ugs_gaussian_grads *dg, void *stream,
+                 ugs_options *chosen, float *ms);
+
+/* Total (tile, Gaussian) pairs of the last bin_sort (synchronises). */
+int ugs_pair_count(ugs_ctx *ctx, void *ws, void *stream, int64_t *P);
+
+/* Timing hook: when `stage` is non-zero, every later call records `ev_start`
+ * (a hipEvent_t) on the stream right before the kernels of that stage and
+ * `ev_stop` right after them, in eager calls and inside a captured step alike.
+ * Stages: 1 project, 2 bin+sort, 3 render_fwd compositing, 4 normal_fwd,
+ * 5 normal_bwd, 6 render_bwd compositing, 7 project_bwd.  stage = 0 disables. */
+int ugs_time_stage(ugs_ctx *ctx, int stage, void *ev_start, void *ev_stop);
+
+/* Introspection for stage-wise tests: device pointer (inside `ws`) and element
+ * count of an internal array after the stage that writes it has run.  `which`:
+ *   0 render records, float[V*N][16] (layout in the source), written by project;
+ *   1 tile rectangles, uint32[V*N][2] = (tx0 | ty0 << 16, tx1 | ty1 << 16),
+ *     half-open, project;
+ *   2 tiles touched, uint32[V*N], project;
+ *   3 sorted keys, uint64[P] = (global tile << 32) | depth bits, bin_sort;
+ *   4 sorted values (Gaussian index), uint32[P], bin_sort;
+ *   5 tile ranges, uint32[total tiles][2] = [start, end), bin_sort;
+ *   6 per-view gradient records, float[V*N][16], render_bwd;
+ *   7 depth gradient incl. the normal branch, float[total pixels], render_bwd.
+ * Counts 3 and 4 read the pair count back (synchronises `stream`). */
+int ugs_debug_buffer(ugs_ctx *ctx, void *ws, int which, void *stream, void **dev_ptr, int64_t *count);
+
+/* Human-readable status; last HIP error string of the context. */
+const char *ugs_status_string(int status);
+const char *ugs_last_hip_error(const ugs_ctx *ctx);
+
+/* Kernel-level counters for roofline accounting: after a render_fwd, the number
+ * of (pixel, list entry) evaluations and of contributing fragments over all
+ * views (synchronises; counting adds atomics, so it is off unless enabled). */
+int ugs_enable_counters(ugs_ctx *ctx, int on);
+int ugs_read_counters(ugs_ctx *ctx, void *ws, void *stream, int64_t *evaluated, int64_t *contributing);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UNIGS_H */

@@ -1,0 +1,515 @@
+// Stage S1 (projection) and stage S9 (its backward) for gfx950.
+//
+// One thread per Gaussian; the thread loops over all views so that the
+// parameters (up to ~750 B per Gaussian) are read from HBM once per step, not
+// once per view.  Parameters are structure-of-arrays, so every load is a fully
+// coalesced 4-byte-per-lane stream.
+#include "ugs_internal.h"
+
+namespace ugs {
+namespace {
+
+constexpr int kProjThreads = 256;
+
+// Real SH basis (degree <= 3, Condon-Shortley phase, the 3DGS ordering that
+// UniGS inherits for colour).  Values are the closed-form normalisations
+// sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) times the Legendre factors.
+struct SHK {
+    static constexpr float c0 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
+    static constexpr float c1 = 0.48860251190291992f;   // sqrt(3)/(2 sqrt(pi))
+    static constexpr float c2a = 1.0925484305920792f;   // sqrt(15)/(2 sqrt(pi))
+    static constexpr float c2b = 0.31539156525252005f;  // sqrt(5)/(4 sqrt(pi))
+    static constexpr float c2c = 0.54627421529603959f;  // sqrt(15)/(4 sqrt(pi))
+    static constexpr float c3a = 0.59004358992664352f;  // sqrt(35/(2 pi))/4
+    static constexpr float c3b = 2.8906114426405538f;   // sqrt(105/pi)/2
+    static constexpr float c3c = 0.45704579946446572f;  // sqrt(21/(2 pi))/4
+    static constexpr float c3d = 0.37317633259011546f;  // sqrt(7/pi)/4
+    static constexpr float c3e = 1.4453057213202769f;   // sqrt(105/pi)/4
+};
+
+template <int DEG>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y)
+{
+    Y[0] = SHK::c0;
+    if constexpr (DEG >= 1) {
+        Y[1] = -SHK::c1 * y;
+        Y[2] = SHK::c1 * z;
+        Y[3] = -SHK::c1 * x;
+    }
+    if constexpr (DEG >= 2) {
+        float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = SHK::c2a * x * y;
+        Y[5] = -SHK::c2a * y * z;
+        Y[6] = SHK::c2b * (2.f * zz - xx - yy);
+        Y[7] = -SHK::c2a * x * z;
+        Y[8] = SHK::c2c * (xx - yy);
+    }
+    if constexpr (DEG >= 3) {
+        float xx = x * x, yy = y * y, zz = z * z;
+        Y[9] = -SHK::c3a * y * (3.f * xx - yy);
+        Y[10] = SHK::c3b * x * y * z;
+        Y[11] = -SHK::c3c * y * (4.f * zz - xx - yy);
+        Y[12] = SHK::c3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+        Y[13] = -SHK::c3c * x * (4.f * zz - xx - yy);
+        Y[14] = SHK::c3e * z * (xx - yy);
+        Y[15] = -SHK::c3a * x * (xx - 3.f * yy);
+    }
+}
+
+// d/d(x,y,z) of sum_c Y_c(x,y,z) w_c for a weight vector w (one colour channel's
+// coefficients scaled by its upstream gradient).
+template <int DEG>
+__device__ __forceinline__ void sh_basis_vjp(float x, float y, float z, const float *w, float &gx, float &gy,
+                                             float &gz)
+{
+    gx = gy = gz = 0.f;
+    if constexpr (DEG >= 1) {
+        gy += -SHK::c1 * w[1];
+        gz += SHK::c1 * w[2];
+        gx += -SHK::c1 * w[3];
+    }
+    if constexpr (DEG >= 2) {
+        gx += SHK::c2a * y * w[4];
+        gy += SHK::c2a * x * w[4];
+        gy += -SHK::c2a * z * w[5];
+        gz += -SHK::c2a * y * w[5];
+        gx += -2.f * SHK::c2b * x * w[6];
+        gy += -2.f * SHK::c2b * y * w[6];
+        gz += 4.f * SHK::c2b * z * w[6];
+        gx += -SHK::c2a * z * w[7];
+        gz += -SHK::c2a * x * w[7];
+        gx += 2.f * SHK::c2c * x * w[8];
+        gy += -2.f * SHK::c2c * y * w[8];
+    }
+    if constexpr (DEG >= 3) {
+        float xx = x * x, yy = y * y, zz = z * z;
+        gx += -6.f * SHK::c3a * x * y * w[9];
+        gy += -3.f * SHK::c3a * (xx - yy) * w[9];
+        gx += SHK::c3b * y * z * w[10];
+        gy += SHK::c3b * x * z * w[10];
+        gz += SHK::c3b * x * y * w[10];
+        gx += 2.f * SHK::c3c * x * y * w[11];
+        gy += -SHK::c3c * (4.f * zz - xx - 3.f * yy) * w[11];
+        gz += -8.f * SHK::c3c * y * z * w[11];
+        gx += -6.f * SHK::c3d * x * z * w[12];
+        gy += -6.f * SHK::c3d * y * z * w[12];
+        gz += SHK::c3d * (6.f * zz - 3.f * xx - 3.f * yy) * w[12];
+        gx += -SHK::c3c * (4.f * zz - 3.f * xx - yy) * w[13];
+        gy += 2.f * SHK::c3c * x * y * w[13];
+        gz += -8.f * SHK::c3c * x * z * w[13];
+        gx += 2.f * SHK::c3e * x * z * w[14];
+        gy += -2.f * SHK::c3e * y * z * w[14];
+        gz += SHK::c3e * (xx - yy) * w[14];
+        gx += -3.f * SHK::c3a * (xx - yy) * w[15];
+        gy += 6.f * SHK::c3a * x * y * w[15];
+    }
+}
+
+// Rotation matrix (row-major) of the unit quaternion (w, x, y, z).
+__device__ __forceinline__ void rotmat(float w, float x, float y, float z, float *M)
+{
+    M[0] = 1.f - 2.f * (y * y + z * z);
+    M[1] = 2.f * (x * y - w * z);
+    M[2] = 2.f * (x * z + w * y);
+    M[3] = 2.f * (x * y + w * z);
+    M[4] = 1.f - 2.f * (x * x + z * z);
+    M[5] = 2.f * (y * z - w * x);
+    M[6] = 2.f * (x * z - w * y);
+    M[7] = 2.f * (y * z + w * x);
+    M[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+// Gaussian-level quantities shared by every view.
+struct GaussState {
+    float mu[3], s[3], is2[3], qn, qh[4], Rg[9], Sig[6];  // Sig: 00 01 02 11 12 22
+    float o, k;
+};
+
+__device__ __forceinline__ void load_gauss(const ugs_gaussians &g, int64_t i, GaussState &G)
+{
+    const int64_t N = g.N;
+    for (int a = 0; a < 3; ++a) {
+        G.mu[a] = g.mean[a * N + i];
+        G.s[a] = __expf(g.log_scale[a * N + i]);
+        G.is2[a] = 1.f / (G.s[a] * G.s[a]);
+    }
+    float q0 = g.quat[i], q1 = g.quat[N + i], q2 = g.quat[2 * N + i], q3 = g.quat[3 * N + i];
+    G.qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    float iq = 1.f / G.qn;
+    G.qh[0] = q0 * iq; G.qh[1] = q1 * iq; G.qh[2] = q2 * iq; G.qh[3] = q3 * iq;
+    rotmat(G.qh[0], G.qh[1], G.qh[2], G.qh[3], G.Rg);
+    float s2[3] = {G.s[0] * G.s[0], G.s[1] * G.s[1], G.s[2] * G.s[2]};
+    const float *M = G.Rg;
+    auto sig = [&](int a, int b) { return M[3 * a] * s2[0] * M[3 * b] + M[3 * a + 1] * s2[1] * M[3 * b + 1] + M[3 * a + 2] * s2[2] * M[3 * b + 2]; };
+    G.Sig[0] = sig(0, 0); G.Sig[1] = sig(0, 1); G.Sig[2] = sig(0, 2);
+    G.Sig[3] = sig(1, 1); G.Sig[4] = sig(1, 2); G.Sig[5] = sig(2, 2);
+    G.o = sigmoidf_(g.opacity_logit[i]);
+    G.k = sigmoidf_(g.mask_logit[i]);
+}
+
+// View-dependent projection state.
+struct ViewState {
+    float mc[3], z, tx, ty;
+    bool clx, cly;
+    float T0[3], T1[3];      // rows of J R
+    float cov00, cov01, cov11;
+    float ca, cb, cc;         // conic
+    float m2x, m2y;
+    float dir[3], dist;
+    float M[9];               // R Rg
+    float p0[3], wv[3], A, iA, Qp0x, Qp0y, Q00, Q01, Q11;
+};
+
+__device__ __forceinline__ void project_view(const GaussState &G, const DevCam &cam, ViewState &S)
+{
+    const float *R = cam.R;
+    for (int a = 0; a < 3; ++a) S.mc[a] = R[3 * a] * G.mu[0] + R[3 * a + 1] * G.mu[1] + R[3 * a + 2] * G.mu[2] + cam.t[a];
+    float z = S.mc[2];
+    S.z = z;
+    float iz = 1.f / z;
+    float rx = S.mc[0] * iz, ry = S.mc[1] * iz;
+    S.clx = rx < -cam.limx || rx > cam.limx;
+    S.cly = ry < -cam.limy || ry > cam.limy;
+    S.tx = fminf(cam.limx, fmaxf(-cam.limx, rx)) * z;
+    S.ty = fminf(cam.limy, fmaxf(-cam.limy, ry)) * z;
+    float J00 = cam.fx * iz, J02 = -cam.fx * S.tx * iz * iz;
+    float J11 = cam.fy * iz, J12 = -cam.fy * S.ty * iz * iz;
+    for (int b = 0; b < 3; ++b) {
+        S.T0[b] = J00 * R[b] + J02 * R[6 + b];
+        S.T1[b] = J11 * R[3 + b] + J12 * R[6 + b];
+    }
+    const float *Sg = G.Sig;
+    auto quad = [&](const float *u, const float *v) {
+        float su0 = Sg[0] * u[0] + Sg[1] * u[1] + Sg[2] * u[2];
+        float su1 = Sg[1] * u[0] + Sg[3] * u[1] + Sg[4] * u[2];
+        float su2 = Sg[2] * u[0] + Sg[4] * u[1] + Sg[5] * u[2];
+        return v[0] * su0 + v[1] * su1 + v[2] * su2;
+    };
+    S.cov00 = quad(S.T0, S.T0) + kLowPass;
+    S.cov01 = quad(S.T0, S.T1);
+    S.cov11 = quad(S.T1, S.T1) + kLowPass;
+    float idet = 1.f / (S.cov00 * S.cov11 - S.cov01 * S.cov01);
+    S.ca = S.cov11 * idet;
+    S.cb = -S.cov01 * idet;
+    S.cc = S.cov00 * idet;
+    S.m2x = cam.fx * S.mc[0] * iz + cam.cx;
+    S.m2y = cam.fy * S.mc[1] * iz + cam.cy;
+    float v0 = G.mu[0] - cam.C[0], v1 = G.mu[1] - cam.C[1], v2 = G.mu[2] - cam.C[2];
+    S.dist = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+    float id = 1.f / S.dist;
+    S.dir[0] = v0 * id; S.dir[1] = v1 * id; S.dir[2] = v2 * id;
+    // camera-frame axes of the ellipsoid and the depth quadric
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 3; ++k) S.M[3 * a + k] = R[3 * a] * G.Rg[k] + R[3 * a + 1] * G.Rg[3 + k] + R[3 * a + 2] * G.Rg[6 + k];
+    S.p0[0] = S.mc[0] * iz; S.p0[1] = S.mc[1] * iz; S.p0[2] = 1.f;
+    S.A = 0.f;
+    for (int k = 0; k < 3; ++k) {
+        S.wv[k] = S.M[k] * S.p0[0] + S.M[3 + k] * S.p0[1] + S.M[6 + k];
+        S.A += S.wv[k] * S.wv[k] * G.is2[k];
+    }
+    S.iA = 1.f / S.A;
+    S.Qp0x = S.Qp0y = S.Q00 = S.Q01 = S.Q11 = 0.f;
+    for (int k = 0; k < 3; ++k) {
+        float e = S.wv[k] * G.is2[k];
+        S.Qp0x += S.M[k] * e;
+        S.Qp0y += S.M[3 + k] * e;
+        S.Q00 += S.M[k] * S.M[k] * G.is2[k];
+        S.Q01 += S.M[k] * S.M[3 + k] * G.is2[k];
+        S.Q11 += S.M[3 + k] * S.M[3 + k] * G.is2[k];
+    }
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(kProjThreads) project_fwd_kernel(ugs_gaussians g, const DevCam *__restrict__ cams,
+                                                                   int V, int tile_w, int tile_h, float prune_Tk,
+                                                                   float4 *__restrict__ rec, uint2 *__restrict__ rect,
+                                                                   uint32_t *__restrict__ touched,
+                                                                   float4 *__restrict__ grec, int zero_grad)
+{
+    const int64_t N = g.N;
+    const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
+    if (i >= N) return;
+    constexpr int NC = (DEG + 1) * (DEG + 1);
+    GaussState G;
+    load_gauss(g, i, G);
+    bool alive = G.o >= kAlphaMin && !(prune_Tk > 0.f && fabsf(G.k - 1.f) > prune_Tk);
+    float sh[NC][3];
+    if (alive)
+        for (int c = 0; c < NC; ++c)
+            for (int ch = 0; ch < 3; ++ch) sh[c][ch] = g.sh[((int64_t)c * 3 + ch) * N + i];
+    const float r2 = alive ? 2.f * __logf(255.f * G.o) : 0.f;
+    for (int v = 0; v < V; ++v) {
+        const DevCam &cam = cams[v];
+        const int64_t idx = (int64_t)v * N + i;
+        uint32_t nt = 0;
+        uint2 rc = make_uint2(0, 0);
+        float zc = cam.R[6] * G.mu[0] + cam.R[7] * G.mu[1] + cam.R[8] * G.mu[2] + cam.t[2];
+        if (alive && zc > cam.z_near) {
+            ViewState S;
+            project_view(G, cam, S);
+            float rx = sqrtf(S.cov00 * r2) * (1.f + 1e-4f) + 1e-3f;
+            float ry = sqrtf(S.cov11 * r2) * (1.f + 1e-4f) + 1e-3f;
+            float u0 = fmaxf(ceilf(S.m2x - rx), 0.f), u1 = fminf(floorf(S.m2x + rx), (float)(cam.W - 1));
+            float v0 = fmaxf(ceilf(S.m2y - ry), 0.f), v1 = fminf(floorf(S.m2y + ry), (float)(cam.H - 1));
+            if (u0 <= u1 && v0 <= v1 && isfinite(S.m2x) && isfinite(S.m2y)) {
+                int tx0 = (int)u0 / tile_w, tx1 = (int)u1 / tile_w + 1;
+                int ty0 = (int)v0 / tile_h, ty1 = (int)v1 / tile_h + 1;
+                nt = (uint32_t)((tx1 - tx0) * (ty1 - ty0));
+                rc = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
+                float Y[NC];
+                sh_basis<DEG>(S.dir[0], S.dir[1], S.dir[2], Y);
+                float col[3];
+                for (int ch = 0; ch < 3; ++ch) {
+                    float acc = 0.5f;
+                    for (int c = 0; c < NC; ++c) acc += Y[c] * sh[c][ch];
+                    col[ch] = fmaxf(acc, 0.f);
+                }
+                float iA = S.iA;
+                float4 *r = rec + idx * 4;
+                r[0] = make_float4(S.m2x, S.m2y, S.ca, S.cb);
+                r[1] = make_float4(S.cc, G.o, G.k, S.z);
+                r[2] = make_float4(S.Qp0x * iA / cam.fx, S.Qp0y * iA / cam.fy, S.Q00 * iA / (cam.fx * cam.fx),
+                                   S.Q01 * iA / (cam.fx * cam.fy));
+                r[3] = make_float4(S.Q11 * iA / (cam.fy * cam.fy), col[0], col[1], col[2]);
+                if (zero_grad) {
+                    float4 zf = make_float4(0.f, 0.f, 0.f, 0.f);
+                    float4 *gr = grec + idx * 4;
+                    gr[0] = zf; gr[1] = zf; gr[2] = zf; gr[3] = zf;
+                }
+            }
+        }
+        touched[idx] = nt;
+        rect[idx] = rc;
+    }
+}
+
+// Backward of the per-view record into the Gaussian parameters, summed over views.
+template <int DEG>
+__global__ void __launch_bounds__(kProjThreads) project_bwd_kernel(ugs_gaussians g, const DevCam *__restrict__ cams,
+                                                                   int V, const uint32_t *__restrict__ touched,
+                                                                   const float4 *__restrict__ grec,
+                                                                   ugs_gaussian_grads dg)
+{
+    const int64_t N = g.N;
+    const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
+    if (i >= N) return;
+    constexpr int NC = (DEG + 1) * (DEG + 1);
+    GaussState G;
+    load_gauss(g, i, G);
+    float dmu[3] = {0.f, 0.f, 0.f}, dRg[9], ds[3] = {0.f, 0.f, 0.f}, dSig[6], dis2[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < 9; ++k) dRg[k] = 0.f;
+    for (int k = 0; k < 6; ++k) dSig[k] = 0.f;
+    float dop = 0.f;
+    float sh[NC][3], dsh[NC][3];
+    bool loaded = false;
+    for (int v = 0; v < V; ++v) {
+        const int64_t idx = (int64_t)v * N + i;
+        if (touched[idx] == 0) continue;
+        const DevCam &cam = cams[v];
+        if (!loaded) {
+            for (int c = 0; c < NC; ++c)
+                for (int ch = 0; ch < 3; ++ch) {
+                    sh[c][ch] = g.sh[((int64_t)c * 3 + ch) * N + i];
+                    dsh[c][ch] = 0.f;
+                }
+            loaded = true;
+        }
+        const float4 *gr = grec + idx * 4;
+        float4 g0 = gr[0], g1 = gr[1], g2 = gr[2], g3 = gr[3];
+        ViewState S;
+        project_view(G, cam, S);
+        const float *R = cam.R;
+        const float fx = cam.fx, fy = cam.fy, z = S.z, iz = 1.f / z;
+        dop += g1.y;
+        float dmc[3] = {0.f, 0.f, 0.f};
+
+        // colour (SH) and the view direction
+        {
+            float Y[NC];
+            sh_basis<DEG>(S.dir[0], S.dir[1], S.dir[2], Y);
+            float dcol[3] = {g3.y, g3.z, g3.w};
+            float ddx = 0.f, ddy = 0.f, ddz = 0.f;
+            for (int ch = 0; ch < 3; ++ch) {
+                float raw = 0.5f;
+                for (int c = 0; c < NC; ++c) raw += Y[c] * sh[c][ch];
+                float dc = raw > 0.f ? dcol[ch] : 0.f;
+                if (dc == 0.f) continue;
+                float w[NC];
+                for (int c = 0; c < NC; ++c) {
+                    dsh[c][ch] += dc * Y[c];
+                    w[c] = dc * sh[c][ch];
+                }
+                float gx, gy, gz;
+                sh_basis_vjp<DEG>(S.dir[0], S.dir[1], S.dir[2], w, gx, gy, gz);
+                ddx += gx; ddy += gy; ddz += gz;
+            }
+            float pr = S.dir[0] * ddx + S.dir[1] * ddy + S.dir[2] * ddz;
+            float id = 1.f / S.dist;
+            dmu[0] += (ddx - S.dir[0] * pr) * id;
+            dmu[1] += (ddy - S.dir[1] * pr) * id;
+            dmu[2] += (ddz - S.dir[2] * pr) * id;
+        }
+        // 2D mean
+        dmc[0] += g0.x * fx * iz;
+        dmc[1] += g0.y * fy * iz;
+        dmc[2] -= (g0.x * fx * S.mc[0] + g0.y * fy * S.mc[1]) * iz * iz;
+        // conic -> 2D covariance: dS = -C dC C with dC = [[da, db/2], [db/2, dc]]
+        {
+            float a = S.ca, b = S.cb, c = S.cc;
+            float da = g0.z, db = 0.5f * g0.w, dcn = g1.x;
+            float X00 = da * a + db * b, X01 = da * b + db * c, X10 = db * a + dcn * b, X11 = db * b + dcn * c;
+            float dS00 = -(a * X00 + b * X10), dS01 = -(a * X01 + b * X11), dS11 = -(b * X01 + c * X11);
+            // cov = T Sig T^T: dSig += T^T dS T, dT = 2 dS T Sig
+            const float *t0 = S.T0, *t1 = S.T1;
+            for (int p = 0, n = 0; p < 3; ++p)
+                for (int q = p; q < 3; ++q, ++n) {
+                    float val = t0[p] * dS00 * t0[q] + t0[p] * dS01 * t1[q] + t1[p] * dS01 * t0[q] + t1[p] * dS11 * t1[q];
+                    dSig[n] += val;
+                }
+            const float *Sg = G.Sig;
+            float TS0[3], TS1[3];
+            TS0[0] = t0[0] * Sg[0] + t0[1] * Sg[1] + t0[2] * Sg[2];
+            TS0[1] = t0[0] * Sg[1] + t0[1] * Sg[3] + t0[2] * Sg[4];
+            TS0[2] = t0[0] * Sg[2] + t0[1] * Sg[4] + t0[2] * Sg[5];
+            TS1[0] = t1[0] * Sg[0] + t1[1] * Sg[1] + t1[2] * Sg[2];
+            TS1[1] = t1[0] * Sg[1] + t1[1] * Sg[3] + t1[2] * Sg[4];
+            TS1[2] = t1[0] * Sg[2] + t1[1] * Sg[4] + t1[2] * Sg[5];
+            float dT0[3], dT1[3];
+            for (int q = 0; q < 3; ++q) {
+                dT0[q] = 2.f * (dS00 * TS0[q] + dS01 * TS1[q]);
+                dT1[q] = 2.f * (dS01 * TS0[q] + dS11 * TS1[q]);
+            }
+            // T0 = J00 R0 + J02 R2, T1 = J11 R1 + J12 R2
+            float dJ00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
+            float dJ02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
+            float dJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
+            float dJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
+            float iz2 = iz * iz, iz3 = iz2 * iz;
+            dmc[2] += -dJ00 * fx * iz2 - dJ11 * fy * iz2 + 2.f * dJ02 * fx * S.tx * iz3 + 2.f * dJ12 * fy * S.ty * iz3;
+            float dtx = -dJ02 * fx * iz2, dty = -dJ12 * fy * iz2;
+            if (!S.clx) dmc[0] += dtx; else dmc[2] += dtx * S.tx * iz;
+            if (!S.cly) dmc[1] += dty; else dmc[2] += dty * S.ty * iz;
+        }
+        // depth coefficients: beta = (Qp0)_xy / (A f), gam = Q_xy / (A f f), z0 = mc.z
+        {
+            float iA = S.iA;
+            float bx = S.Qp0x * iA / fx, by = S.Qp0y * iA / fy;
+            float gA = S.Q00 * iA / (fx * fx), gB = S.Q01 * iA / (fx * fy), gC = S.Q11 * iA / (fy * fy);
+            float dbx = g2.x, dby = g2.y, dgA = g2.z, dgB = g2.w, dgC = g3.x;
+            float dA = -iA * (dbx * bx + dby * by + dgA * gA + dgB * gB + dgC * gC);
+            float dQpx = dbx * iA / fx, dQpy = dby * iA / fy;
+            float dQ00 = dgA * iA / (fx * fx), dQ01 = dgB * iA / (fx * fy), dQ11 = dgC * iA / (fy * fy);
+            float dM[9];
+            for (int k = 0; k < 9; ++k) dM[k] = 0.f;
+            float dwv[3];
+            const float *M = S.M;
+            for (int k = 0; k < 3; ++k) {
+                float e = G.is2[k], w = S.wv[k];
+                // A = sum_k wv_k^2 is2_k
+                dwv[k] = 2.f * dA * w * e;
+                dis2[k] += dA * w * w;
+                // Qp0_a = sum_k M_ak wv_k is2_k  (a = 0, 1)
+                float t = dQpx * M[k] + dQpy * M[3 + k];
+                dM[k] += dQpx * w * e;
+                dM[3 + k] += dQpy * w * e;
+                dwv[k] += t * e;
+                dis2[k] += t * w;
+                // Q00, Q01, Q11
+                dM[k] += 2.f * dQ00 * M[k] * e + dQ01 * M[3 + k] * e;
+                dM[3 + k] += 2.f * dQ11 * M[3 + k] * e + dQ01 * M[k] * e;
+                dis2[k] += dQ00 * M[k] * M[k] + dQ01 * M[k] * M[3 + k] + dQ11 * M[3 + k] * M[3 + k];
+            }
+            // wv_k = sum_a M_ak p0_a
+            float dp0[2] = {0.f, 0.f};
+            for (int k = 0; k < 3; ++k) {
+                dM[k] += dwv[k] * S.p0[0];
+                dM[3 + k] += dwv[k] * S.p0[1];
+                dM[6 + k] += dwv[k];
+                dp0[0] += dwv[k] * M[k];
+                dp0[1] += dwv[k] * M[3 + k];
+            }
+            dmc[0] += dp0[0] * iz;
+            dmc[1] += dp0[1] * iz;
+            dmc[2] += g1.w - (dp0[0] * S.mc[0] + dp0[1] * S.mc[1]) * iz * iz;
+            // M = R Rg  ->  dRg = R^T dM
+            for (int b = 0; b < 3; ++b)
+                for (int k = 0; k < 3; ++k) dRg[3 * b + k] += R[b] * dM[k] + R[3 + b] * dM[3 + k] + R[6 + b] * dM[6 + k];
+        }
+        // mc = R mu + t
+        for (int e = 0; e < 3; ++e) dmu[e] += R[e] * dmc[0] + R[3 + e] * dmc[1] + R[6 + e] * dmc[2];
+    }
+    if (!loaded) return;
+    // Sig = Rg S^2 Rg^T: with Mg = Rg S, dMg = 2 dSig Mg (full symmetric dSig)
+    {
+        float D[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
+        for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q) {
+                float acc = 0.f;
+                for (int k = 0; k < 3; ++k) acc += D[3 * r + k] * G.Rg[3 * k + q];
+                float dMg = 2.f * acc * G.s[q];
+                dRg[3 * r + q] += dMg * G.s[q];
+                ds[q] += G.Rg[3 * r + q] * dMg;
+            }
+    }
+    for (int k = 0; k < 3; ++k) ds[k] += dis2[k] * (-2.f) * G.is2[k] / G.s[k];
+    // rotation matrix -> unit quaternion -> quaternion
+    float w = G.qh[0], x = G.qh[1], y = G.qh[2], z = G.qh[3];
+    const float *d = dRg;
+    float gw = 2.f * (-z * d[1] + y * d[2] + z * d[3] - x * d[5] - y * d[6] + x * d[7]);
+    float gx = 2.f * (y * d[1] + z * d[2] + y * d[3] - 2.f * x * d[4] - w * d[5] + z * d[6] + w * d[7] - 2.f * x * d[8]);
+    float gy = 2.f * (-2.f * y * d[0] + x * d[1] + w * d[2] + x * d[3] + z * d[5] - w * d[6] + z * d[7] - 2.f * y * d[8]);
+    float gz = 2.f * (-2.f * z * d[0] - w * d[1] + x * d[2] + w * d[3] - 2.f * z * d[4] + y * d[5] + x * d[6] + y * d[7]);
+    float pq = gw * w + gx * x + gy * y + gz * z;
+    float iq = 1.f / G.qn;
+    dg.quat[i] += (gw - w * pq) * iq;
+    dg.quat[N + i] += (gx - x * pq) * iq;
+    dg.quat[2 * N + i] += (gy - y * pq) * iq;
+    dg.quat[3 * N + i] += (gz - z * pq) * iq;
+    for (int e = 0; e < 3; ++e) {
+        dg.mean[e * N + i] += dmu[e];
+        dg.log_scale[e * N + i] += ds[e] * G.s[e];
+    }
+    dg.opacity_logit[i] += dop * G.o * (1.f - G.o);
+    for (int c = 0; c < NC; ++c)
+        for (int ch = 0; ch < 3; ++ch) dg.sh[((int64_t)c * 3 + ch) * N + i] += dsh[c][ch];
+}
+
+}  // namespace
+
+hipError_t launch_project_fwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws, bool zero_grad,
+                              hipStream_t s)
+{
+    if (g.N == 0) return hipSuccess;
+    dim3 grid((unsigned)((g.N + kProjThreads - 1) / kProjThreads));
+    auto cams = (const DevCam *)(ws + L.cams);
+    auto rec = (float4 *)(ws + L.rec);
+    auto rect = (uint2 *)(ws + L.rect);
+    auto touched = (uint32_t *)(ws + L.touched);
+    auto grec = (float4 *)(ws + L.grec);
+    switch (g.sh_deg) {
+    case 0: hipLaunchKernelGGL(project_fwd_kernel<0>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad); break;
+    case 1: hipLaunchKernelGGL(project_fwd_kernel<1>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad); break;
+    case 2: hipLaunchKernelGGL(project_fwd_kernel<2>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad); break;
+    default: hipLaunchKernelGGL(project_fwd_kernel<3>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                              const ugs_gaussian_grads &dg, hipStream_t s)
+{
+    if (g.N == 0) return hipSuccess;
+    dim3 grid((unsigned)((g.N + kProjThreads - 1) / kProjThreads));
+    auto cams = (const DevCam *)(ws + L.cams);
+    auto touched = (const uint32_t *)(ws + L.touched);
+    auto grec = (const float4 *)(ws + L.grec);
+    switch (g.sh_deg) {
+    case 0: hipLaunchKernelGGL(project_bwd_kernel<0>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, touched, grec, dg); break;
+    case 1: hipLaunchKernelGGL(project_bwd_kernel<1>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, touched, grec, dg); break;
+    case 2: hipLaunchKernelGGL(project_bwd_kernel<2>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, touched, grec, dg); break;
+    default: hipLaunchKernelGGL(project_bwd_kernel<3>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, touched, grec, dg); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ugs

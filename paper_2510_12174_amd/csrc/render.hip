@@ -1,0 +1,435 @@
+// Stages S5 and S8: the per-pixel compositing loop of Alg. forward_render and
+// its reverse of Alg. backward_render, for gfx950.
+//
+// One workgroup per (view, tile), one lane per pixel.  The tile's sorted list is
+// walked in batches that the workgroup stages in LDS (64 B record + the C_o
+// semantic logits per Gaussian); every lane then reads the batch with broadcast
+// LDS loads.  The forward keeps transmittance and depth in FP64 (the depth
+// feeds a finite-difference normal, which amplifies its error), everything else
+// in FP32.  The backward recovers T from T_final by division, keeps the pixel's
+// adjoint state O(1) (a running sum A of w_j s_j over later fragments, with s_j
+// the dot product of the upstream gradients with fragment j's values), reduces
+// each fragment's gradient over the 64 lanes of a wavefront with DPP, and
+// issues one coalesced atomic per wavefront and fragment.
+#include "ugs_internal.h"
+
+namespace ugs {
+namespace {
+
+// ---------------------------------------------------------------- wave64 sum
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_step(float x)
+{
+    int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWMASK, 0xf, false);
+    return x + __int_as_float(y);
+}
+
+// Sum over the 64 lanes; the result is returned (uniform) in every lane.
+// All 64 lanes must be active.
+__device__ __forceinline__ float wave_sum(float x)
+{
+    x = dpp_step<0xB1, 0xf>(x);   // quad_perm [1,0,3,2]
+    x = dpp_step<0x4E, 0xf>(x);   // quad_perm [2,3,0,1]
+    x = dpp_step<0x124, 0xf>(x);  // row_ror:4
+    x = dpp_step<0x128, 0xf>(x);  // row_ror:8
+    x = dpp_step<0x142, 0xa>(x);  // row_bcast:15
+    x = dpp_step<0x143, 0xc>(x);  // row_bcast:31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+// Returns `s` in lane `lane` and `v` elsewhere.
+__device__ __forceinline__ float put_lane(float v, float s, int lane) { return __lane_id() == lane ? s : v; }
+
+struct TileInfo {
+    int v, px, py;
+    bool inside;
+    int64_t pix;  // pixel index within the view
+    int64_t HW, off;
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ TileInfo tile_info(const DevCam *cams, int V, uint32_t tile)
+{
+    TileInfo ti;
+    ti.v = view_of_tile(cams, V, tile);
+    const DevCam &cam = cams[ti.v];
+    uint32_t lt = tile - cam.tile_base;
+    int tx = (int)(lt % (uint32_t)cam.tiles_x), ty = (int)(lt / (uint32_t)cam.tiles_x);
+    ti.px = tx * TW + (int)(threadIdx.x % TW);
+    ti.py = ty * TH + (int)(threadIdx.x / TW);
+    ti.inside = ti.px < cam.W && ti.py < cam.H;
+    ti.HW = (int64_t)cam.W * cam.H;
+    ti.pix = (int64_t)ti.py * cam.W + ti.px;
+    ti.off = cam.pix_off;
+    return ti;
+}
+
+// Stage `n` list entries [start, start+n) into LDS: 4 float4 of record and CO
+// semantic floats (zero beyond C_o) each.
+template <int NT, int CO>
+__device__ __forceinline__ void stage_batch(float4 *srec, float *ssem, const uint32_t *vals, uint32_t start, int n,
+                                            const float4 *rec, int64_t recbase, const float *sem, int C_o)
+{
+    for (int q = threadIdx.x; q < n * 4; q += NT) {
+        uint32_t id = vals[start + (q >> 2)];
+        srec[q] = rec[(recbase + id) * 4 + (q & 3)];
+    }
+    if constexpr (CO > 0) {
+        for (int q = threadIdx.x; q < n * CO; q += NT) {
+            int e = q / CO, c = q - e * CO;
+            uint32_t id = vals[start + e];
+            ssem[q] = c < C_o ? sem[(int64_t)id * C_o + c] : 0.f;
+        }
+    }
+}
+
+template <int TW, int TH, int CO>
+__global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
+    const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
+    const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
+    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count)
+{
+    constexpr int NT = TW * TH;
+    extern __shared__ float4 smem[];
+    float4 *srec = smem;
+    float *ssem = (float *)(smem + 4 * batch);
+    const uint32_t tile = blockIdx.x;
+    const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    const uint2 range = ranges[tile];
+    const float fx = (float)ti.px, fy = (float)ti.py;
+    const int64_t recbase = (int64_t)ti.v * N;
+
+    double T = 1.0, D = 0.0;
+    float cr = 0.f, cg = 0.f, cb = 0.f, K = 0.f;
+    float acc[CO > 0 ? CO : 1];
+#pragma unroll
+    for (int c = 0; c < (CO > 0 ? CO : 1); ++c) acc[c] = 0.f;
+    uint32_t last = 0, n_eval = 0, n_con = 0;
+    bool done = !ti.inside;
+
+    for (uint32_t start = range.x; start < range.y; start += (uint32_t)batch) {
+        if (__syncthreads_count(done) == NT) break;
+        const int n = (int)min((uint32_t)batch, range.y - start);
+        stage_batch<NT, CO>(srec, ssem, vals, start, n, rec, recbase, sem, C_o);
+        __syncthreads();
+        if (!done) {
+            for (int j = 0; j < n; ++j) {
+                const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
+                const float dx = fx - r0.x, dy = fy - r0.y;
+                const float power = -0.5f * (r0.z * dx * dx + r1.x * dy * dy) - r0.w * dx * dy;
+                const float alpha = fminf(kAlphaMax, r1.y * __expf(power));
+                ++n_eval;
+                if (alpha < kAlphaMin) continue;
+                const double tT = T * (1.0 - (double)alpha);
+                if (tT < kTStop) {
+                    done = true;
+                    break;
+                }
+                const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
+                const float B = r2.x * dx + r2.y * dy;
+                const float Cq = r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy;
+                const float d = r1.w * (1.f + B) / (1.f + 2.f * B + Cq);
+                const double w = (double)alpha * T;
+                const float wf = (float)w;
+                cr += wf * r3.y;
+                cg += wf * r3.z;
+                cb += wf * r3.w;
+                K += wf * r1.z;
+                D += w * (double)d;
+                if constexpr (CO > 0) {
+                    const float4 *s4 = (const float4 *)(ssem + j * CO);
+#pragma unroll
+                    for (int c = 0; c < CO / 4; ++c) {
+                        float4 o = s4[c];
+                        acc[4 * c] += wf * o.x;
+                        acc[4 * c + 1] += wf * o.y;
+                        acc[4 * c + 2] += wf * o.z;
+                        acc[4 * c + 3] += wf * o.w;
+                    }
+                }
+                T = tT;
+                last = start + (uint32_t)j + 1;
+                ++n_con;
+            }
+        }
+    }
+    if (ti.inside) {
+        const int64_t p = ti.pix, HW = ti.HW, off = ti.off;
+        out.rgb[3 * off + p] = cr;
+        out.rgb[3 * off + HW + p] = cg;
+        out.rgb[3 * off + 2 * HW + p] = cb;
+        out.depth[off + p] = (float)D;
+        out.kmap[off + p] = K;
+        out.T_final[off + p] = (float)T;
+        out.n_contrib[off + p] = last;
+        if constexpr (CO > 0) {
+#pragma unroll
+            for (int c = 0; c < CO; ++c)
+                if (c < C_o) out.sem[(int64_t)C_o * off + c * HW + p] = acc[c];
+        }
+    }
+    if (count) {
+        unsigned long long e = n_eval, c = n_con;
+        for (int o = 32; o > 0; o >>= 1) {
+            e += __shfl_xor(e, o, 64);
+            c += __shfl_xor(c, o, 64);
+        }
+        if (__lane_id() == 0) {
+            atomicAdd(&cnt->n_eval, e);
+            atomicAdd(&cnt->n_contrib, c);
+        }
+    }
+}
+
+template <int TW, int TH, int CO>
+__global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
+    const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
+    const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
+    const float *__restrict__ T_final, const uint32_t *__restrict__ n_contrib, const float *__restrict__ up_rgb,
+    const float *__restrict__ gD_img, const float *__restrict__ up_kmap, const float *__restrict__ up_sem,
+    float *__restrict__ grec, float *__restrict__ dsem, float *__restrict__ dmask, int batch)
+{
+    constexpr int NT = TW * TH;
+    constexpr int CA = CO > 0 ? CO : 1;
+    extern __shared__ float4 smem[];
+    __shared__ uint32_t s_max;
+    float4 *srec = smem;
+    float *ssem = (float *)(smem + 4 * batch);
+    const uint32_t tile = blockIdx.x;
+    const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    const uint2 range = ranges[tile];
+    const float fx = (float)ti.px, fy = (float)ti.py;
+    const int64_t recbase = (int64_t)ti.v * N;
+    const int lane = __lane_id();
+
+    float T = 1.f, gR = 0.f, gG = 0.f, gB = 0.f, gDp = 0.f, gK = 0.f;
+    uint32_t last = 0;
+    float gO[CA];
+#pragma unroll
+    for (int c = 0; c < CA; ++c) gO[c] = 0.f;
+    if (ti.inside) {
+        const int64_t p = ti.pix, HW = ti.HW, off = ti.off;
+        T = T_final[off + p];
+        last = n_contrib[off + p];
+        if (up_rgb) {
+            gR = up_rgb[3 * off + p];
+            gG = up_rgb[3 * off + HW + p];
+            gB = up_rgb[3 * off + 2 * HW + p];
+        }
+        gDp = gD_img[off + p];
+        if (up_kmap) gK = up_kmap[off + p];
+        if constexpr (CO > 0) {
+            if (up_sem) {
+#pragma unroll
+                for (int c = 0; c < CO; ++c)
+                    if (c < C_o) gO[c] = up_sem[(int64_t)C_o * off + c * HW + p];
+            }
+        }
+    }
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    if (last) atomicMax(&s_max, last);
+    __syncthreads();
+    const uint32_t end_all = s_max;
+    float A = 0.f;
+
+    for (uint32_t end = end_all; end > range.x;) {
+        const uint32_t start = end - range.x > (uint32_t)batch ? end - (uint32_t)batch : range.x;
+        const int n = (int)(end - start);
+        __syncthreads();
+        stage_batch<NT, CO>(srec, ssem, vals, start, n, rec, recbase, sem, C_o);
+        __syncthreads();
+        for (int j = n - 1; j >= 0; --j) {
+            const uint32_t entry = start + (uint32_t)j;
+            const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
+            const float dx = fx - r0.x, dy = fy - r0.y;
+            const float power = -0.5f * (r0.z * dx * dx + r1.x * dy * dy) - r0.w * dx * dy;
+            const float G = __expf(power);
+            const float oG = r1.y * G;
+            const float alpha = fminf(kAlphaMax, oG);
+            const bool contrib = entry < last && alpha >= kAlphaMin;
+            if (!__any(contrib)) continue;
+            float v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = 0.f;
+            float w = 0.f;
+            if (contrib) {
+                const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
+                const float om = 1.f - alpha;
+                T = T / om;
+                w = alpha * T;
+                const float B = r2.x * dx + r2.y * dy;
+                const float Cq = r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy;
+                const float iden = 1.f / (1.f + 2.f * B + Cq);
+                const float d = r1.w * (1.f + B) * iden;
+                float s = gR * r3.y + gG * r3.z + gB * r3.w + gDp * d + gK * r1.z;
+                if constexpr (CO > 0) {
+                    const float4 *s4 = (const float4 *)(ssem + j * CO);
+#pragma unroll
+                    for (int c = 0; c < CO / 4; ++c) {
+                        float4 o = s4[c];
+                        s += gO[4 * c] * o.x + gO[4 * c + 1] * o.y + gO[4 * c + 2] * o.z + gO[4 * c + 3] * o.w;
+                    }
+                }
+                const float dalpha = T * s - A / om;
+                A += w * s;
+                // colour
+                v[13] = w * gR;
+                v[14] = w * gG;
+                v[15] = w * gB;
+                // depth: d = z0 (1 + B) / (1 + 2B + Cq)
+                const float dd = w * gDp;
+                const float z0 = r1.w;
+                const float dB = dd * z0 * (Cq - 1.f) * iden * iden;
+                const float dC = -dd * z0 * (1.f + B) * iden * iden;
+                v[7] = dd * (1.f + B) * iden;     // z0
+                v[8] = dB * dx;                    // beta.x
+                v[9] = dB * dy;                    // beta.y
+                v[10] = dC * dx * dx;              // gam.a
+                v[11] = 2.f * dC * dx * dy;        // gam.b
+                v[12] = dC * dy * dy;              // gam.c
+                // d depth / d(dx, dy); the pixel offset is (pixel - mean2d)
+                float ddx = dB * r2.x + dC * 2.f * (r2.z * dx + r2.w * dy);
+                float ddy = dB * r2.y + dC * 2.f * (r2.w * dx + r3.x * dy);
+                float dm0 = -ddx, dm1 = -ddy;
+                if (oG < kAlphaMax) {
+                    const float dpow = dalpha * oG;
+                    v[5] = dalpha * G;                 // opacity
+                    v[2] = -0.5f * dx * dx * dpow;     // conic.a
+                    v[3] = -dx * dy * dpow;            // conic.b
+                    v[4] = -0.5f * dy * dy * dpow;     // conic.c
+                    dm0 += (r0.z * dx + r0.w * dy) * dpow;
+                    dm1 += (r0.w * dx + r1.x * dy) * dpow;
+                }
+                v[0] = dm0;
+                v[1] = dm1;
+            }
+            // reduce over the wavefront and scatter: lanes 0..15 own the record slots
+            float slot = 0.f;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k == 6) continue;
+                slot = put_lane(slot, wave_sum(v[k]), k);
+            }
+            const uint32_t id = vals[entry];
+            const int64_t ridx = recbase + id;
+            if (lane < 16 && lane != 6) unsafeAtomicAdd(&grec[ridx * kRecFloats + lane], slot);
+            const float sk = wave_sum(w * gK);
+            if (lane == 0) {
+                const float k = r1.z;
+                unsafeAtomicAdd(&dmask[id], sk * k * (1.f - k));
+            }
+            if constexpr (CO > 0) {
+                float o0 = 0.f, o1 = 0.f;
+#pragma unroll
+                for (int c = 0; c < CO; ++c) {
+                    float sc = wave_sum(w * gO[c]);
+                    if (c < 64) o0 = put_lane(o0, sc, c);
+                    else o1 = put_lane(o1, sc, c - 64);
+                }
+                if (lane < C_o) unsafeAtomicAdd(&dsem[(int64_t)id * C_o + lane], o0);
+                if constexpr (CO > 64) {
+                    if (lane + 64 < C_o) unsafeAtomicAdd(&dsem[(int64_t)id * C_o + 64 + lane], o1);
+                }
+            }
+        }
+        end = start;
+    }
+}
+
+template <int TW, int TH, int CO>
+hipError_t fwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                        const ugs_outputs &out, int batch, bool counters, int final_buf, hipStream_t s)
+{
+    size_t lds = (size_t)batch * (64 + 4 * CO);
+    auto cams = (const DevCam *)(ws + L.cams);
+    auto ranges = (const uint2 *)(ws + L.ranges);
+    auto vals = (const uint32_t *)(ws + (final_buf ? L.vals1 : L.vals0));
+    auto rec = (const float4 *)(ws + L.rec);
+    auto cnt = (DevCounters *)(ws + L.counters);
+    hipLaunchKernelGGL((render_fwd_kernel<TW, TH, CO>), dim3((unsigned)pb.total_tiles), dim3(TW * TH), lds, s, cams,
+                       pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out, batch, cnt, (int)counters);
+    return hipGetLastError();
+}
+
+template <int TW, int TH, int CO>
+hipError_t bwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                        const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg, int batch,
+                        int final_buf, hipStream_t s)
+{
+    size_t lds = (size_t)batch * (64 + 4 * CO);
+    auto cams = (const DevCam *)(ws + L.cams);
+    auto ranges = (const uint2 *)(ws + L.ranges);
+    auto vals = (const uint32_t *)(ws + (final_buf ? L.vals1 : L.vals0));
+    auto rec = (const float4 *)(ws + L.rec);
+    auto grec = (float *)(ws + L.grec);
+    auto gd = (const float *)(ws + L.gd);
+    hipLaunchKernelGGL((render_bwd_kernel<TW, TH, CO>), dim3((unsigned)pb.total_tiles), dim3(TW * TH), lds, s, cams,
+                       pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out.T_final, out.n_contrib, up.rgb, gd,
+                       up.kmap, up.sem, grec, dg.sem, dg.mask_logit, batch);
+    return hipGetLastError();
+}
+
+template <int TW, int TH>
+hipError_t fwd_co(int co_pad, const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                  const ugs_outputs &out, int batch, bool counters, int fb, hipStream_t s)
+{
+    switch (co_pad) {
+    case 0: return fwd_dispatch<TW, TH, 0>(g, pb, L, ws, out, batch, counters, fb, s);
+    case 8: return fwd_dispatch<TW, TH, 8>(g, pb, L, ws, out, batch, counters, fb, s);
+    case 16: return fwd_dispatch<TW, TH, 16>(g, pb, L, ws, out, batch, counters, fb, s);
+    case 32: return fwd_dispatch<TW, TH, 32>(g, pb, L, ws, out, batch, counters, fb, s);
+    case 64: return fwd_dispatch<TW, TH, 64>(g, pb, L, ws, out, batch, counters, fb, s);
+    default: return fwd_dispatch<TW, TH, 128>(g, pb, L, ws, out, batch, counters, fb, s);
+    }
+}
+
+template <int TW, int TH>
+hipError_t bwd_co(int co_pad, const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                  const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg, int batch, int fb,
+                  hipStream_t s)
+{
+    switch (co_pad) {
+    case 0: return bwd_dispatch<TW, TH, 0>(g, pb, L, ws, out, up, dg, batch, fb, s);
+    case 8: return bwd_dispatch<TW, TH, 8>(g, pb, L, ws, out, up, dg, batch, fb, s);
+    case 16: return bwd_dispatch<TW, TH, 16>(g, pb, L, ws, out, up, dg, batch, fb, s);
+    case 32: return bwd_dispatch<TW, TH, 32>(g, pb, L, ws, out, up, dg, batch, fb, s);
+    case 64: return bwd_dispatch<TW, TH, 64>(g, pb, L, ws, out, up, dg, batch, fb, s);
+    default: return bwd_dispatch<TW, TH, 128>(g, pb, L, ws, out, up, dg, batch, fb, s);
+    }
+}
+
+}  // namespace
+
+int channel_pad(int C_o)
+{
+    if (C_o <= 0) return 0;
+    if (C_o <= 8) return 8;
+    if (C_o <= 16) return 16;
+    if (C_o <= 32) return 32;
+    if (C_o <= 64) return 64;
+    return 128;
+}
+
+hipError_t launch_render_fwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                             const ugs_outputs &out, int batch, bool counters, int final_buf, hipStream_t s)
+{
+    if (pb.total_tiles == 0) return hipSuccess;
+    int cp = channel_pad(pb.C_o);
+    if (pb.tile_w == 8 && pb.tile_h == 8) return fwd_co<8, 8>(cp, g, pb, L, ws, out, batch, counters, final_buf, s);
+    if (pb.tile_w == 32 && pb.tile_h == 8) return fwd_co<32, 8>(cp, g, pb, L, ws, out, batch, counters, final_buf, s);
+    return fwd_co<16, 16>(cp, g, pb, L, ws, out, batch, counters, final_buf, s);
+}
+
+hipError_t launch_render_bwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                             const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg,
+                             int batch, int final_buf, hipStream_t s)
+{
+    if (pb.total_tiles == 0) return hipSuccess;
+    int cp = channel_pad(pb.C_o);
+    if (pb.tile_w == 8 && pb.tile_h == 8) return bwd_co<8, 8>(cp, g, pb, L, ws, out, up, dg, batch, final_buf, s);
+    if (pb.tile_w == 32 && pb.tile_h == 8) return bwd_co<32, 8>(cp, g, pb, L, ws, out, up, dg, batch, final_buf, s);
+    return bwd_co<16, 16>(cp, g, pb, L, ws, out, up, dg, batch, final_buf, s);
+}
+
+}  // namespace ugs

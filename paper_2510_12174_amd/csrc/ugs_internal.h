@@ -1,0 +1,103 @@
+// Internal definitions shared by the gfx950 kernels and the C-ABI host code.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "unigs.h"
+
+namespace ugs {
+
+// Splatting constants of the 3DGS pipeline UniGS extends (section 3.4): alpha
+// cut-off, alpha clamp, transmittance termination, EWA low-pass, FOV clamp.
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr double kTStop = 1e-4;
+constexpr float kLowPass = 0.3f;
+constexpr float kFovClamp = 1.3f;
+
+// Per-view constants on the device.
+struct DevCam {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    float C[3];         // camera centre -R^T t
+    float limx, limy;   // 1.3 * tan(half FOV)
+    float z_near;
+    int W, H;
+    int tiles_x, tiles_y;
+    uint32_t tile_base; // first global tile of this view
+    int64_t pix_off;    // first pixel of this view in the stacked image planes
+};
+
+// Per-(view, Gaussian) render record, 4 x float4 = 64 B:
+//   r0 = (mean2d.x, mean2d.y, conic.a, conic.b)
+//   r1 = (conic.c, opacity, k, z0)
+//   r2 = (beta.x, beta.y, gam.a, gam.b)
+//   r3 = (gam.c, rgb.r, rgb.g, rgb.b)
+// conic (a, b, c): power = -0.5 (a dx^2 + c dy^2) - b dx dy, with (dx, dy) the
+// pixel minus mean2d.  Depth of the ray-ellipsoid midpoint at that pixel:
+//   d = z0 (1 + B) / (1 + 2B + Cq),  B = beta . (dx, dy),
+//   Cq = gam.a dx^2 + 2 gam.b dx dy + gam.c dy^2.
+// The per-view gradient record has the same 16 slots:
+//   g0 = (d mean2d.x, d mean2d.y, d conic.a, d conic.b)
+//   g1 = (d conic.c, d opacity, -, d z0)
+//   g2 = (d beta.x, d beta.y, d gam.a, d gam.b)
+//   g3 = (d gam.c, d rgb.r, d rgb.g, d rgb.b)
+constexpr int kRecFloats = 16;
+
+struct DevCounters {
+    uint32_t P;          // pairs emitted (or required when overflowing)
+    uint32_t overflow;   // non-zero when P exceeded the capacity
+    uint32_t pad0, pad1;
+    unsigned long long n_eval, n_contrib;
+};
+
+struct WsLayout {
+    size_t cams, rec, rect, touched, offs, scan_part, keys0, keys1, vals0, vals1, hist, digit_tot, ranges, grec, gd,
+        nadj, counters, total;
+    int64_t N, VN, total_tiles, total_pix, pair_cap;
+    int V, nb_scan, nb_sort, sort_passes;
+};
+
+constexpr int kScanBlock = 1024;  // elements per scan block (256 threads x 4)
+constexpr int kSortBlocks = 1024; // fixed radix-sort grid
+constexpr int kSortThreads = 256;
+
+struct Problem {
+    int64_t N;
+    int sh_deg, C_o, V;
+    int tile_w, tile_h;
+    int64_t total_tiles, total_pix;
+    float prune_Tk;
+};
+
+// ---- launchers (each enqueues on `s`; return the launch error) ----
+hipError_t launch_project_fwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                              bool zero_grad, hipStream_t s);
+hipError_t launch_project_bwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                              const ugs_gaussian_grads &dg, hipStream_t s);
+hipError_t launch_binsort(const Problem &pb, const WsLayout &L, char *ws, hipStream_t s, int *final_buf);
+hipError_t launch_render_fwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                             const ugs_outputs &out, int batch, bool counters, int final_buf, hipStream_t s);
+hipError_t launch_render_bwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                             const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg,
+                             int batch, int final_buf, hipStream_t s);
+hipError_t launch_normal_fwd(const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out,
+                             const ugs_options &opt, hipStream_t s);
+hipError_t launch_normal_bwd(const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out,
+                             const ugs_upstream &up, const ugs_options &opt, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+int channel_pad(int C_o);
+
+// index of the view owning a global tile (V small: linear scan over tile_base)
+__device__ __forceinline__ int view_of_tile(const DevCam *cams, int V, uint32_t tile)
+{
+    int v = 0;
+    for (int k = 1; k < V; ++k)
+        if (tile >= cams[k].tile_base) v = k;
+    return v;
+}
+
+__device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+}  // namespace ugs

@@ -1,0 +1,443 @@
+"""Python binding of libunigs (the gfx950 multimodal Gaussian rasterizer).
+
+Argument marshalling only: every step of the rendering path runs in the HIP
+kernels behind the C ABI declared in include/unigs.h.  PyTorch provides device
+memory and the stream.  The functions ugs_* mirror the C entry points one to
+one; `Rasterizer` sequences them for the per-view and batched forms, and
+`RasterizeFunction` is the torch.autograd.Function around forward/backward.
+
+There is no fallback: if libunigs.so is missing or no GPU is present, loading
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(PKG, "libunigs.so")
+
+UGS_OK = 0
+UGS_ERR_INVALID_ARG = -1
+UGS_ERR_UNSUPPORTED = -2
+UGS_ERR_CAPACITY = -3
+UGS_ERR_HIP = -4
+UGS_ERR_NOT_CAPTURED = -5
+UGS_ERR_STATE = -6
+UGS_MAX_CHANNELS = 128
+UGS_MAX_VIEWS = 64
+
+EXPORTS = ["ugs_default_options", "ugs_create", "ugs_destroy", "ugs_set_options", "ugs_workspace_size",
+           "ugs_project", "ugs_bin_sort", "ugs_check_overflow", "ugs_render_fwd", "ugs_render_bwd",
+           "ugs_step_capture", "ugs_step_replay", "ugs_autotune", "ugs_pair_count", "ugs_status_string",
+           "ugs_last_hip_error", "ugs_enable_counters", "ugs_read_counters", "ugs_debug_buffer", "ugs_time_stage"]
+
+
+class UgsError(RuntimeError):
+    def __init__(self, code, what, detail=""):
+        self.code = code
+        super().__init__(f"{what} failed: {code} ({status_string(code)}) {detail}".strip())
+
+
+class ugs_camera(C.Structure):
+    _fields_ = [("W", C.c_int), ("H", C.c_int), ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float),
+                ("cy", C.c_float), ("R", C.c_float * 9), ("t", C.c_float * 3), ("z_near", C.c_float)]
+
+
+class ugs_gaussians(C.Structure):
+    _fields_ = [("N", C.c_int64), ("sh_deg", C.c_int), ("C_o", C.c_int)] + \
+               [(k, C.c_void_p) for k in ("mean", "quat", "log_scale", "opacity_logit", "mask_logit", "sh", "sem")]
+
+
+class ugs_gaussian_grads(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("mean", "quat", "log_scale", "opacity_logit", "mask_logit", "sh", "sem")]
+
+
+class ugs_outputs(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("rgb", "depth", "kmap", "normal", "sem", "T_final", "n_contrib")]
+
+
+class ugs_upstream(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("rgb", "depth", "kmap", "normal", "sem")]
+
+
+class ugs_options(C.Structure):
+    _fields_ = [("tile_w", C.c_int), ("tile_h", C.c_int), ("batch", C.c_int), ("step1", C.c_int),
+                ("step2", C.c_int), ("lambda_", C.c_float), ("orient_sign", C.c_int), ("prune_Tk", C.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libunigs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise ImportError(f"{LIB} not found: build it with paper_2510_12174_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = C.CDLL(LIB)
+        P = C.c_void_p
+        L.ugs_default_options.argtypes = [C.POINTER(ugs_options)]
+        L.ugs_default_options.restype = None
+        L.ugs_create.argtypes = [C.POINTER(P), C.POINTER(ugs_options)]
+        L.ugs_destroy.argtypes = [P]
+        L.ugs_destroy.restype = None
+        L.ugs_set_options.argtypes = [P, C.POINTER(ugs_options)]
+        L.ugs_workspace_size.argtypes = [P, C.c_int64, C.c_int, C.c_int, C.POINTER(ugs_camera), C.c_int,
+                                         C.c_int64, C.POINTER(C.c_size_t)]
+        L.ugs_project.argtypes = [P, C.POINTER(ugs_gaussians), C.POINTER(ugs_camera), C.c_int, P, C.c_size_t, P]
+        L.ugs_bin_sort.argtypes = [P, P, P, C.POINTER(C.c_int64)]
+        L.ugs_check_overflow.argtypes = [P, P, P, C.POINTER(C.c_int64)]
+        L.ugs_pair_count.argtypes = [P, P, P, C.POINTER(C.c_int64)]
+        L.ugs_render_fwd.argtypes = [P, C.POINTER(ugs_gaussians), P, C.POINTER(ugs_outputs), P]
+        L.ugs_render_bwd.argtypes = [P, C.POINTER(ugs_gaussians), P, C.POINTER(ugs_outputs),
+                                     C.POINTER(ugs_upstream), C.POINTER(ugs_gaussian_grads), P]
+        L.ugs_step_capture.argtypes = [P, C.POINTER(ugs_gaussians), C.POINTER(ugs_camera), C.c_int, P, C.c_size_t,
+                                       C.POINTER(ugs_outputs), C.POINTER(ugs_upstream),
+                                       C.POINTER(ugs_gaussian_grads), P]
+        L.ugs_step_replay.argtypes = [P, P]
+        L.ugs_autotune.argtypes = [P, C.POINTER(ugs_gaussians), C.POINTER(ugs_camera), C.c_int, P, C.c_size_t,
+                                   C.POINTER(ugs_outputs), C.POINTER(ugs_upstream), C.POINTER(ugs_gaussian_grads), P,
+                                   C.POINTER(ugs_options), C.POINTER(C.c_float)]
+        L.ugs_status_string.argtypes = [C.c_int]
+        L.ugs_status_string.restype = C.c_char_p
+        L.ugs_last_hip_error.argtypes = [P]
+        L.ugs_last_hip_error.restype = C.c_char_p
+        L.ugs_enable_counters.argtypes = [P, C.c_int]
+        L.ugs_read_counters.argtypes = [P, P, P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.ugs_debug_buffer.argtypes = [P, P, C.c_int, P, C.POINTER(C.c_void_p), C.POINTER(C.c_int64)]
+        L.ugs_time_stage.argtypes = [P, C.c_int, P, P]
+        _lib = L
+    return _lib
+
+
+def status_string(code):
+    try:
+        return lib().ugs_status_string(int(code)).decode()
+    except Exception:
+        return "?"
+
+
+# ---------------------------------------------------------------- marshalling
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def make_cameras(cams):
+    arr = (ugs_camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i].W, arr[i].H = int(c["W"]), int(c["H"])
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = (float(c[k]) for k in ("fx", "fy", "cx", "cy"))
+        R = np.asarray(c["R"], np.float32).reshape(9)
+        t = np.asarray(c["t"], np.float32).reshape(3)
+        for k in range(9):
+            arr[i].R[k] = float(R[k])
+        for k in range(3):
+            arr[i].t[k] = float(t[k])
+        arr[i].z_near = float(c.get("z_near", 0.2))
+    return arr
+
+
+PARAM_KEYS = ("mean", "quat", "log_scale", "opacity_logit", "mask_logit", "sh", "sem")
+
+
+def make_gaussians(g):
+    """g: dict with N, sh_deg, C_o and contiguous float32 device tensors."""
+    s = ugs_gaussians()
+    s.N, s.sh_deg, s.C_o = int(g["N"]), int(g["sh_deg"]), int(g["C_o"])
+    for k in PARAM_KEYS:
+        t = g[k]
+        _check_tensor(t, k)
+        setattr(s, k, t.data_ptr())
+    return s
+
+
+def make_grads(d):
+    s = ugs_gaussian_grads()
+    for k in PARAM_KEYS:
+        _check_tensor(d[k], "d" + k)
+        setattr(s, k, d[k].data_ptr())
+    return s
+
+
+def _check_tensor(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype not in (torch.float32, torch.int32) \
+            or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+
+
+def make_outputs(o):
+    s = ugs_outputs()
+    for k in ("rgb", "depth", "kmap", "normal", "sem", "T_final", "n_contrib"):
+        setattr(s, k, o[k].data_ptr() if o.get(k) is not None and o[k].numel() > 0 else None)
+    return s
+
+
+def make_upstream(u):
+    s = ugs_upstream()
+    for k in ("rgb", "depth", "kmap", "normal", "sem"):
+        t = u.get(k) if u else None
+        setattr(s, k, t.data_ptr() if t is not None and t.numel() > 0 else None)
+    return s
+
+
+def default_options(**kw):
+    o = ugs_options()
+    lib().ugs_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, "lambda_" if k == "lambda" else k, v)
+    return o
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _chk(rc, what, ctx=None):
+    if rc != UGS_OK:
+        detail = ""
+        if ctx is not None:
+            detail = lib().ugs_last_hip_error(ctx).decode()
+        raise UgsError(rc, what, detail)
+
+
+# ---------------------------------------------------------------- high level
+def to_device(g, device="cuda"):
+    """Seeded-scene dict (numpy) -> dict of contiguous float32 device tensors."""
+    import torch
+    out = dict(N=int(g["N"]), sh_deg=int(g["sh_deg"]), C_o=int(g["C_o"]))
+    for k in PARAM_KEYS:
+        a = np.asarray(g[k], np.float32)
+        if k == "sem" and a.size == 0:
+            a = np.zeros((int(g["N"]), 0), np.float32)
+        out[k] = torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    return out
+
+
+def zeros_like_params(g):
+    import torch
+    return {k: torch.zeros_like(g[k]) for k in PARAM_KEYS}
+
+
+def pixel_offsets(cams):
+    off = [0]
+    for c in cams:
+        off.append(off[-1] + int(c["W"]) * int(c["H"]))
+    return off
+
+
+def alloc_outputs(cams, C_o, device="cuda"):
+    import torch
+    P = pixel_offsets(cams)[-1]
+    f = lambda n: torch.empty(n, dtype=torch.float32, device=device)
+    return dict(rgb=f(3 * P), depth=f(P), kmap=f(P), normal=f(3 * P), sem=f(max(C_o, 0) * P), T_final=f(P),
+                n_contrib=torch.empty(P, dtype=torch.int32, device=device))
+
+
+def split_views(flat, cams, channels):
+    """Flat stacked planes -> list of [channels][H][W] views per camera."""
+    off = pixel_offsets(cams)
+    res = []
+    for v, c in enumerate(cams):
+        H, W = int(c["H"]), int(c["W"])
+        res.append(flat[channels * off[v]:channels * off[v + 1]].view(channels, H, W))
+    return res
+
+
+class Rasterizer:
+    """Owns a libunigs context, its workspace and the output buffers."""
+
+    def __init__(self, **options):
+        import torch
+        self.torch = torch
+        self.opts = default_options(**options)
+        ctx = C.c_void_p()
+        _chk(lib().ugs_create(C.byref(ctx), C.byref(self.opts)), "ugs_create")
+        self.ctx = ctx
+        self.ws = None
+        self.ws_bytes = 0
+        self.pair_cap = 0
+        self._keep = []
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                lib().ugs_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    def set_options(self, **options):
+        for k, v in options.items():
+            setattr(self.opts, "lambda_" if k == "lambda" else k, v)
+        _chk(lib().ugs_set_options(self.ctx, C.byref(self.opts)), "ugs_set_options", self.ctx)
+
+    def workspace_size(self, g, cams, pair_cap):
+        n = C.c_size_t()
+        cs = make_cameras(cams)
+        _chk(lib().ugs_workspace_size(self.ctx, int(g["N"]), int(g["C_o"]), int(g["sh_deg"]), cs, len(cams),
+                                      int(pair_cap), C.byref(n)), "ugs_workspace_size")
+        return n.value
+
+    def ensure_workspace(self, g, cams, pair_cap):
+        need = self.workspace_size(g, cams, pair_cap)
+        if self.ws is None or self.ws_bytes < need:
+            self.ws = None
+            self.ws = self.torch.empty(need + 256, dtype=self.torch.uint8, device="cuda")
+            self.ws_bytes = need
+        self.pair_cap = pair_cap
+        base = self.ws.data_ptr()
+        self.ws_ptr = C.c_void_p((base + 255) & ~255)
+
+    def project_and_sort(self, g, cams, pair_cap=None):
+        """S1-S4 with the pair-count read-back; grows the workspace and repeats on
+        overflow.  Returns the pair count P."""
+        cs = make_cameras(cams)
+        gs = make_gaussians(g)
+        cap = pair_cap or max(self.pair_cap, 1 << 16, 4 * int(g["N"]) * len(cams))
+        for _ in range(4):
+            self.ensure_workspace(g, cams, cap)
+            s = _stream()
+            _chk(lib().ugs_project(self.ctx, C.byref(gs), cs, len(cams), self.ws_ptr, self.ws_bytes, s),
+                 "ugs_project", self.ctx)
+            P = C.c_int64()
+            rc = lib().ugs_bin_sort(self.ctx, self.ws_ptr, s, C.byref(P))
+            if rc == UGS_ERR_CAPACITY:
+                cap = int(P.value * 1.25) + 1024
+                continue
+            _chk(rc, "ugs_bin_sort", self.ctx)
+            return int(P.value)
+        raise UgsError(UGS_ERR_CAPACITY, "project_and_sort")
+
+    def forward(self, g, cams, out=None):
+        self.project_and_sort(g, cams)
+        if out is None:
+            out = alloc_outputs(cams, int(g["C_o"]))
+        _chk(lib().ugs_render_fwd(self.ctx, C.byref(make_gaussians(g)), self.ws_ptr, C.byref(make_outputs(out)),
+                                  _stream()), "ugs_render_fwd", self.ctx)
+        return out
+
+    def backward(self, g, out, up, grads=None):
+        if grads is None:
+            grads = zeros_like_params(g)
+        _chk(lib().ugs_render_bwd(self.ctx, C.byref(make_gaussians(g)), self.ws_ptr, C.byref(make_outputs(out)),
+                                  C.byref(make_upstream(up)), C.byref(make_grads(grads)), _stream()),
+             "ugs_render_bwd", self.ctx)
+        return grads
+
+    def pair_count(self):
+        P = C.c_int64()
+        _chk(lib().ugs_pair_count(self.ctx, self.ws_ptr, _stream(), C.byref(P)), "ugs_pair_count", self.ctx)
+        return int(P.value)
+
+    def enable_counters(self, on=True):
+        _chk(lib().ugs_enable_counters(self.ctx, int(on)), "ugs_enable_counters")
+
+    def read_counters(self):
+        e, c = C.c_int64(), C.c_int64()
+        _chk(lib().ugs_read_counters(self.ctx, self.ws_ptr, _stream(), C.byref(e), C.byref(c)),
+             "ugs_read_counters", self.ctx)
+        return int(e.value), int(c.value)
+
+    STAGES = dict(project=1, bin_sort=2, render_fwd=3, normal_fwd=4, normal_bwd=5, render_bwd=6, project_bwd=7)
+
+    def time_stage(self, stage, ev_start=None, ev_stop=None):
+        """Records the hipEvent_t handles ev_start/ev_stop around one stage's
+        kernels in every later call (and in a step captured afterwards)."""
+        st = self.STAGES[stage] if isinstance(stage, str) else int(stage)
+        _chk(lib().ugs_time_stage(self.ctx, st, C.c_void_p(ev_start), C.c_void_p(ev_stop)), "ugs_time_stage")
+
+    DEBUG = {"records": (0, "float32", 16), "rects": (1, "int32", 2), "touched": (2, "int32", 1),
+             "keys": (3, "int64", 1), "vals": (4, "int32", 1), "ranges": (5, "int32", 2),
+             "grad_records": (6, "float32", 16), "depth_grad": (7, "float32", 1)}
+
+    def debug_buffer(self, name):
+        """Device tensor view of an internal workspace array (see ugs_debug_buffer)."""
+        which, dt, width = self.DEBUG[name]
+        ptr, cnt = C.c_void_p(), C.c_int64()
+        _chk(lib().ugs_debug_buffer(self.ctx, self.ws_ptr, which, _stream(), C.byref(ptr), C.byref(cnt)),
+             "ugs_debug_buffer", self.ctx)
+        dtype = getattr(self.torch, dt)
+        esize = self.torch.empty(0, dtype=dtype).element_size()
+        off = int(ptr.value or self.ws.data_ptr()) - self.ws.data_ptr()
+        n = int(cnt.value) * width
+        return self.ws[off:off + n * esize].view(dtype).view(-1, width) if width > 1 else \
+            self.ws[off:off + n * esize].view(dtype)
+
+    # batched step ------------------------------------------------------
+    def capture_step(self, g, cams, out, up, grads, margin=1.25):
+        """Sizes the workspace from an eager pass (pair count x margin) and
+        captures the whole fwd+bwd step for all views into one HIP graph."""
+        P = self.project_and_sort(g, cams)
+        self.ensure_workspace(g, cams, max(int(P * margin) + 4096, self.pair_cap))
+        self._keep = [make_gaussians(g), make_cameras(cams), make_outputs(out), make_upstream(up), make_grads(grads)]
+        gs, cs, os_, us, ds = self._keep
+        _chk(lib().ugs_step_capture(self.ctx, C.byref(gs), cs, len(cams), self.ws_ptr, self.ws_bytes, C.byref(os_),
+                                    C.byref(us), C.byref(ds), _stream()), "ugs_step_capture", self.ctx)
+
+    def replay(self):
+        _chk(lib().ugs_step_replay(self.ctx, _stream()), "ugs_step_replay", self.ctx)
+
+    def autotune(self, g, cams, out, up, grads):
+        P = self.project_and_sort(g, cams)
+        # the smallest tile needs the most pairs: leave room for it
+        self.ensure_workspace(g, cams, max(int(P * 3.0) + 4096, self.pair_cap))
+        chosen = ugs_options()
+        ms = C.c_float()
+        rc = lib().ugs_autotune(self.ctx, C.byref(make_gaussians(g)), make_cameras(cams), len(cams), self.ws_ptr,
+                                self.ws_bytes, C.byref(make_outputs(out)), C.byref(make_upstream(up)),
+                                C.byref(make_grads(grads)), _stream(), C.byref(chosen), C.byref(ms))
+        _chk(rc, "ugs_autotune", self.ctx)
+        self.opts = chosen
+        return dict(tile_w=chosen.tile_w, tile_h=chosen.tile_h, batch=chosen.batch, ms=float(ms.value))
+
+
+def _autograd_function():
+    import torch
+
+    class RasterizeFunction(torch.autograd.Function):
+        """Differentiable multimodal render of all views.  Inputs are the seven
+        parameter tensors; outputs are the stacked planes (rgb, depth, kmap,
+        normal, sem).  The backward recomputes transmittance from the saved
+        T_final (no per-fragment state is stored)."""
+
+        @staticmethod
+        def forward(ctx, rast, meta, cams, mean, quat, log_scale, opacity_logit, mask_logit, sh, sem):
+            g = dict(meta, mean=mean.contiguous(), quat=quat.contiguous(), log_scale=log_scale.contiguous(),
+                     opacity_logit=opacity_logit.contiguous(), mask_logit=mask_logit.contiguous(),
+                     sh=sh.contiguous(), sem=sem.contiguous())
+            out = rast.forward(g, cams)
+            ctx.rast, ctx.g, ctx.out = rast, g, out
+            ctx.mark_non_differentiable(out["T_final"], out["n_contrib"])
+            return out["rgb"], out["depth"], out["kmap"], out["normal"], out["sem"], out["T_final"], out["n_contrib"]
+
+        @staticmethod
+        def backward(ctx, d_rgb, d_depth, d_kmap, d_normal, d_sem, _dT, _dn):
+            up = {}
+            for k, t in (("rgb", d_rgb), ("depth", d_depth), ("kmap", d_kmap), ("normal", d_normal),
+                         ("sem", d_sem)):
+                up[k] = None if t is None else t.contiguous()
+            grads = ctx.rast.backward(ctx.g, ctx.out, up)
+            return (None, None, None, grads["mean"], grads["quat"], grads["log_scale"], grads["opacity_logit"],
+                    grads["mask_logit"], grads["sh"], grads["sem"])
+
+    return RasterizeFunction
+
+
+_RF = None
+
+
+def rasterize(rast, g, cams):
+    """Differentiable render: returns dict of stacked output planes."""
+    global _RF
+    if _RF is None:
+        _RF = _autograd_function()
+    meta = dict(N=int(g["N"]), sh_deg=int(g["sh_deg"]), C_o=int(g["C_o"]))
+    r = _RF.apply(rast, meta, cams, g["mean"], g["quat"], g["log_scale"], g["opacity_logit"], g["mask_logit"],
+                  g["sh"], g["sem"])
+    return dict(zip(("rgb", "depth", "kmap", "normal", "sem", "T_final", "n_contrib"), r))

@@ -1,0 +1,114 @@
+"""The C-ABI library loads, exports every symbol include/unigs.h declares, and
+rejects invalid arguments before touching the GPU.  CPU only."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def U():
+    from paper_2510_12174_amd import unigs
+    if not os.path.exists(unigs.LIB):
+        from paper_2510_12174_amd import build
+        build.build()
+    unigs.lib()
+    return unigs
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "unigs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ugs_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_match_header(U):
+    names = header_functions()
+    assert len(names) >= 18
+    L = U.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(U.EXPORTS) == names
+
+
+def test_symbols_are_exported_dynamically(U):
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", U.LIB], capture_output=True, text=True).stdout
+    for n in header_functions():
+        assert re.search(rf"\bT {n}\b", out), n
+
+
+def test_options_validation(U):
+    L = U.lib()
+    ctx = C.c_void_p()
+    o = U.default_options()
+    assert (o.tile_w, o.tile_h, o.step1, o.step2, o.orient_sign) == (16, 16, 1, 2, 1)
+    assert L.ugs_create(C.byref(ctx), C.byref(o)) == U.UGS_OK
+    bad = U.default_options(tile_w=12)
+    assert L.ugs_set_options(ctx, C.byref(bad)) == U.UGS_ERR_UNSUPPORTED
+    bad = U.default_options(orient_sign=0)
+    assert L.ugs_set_options(ctx, C.byref(bad)) == U.UGS_ERR_INVALID_ARG
+    bad = U.default_options(lambda_=1.5)
+    assert L.ugs_set_options(ctx, C.byref(bad)) == U.UGS_ERR_INVALID_ARG
+    for tw, th in ((8, 8), (32, 8), (16, 16)):
+        ok = U.default_options(tile_w=tw, tile_h=th)
+        assert L.ugs_set_options(ctx, C.byref(ok)) == U.UGS_OK
+    L.ugs_destroy(ctx)
+
+
+def _cams():
+    from paper_2510_12174_amd import scenes
+    return U_cams([scenes.camera(64, 48, 50, 50, 32, 24, np.eye(3), [0, 0, 3])])
+
+
+def U_cams(cams):
+    from paper_2510_12174_amd import unigs
+    return unigs.make_cameras(cams)
+
+
+def test_workspace_size_and_limits(U):
+    L = U.lib()
+    ctx = C.c_void_p()
+    assert L.ugs_create(C.byref(ctx), None) == U.UGS_OK
+    cams = _cams()
+    n = C.c_size_t()
+    assert L.ugs_workspace_size(ctx, 1000, 8, 3, cams, 1, 100000, C.byref(n)) == U.UGS_OK
+    small = n.value
+    assert L.ugs_workspace_size(ctx, 1000, 8, 3, cams, 1, 200000, C.byref(n)) == U.UGS_OK
+    assert abs((n.value - small) - 100000 * 24) <= 4 * 256  # 2 x 8 B keys + 2 x 4 B values per pair
+    assert L.ugs_workspace_size(ctx, 1000, 200, 3, cams, 1, 10, C.byref(n)) == U.UGS_ERR_UNSUPPORTED
+    assert L.ugs_workspace_size(ctx, 1000, 8, 4, cams, 1, 10, C.byref(n)) == U.UGS_ERR_UNSUPPORTED
+    assert L.ugs_workspace_size(ctx, -1, 8, 3, cams, 1, 10, C.byref(n)) == U.UGS_ERR_INVALID_ARG
+    assert L.ugs_workspace_size(ctx, 10, 8, 3, cams, 0, 10, C.byref(n)) == U.UGS_ERR_INVALID_ARG
+    assert L.ugs_workspace_size(ctx, 10, 8, 3, cams, 1, 1 << 40, C.byref(n)) == U.UGS_ERR_INVALID_ARG
+    badcam = _cams()
+    badcam[0].fx = 0.0
+    assert L.ugs_workspace_size(ctx, 10, 8, 3, badcam, 1, 10, C.byref(n)) == U.UGS_ERR_INVALID_ARG
+    L.ugs_destroy(ctx)
+
+
+def test_calls_rejected_before_launch(U):
+    """Null / inconsistent arguments and out-of-order calls return status codes
+    without any HIP call (this runs on a machine without a GPU)."""
+    L = U.lib()
+    ctx = C.c_void_p()
+    assert L.ugs_create(C.byref(ctx), None) == U.UGS_OK
+    cams = _cams()
+    g = U.ugs_gaussians()
+    g.N, g.sh_deg, g.C_o = 10, 0, 4  # null parameter pointers
+    assert L.ugs_project(ctx, C.byref(g), cams, 1, C.c_void_p(256), 1 << 20, None) == U.UGS_ERR_INVALID_ARG
+    g.sh_deg = 5
+    assert L.ugs_project(ctx, C.byref(g), cams, 1, C.c_void_p(256), 1 << 20, None) == U.UGS_ERR_UNSUPPORTED
+    assert L.ugs_bin_sort(ctx, C.c_void_p(256), None, None) == U.UGS_ERR_STATE
+    assert L.ugs_render_fwd(ctx, C.byref(g), C.c_void_p(256), None, None) == U.UGS_ERR_STATE
+    assert L.ugs_step_replay(ctx, None) == U.UGS_ERR_NOT_CAPTURED
+    assert L.ugs_bin_sort(None, None, None, None) == U.UGS_ERR_INVALID_ARG
+    assert L.ugs_time_stage(ctx, 9, None, None) == U.UGS_ERR_INVALID_ARG
+    assert L.ugs_time_stage(ctx, 0, None, None) == U.UGS_OK
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.ugs_status_string(code)
+    L.ugs_destroy(ctx)
