@@ -427,7 +427,22 @@ static int pixel_frags(const ctx_t *c, int u, int v, frag_t *F, pixinfo_t *info)
         double tT = T * (1.0 - alpha);
         double m2 = relmargin(tT, T_STOP);
         if (m2 < margin) margin = m2;
-        if (tT < T_STOP) break;
+        if (tT < T_STOP) {
+            /* the terminating fragment and the next one in depth order could swap
+             * under a rounding of the depth key: compare their depths too */
+            for (int64_t k = j + 1; k < je; ++k) {
+                const proj_t *Q = &c->P[items[k]];
+                if (c->path == 1 && (u < Q->m2[0] - Q->rx - 1.0 || u > Q->m2[0] + Q->rx + 1.0)) continue;
+                double ex = u - Q->m2[0], ey = v - Q->m2[1];
+                double pw = -0.5 * (Q->conic[0] * ex * ex + Q->conic[2] * ey * ey) - Q->conic[1] * ex * ey;
+                double a2 = Q->o * exp(pw);
+                if ((a2 < ALPHA_MAX ? a2 : ALPHA_MAX) < ALPHA_MIN) continue;
+                double mo = 10.0 * fabs(Q->z - P->z) / Q->z;
+                if (mo < margin) margin = mo;
+                break;
+            }
+            break;
+        }
         double mc = relmargin(oG, ALPHA_MAX);
         if (mc < gmargin) gmargin = mc;
         if (n >= MAX_FRAG) return -1;

@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
         out.depth[off + p] = (float)D;
         out.kmap[off + p] = K;
         out.T_final[off + p] = (float)T;
-        out.n_contrib[off + p] = last;
+        out.n_contrib[off + p] = last ? last - range.x : 0u;
         if constexpr (CO > 0) {
 #pragma unroll
             for (int c = 0; c < CO; ++c)
@@ -210,7 +210,8 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     if (ti.inside) {
         const int64_t p = ti.pix, HW = ti.HW, off = ti.off;
         T = T_final[off + p];
-        last = n_contrib[off + p];
+        const uint32_t rel = n_contrib[off + p];
+        last = rel ? range.x + rel : 0u;
         if (up_rgb) {
             gR = up_rgb[3 * off + p];
             gG = up_rgb[3 * off + HW + p];

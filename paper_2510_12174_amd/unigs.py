@@ -377,8 +377,17 @@ class Rasterizer:
         self.ensure_workspace(g, cams, max(int(P * margin) + 4096, self.pair_cap))
         self._keep = [make_gaussians(g), make_cameras(cams), make_outputs(out), make_upstream(up), make_grads(grads)]
         gs, cs, os_, us, ds = self._keep
-        _chk(lib().ugs_step_capture(self.ctx, C.byref(gs), cs, len(cams), self.ws_ptr, self.ws_bytes, C.byref(os_),
-                                    C.byref(us), C.byref(ds), _stream()), "ugs_step_capture", self.ctx)
+        # capture needs a non-default stream; the graph is launched later on
+        # whatever stream is current
+        torch = self.torch
+        cur = torch.cuda.current_stream()
+        side = torch.cuda.Stream()
+        side.wait_stream(cur)
+        with torch.cuda.stream(side):
+            rc = lib().ugs_step_capture(self.ctx, C.byref(gs), cs, len(cams), self.ws_ptr, self.ws_bytes,
+                                        C.byref(os_), C.byref(us), C.byref(ds), C.c_void_p(side.cuda_stream))
+        cur.wait_stream(side)
+        _chk(rc, "ugs_step_capture", self.ctx)
 
     def replay(self):
         _chk(lib().ugs_step_replay(self.ctx, _stream()), "ugs_step_replay", self.ctx)
