@@ -112,8 +112,11 @@ def cpu_baseline(g, cams, opts, budget_s=15.0):
         O.backward(S, cam, up, o["depth"], opts, path=1, pixmask=pm)
         return time.perf_counter() - t, int(pm.sum()), n
 
-    t1, px1, _ = run(4)
-    rows = int(min(H, max(4, 4 * budget_s / max(t1, 1e-3))))
+    t1, _, _ = run(4)
+    t2, _, _ = run(12)
+    per_row = max((t2 - t1) / 8, 1e-4)
+    fixed = max(t1 - 4 * per_row, 0.0)
+    rows = int(min(H, max(4, (budget_s - fixed) / per_row)))
     t, px, _ = run(rows)
     return dict(value=px / t / 1e6, unit="MP/s", cores=O.max_threads(), kind="oracle",
                 sample=f"view 0 ({W}x{H}), {rows} central rows = {px} pixels, fwd+normals+bwd, {t:.1f} s")

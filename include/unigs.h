@@ -181,7 +181,9 @@ int ugs_step_replay(ugs_ctx *ctx, void *stream);
  * forward outputs are bit-identical to the first one's, keeps the fastest in the
  * context options and returns it in *chosen (and its time in *ms if non-NULL).
  * Synchronous.  Uses `out` and `dg` as scratch (dg is zeroed afterwards).
- * Returns UGS_ERR_STATE if the candidates' outputs differ. */
+ * Candidates whose pair count exceeds the workspace capacity are skipped
+ * (UGS_ERR_CAPACITY only if all are).  Returns UGS_ERR_STATE if the candidates'
+ * outputs differ. */
 int ugs_autotune(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, int V, void *ws, size_t ws_bytes,
                  const ugs_outputs *out, const ugs_upstream *dout, const ugs_gaussian_grads *dg, void *stream,
                  ugs_options *chosen, float *ms);

@@ -167,8 +167,11 @@ def normal_backward(depth, cam, dnormal, opts=None):
 
 
 def zero_grads(g):
-    N, C_o = int(g["N"]), int(g["C_o"])
-    nc = (int(g["sh_deg"]) + 1) ** 2
+    if isinstance(g, _Scene):
+        N, C_o, nc = g.N, g.C_o, (g.sh_deg + 1) ** 2
+    else:
+        N, C_o = int(g["N"]), int(g["C_o"])
+        nc = (int(g["sh_deg"]) + 1) ** 2
     return dict(mean=np.zeros((3, N)), quat=np.zeros((4, N)), log_scale=np.zeros((3, N)),
                 opacity_logit=np.zeros(N), mask_logit=np.zeros(N), sh=np.zeros((nc, 3, N)),
                 sem=np.zeros((N, C_o)))

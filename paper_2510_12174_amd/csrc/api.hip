@@ -36,6 +36,16 @@ namespace {
 
 constexpr size_t kAlign = 256;
 
+// Records an event on an eager stream.  While a step is being captured the
+// stage is bracketed by event-record nodes of the graph instead (see
+// ugs_step_capture), so nothing is recorded here.
+void record_event(hipEvent_t e, hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    hipStreamIsCapturing(s, &st);
+    if (st == hipStreamCaptureStatusNone) hipEventRecord(e, s);
+}
+
 // Brackets the launches of one stage with the context's timing events.
 struct StageTimer {
     ugs_ctx *c;
@@ -43,11 +53,11 @@ struct StageTimer {
     hipStream_t s;
     StageTimer(ugs_ctx *c_, int st_, hipStream_t s_) : c(c_), st(st_), s(s_)
     {
-        if (c->timed_stage == st) hipEventRecord(c->ev_start, s);
+        if (c->timed_stage == st) record_event(c->ev_start, s);
     }
     ~StageTimer()
     {
-        if (c->timed_stage == st) hipEventRecord(c->ev_stop, s);
+        if (c->timed_stage == st) record_event(c->ev_stop, s);
     }
 };
 
@@ -227,7 +237,7 @@ int auto_batch(const ugs_options &o, int C_o)
     int nt = o.tile_w * o.tile_h;
     int per = 64 + 4 * channel_pad(C_o);
     int b = nt;
-    while (b > 16 && (size_t)b * per > 48 * 1024) b /= 2;
+    while (b > 16 && (size_t)b * per > 32 * 1024) b /= 2;
     return b;
 }
 
@@ -340,42 +350,108 @@ int do_bin_sort(ugs_ctx *ctx, void *ws, hipStream_t s, int64_t *P_out)
     return UGS_OK;
 }
 
-int do_render_fwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs *out, hipStream_t s)
+int check_fwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs *out)
 {
     int rc;
     if (!ctx->sorted || ws != ctx->ws) return UGS_ERR_STATE;
     if ((rc = check_gaussians(g)) || (rc = check_outputs(out, g->C_o))) return rc;
     if (g->N != ctx->pb.N || g->C_o != ctx->pb.C_o || g->sh_deg != ctx->pb.sh_deg) return UGS_ERR_INVALID_ARG;
-    int batch = auto_batch(ctx->opt, g->C_o);
-    {
-        StageTimer tm(ctx, 3, s);
-        HIPCHK(ctx, launch_render_fwd(*g, ctx->pb, ctx->L, ctx->ws, *out, batch, ctx->counters, ctx->final_buf, s));
-    }
-    StageTimer tm(ctx, 4, s);
-    HIPCHK(ctx, launch_normal_fwd(ctx->pb, ctx->L, ctx->ws, *out, ctx->opt, s));
     return UGS_OK;
+}
+
+int check_bwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs *out, const ugs_upstream *up,
+              const ugs_gaussian_grads *dg)
+{
+    int rc;
+    if ((rc = check_fwd(ctx, g, ws, out))) return rc;
+    if ((rc = check_grads(dg, g->C_o))) return rc;
+    return up ? UGS_OK : UGS_ERR_INVALID_ARG;
+}
+
+// Stages of one step: 0 zero gradients, 1 project, 2 bin+sort, 3 compositing
+// forward, 4 normals, 5 normal backward, 6 compositing backward, 7 projection
+// backward, 8 overflow report (captured steps only).
+struct StepArgs {
+    const ugs_gaussians *g;
+    const ugs_camera *cams;
+    int V;
+    void *ws;
+    size_t ws_bytes;
+    const ugs_outputs *out;
+    const ugs_upstream *up;
+    const ugs_gaussian_grads *dg;
+};
+
+int zero_grads(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_gaussian_grads *dg, hipStream_t s);
+
+int step_stage(ugs_ctx *ctx, const StepArgs &a, int st, hipStream_t s)
+{
+    int rc;
+    switch (st) {
+    case 0: return zero_grads(ctx, a.g, a.dg, s);
+    case 1: return do_project(ctx, a.g, a.cams, a.V, a.ws, a.ws_bytes, s);
+    case 2: return do_bin_sort(ctx, a.ws, s, nullptr);
+    case 3: {
+        if ((rc = check_fwd(ctx, a.g, a.ws, a.out))) return rc;
+        StageTimer tm(ctx, 3, s);
+        HIPCHK(ctx, launch_render_fwd(*a.g, ctx->pb, ctx->L, ctx->ws, *a.out, auto_batch(ctx->opt, a.g->C_o),
+                                      ctx->counters, ctx->final_buf, s));
+        return UGS_OK;
+    }
+    case 4: {
+        if ((rc = check_fwd(ctx, a.g, a.ws, a.out))) return rc;
+        StageTimer tm(ctx, 4, s);
+        HIPCHK(ctx, launch_normal_fwd(ctx->pb, ctx->L, ctx->ws, *a.out, ctx->opt, s));
+        return UGS_OK;
+    }
+    case 5: {
+        if ((rc = check_bwd(ctx, a.g, a.ws, a.out, a.up, a.dg))) return rc;
+        StageTimer tm(ctx, 5, s);
+        HIPCHK(ctx, launch_normal_bwd(ctx->pb, ctx->L, ctx->ws, *a.out, *a.up, ctx->opt, s));
+        return UGS_OK;
+    }
+    case 6: {
+        if ((rc = check_bwd(ctx, a.g, a.ws, a.out, a.up, a.dg))) return rc;
+        StageTimer tm(ctx, 6, s);
+        HIPCHK(ctx, launch_render_bwd(*a.g, ctx->pb, ctx->L, ctx->ws, *a.out, *a.up, *a.dg,
+                                      auto_batch(ctx->opt, a.g->C_o), ctx->final_buf, s));
+        return UGS_OK;
+    }
+    case 7: {
+        if ((rc = check_bwd(ctx, a.g, a.ws, a.out, a.up, a.dg))) return rc;
+        StageTimer tm(ctx, 7, s);
+        HIPCHK(ctx, launch_project_bwd(*a.g, ctx->pb, ctx->L, ctx->ws, *a.dg, s));
+        return UGS_OK;
+    }
+    case 8:
+        hipLaunchKernelGGL(report_flag, dim3(1), dim3(64), 0, s, (const DevCounters *)(ctx->ws + ctx->L.counters),
+                           ctx->host_flag_dev);
+        HIPCHK(ctx, hipGetLastError());
+        return UGS_OK;
+    default: return UGS_ERR_INVALID_ARG;
+    }
+}
+
+int run_stages(ugs_ctx *ctx, const StepArgs &a, int first, int last, hipStream_t s)
+{
+    for (int st = first; st <= last; ++st) {
+        int rc = step_stage(ctx, a, st, s);
+        if (rc) return rc;
+    }
+    return UGS_OK;
+}
+
+int do_render_fwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs *out, hipStream_t s)
+{
+    StepArgs a{g, nullptr, 0, ws, 0, out, nullptr, nullptr};
+    return run_stages(ctx, a, 3, 4, s);
 }
 
 int do_render_bwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs *out, const ugs_upstream *up,
                   const ugs_gaussian_grads *dg, hipStream_t s)
 {
-    int rc;
-    if (!ctx->sorted || ws != ctx->ws) return UGS_ERR_STATE;
-    if ((rc = check_gaussians(g)) || (rc = check_outputs(out, g->C_o)) || (rc = check_grads(dg, g->C_o))) return rc;
-    if (!up) return UGS_ERR_INVALID_ARG;
-    if (g->N != ctx->pb.N || g->C_o != ctx->pb.C_o || g->sh_deg != ctx->pb.sh_deg) return UGS_ERR_INVALID_ARG;
-    int batch = auto_batch(ctx->opt, g->C_o);
-    {
-        StageTimer tm(ctx, 5, s);
-        HIPCHK(ctx, launch_normal_bwd(ctx->pb, ctx->L, ctx->ws, *out, *up, ctx->opt, s));
-    }
-    {
-        StageTimer tm(ctx, 6, s);
-        HIPCHK(ctx, launch_render_bwd(*g, ctx->pb, ctx->L, ctx->ws, *out, *up, *dg, batch, ctx->final_buf, s));
-    }
-    StageTimer tm(ctx, 7, s);
-    HIPCHK(ctx, launch_project_bwd(*g, ctx->pb, ctx->L, ctx->ws, *dg, s));
-    return UGS_OK;
+    StepArgs a{g, nullptr, 0, ws, 0, out, up, dg};
+    return run_stages(ctx, a, 5, 7, s);
 }
 
 int zero_grads(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_gaussian_grads *dg, hipStream_t s)
@@ -398,11 +474,24 @@ int full_step(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, int 
 {
     int rc;
     if ((rc = check_grads(dg, g ? g->C_o : 0))) return rc;
-    if (zero && (rc = zero_grads(ctx, g, dg, s))) return rc;
-    if ((rc = do_project(ctx, g, cams, V, ws, ws_bytes, s))) return rc;
-    if ((rc = do_bin_sort(ctx, ws, s, nullptr))) return rc;
-    if ((rc = do_render_fwd(ctx, g, ws, out, s))) return rc;
-    return do_render_bwd(ctx, g, ws, out, up, dg, s);
+    StepArgs a{g, cams, V, ws, ws_bytes, out, up, dg};
+    return run_stages(ctx, a, zero ? 0 : 1, 7, s);
+}
+
+// Captures stages [first, last] of a step into a new graph.
+int capture_stages(ugs_ctx *ctx, const StepArgs &a, int first, int last, hipStream_t s, hipGraph_t *graph)
+{
+    *graph = nullptr;
+    HIPCHK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = run_stages(ctx, a, first, last, s);
+    hipError_t e = hipStreamEndCapture(s, graph);
+    if (rc != UGS_OK) {
+        if (*graph) hipGraphDestroy(*graph);
+        *graph = nullptr;
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+    return UGS_OK;
 }
 
 void release_graph(ugs_ctx *ctx)
@@ -545,19 +634,35 @@ int ugs_step_capture(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cam
         HIPCHK(ctx, hipHostGetDevicePointer((void **)&ctx->host_flag_dev, ctx->host_flag, 0));
     }
     ctx->host_flag[0] = 0;
-    HIPCHK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    rc = full_step(ctx, g, cams, V, ws, ws_bytes, out, dout, dg, s, true);
-    if (rc == UGS_OK) hipLaunchKernelGGL(report_flag, dim3(1), dim3(64), 0, s,
-                                         (const DevCounters *)(ctx->ws + ctx->L.counters), ctx->host_flag_dev);
+    StepArgs a{g, cams, V, ws, ws_bytes, out, dout, dg};
     hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(s, &graph);
-    if (rc != UGS_OK) {
-        if (graph) hipGraphDestroy(graph);
-        return rc;
+    const int T = ctx->timed_stage;
+    if (T == 0) {
+        if ((rc = capture_stages(ctx, a, 0, 8, s, &graph))) return rc;
+    } else {
+        // before -> event -> timed stage -> event -> after, as child graphs of one graph
+        hipGraph_t parts[3] = {nullptr, nullptr, nullptr};
+        if ((rc = capture_stages(ctx, a, 0, T - 1, s, &parts[0])) || (rc = capture_stages(ctx, a, T, T, s, &parts[1])) ||
+            (rc = capture_stages(ctx, a, T + 1, 8, s, &parts[2]))) {
+            for (auto p : parts)
+                if (p) hipGraphDestroy(p);
+            return rc;
+        }
+        hipError_t e = hipGraphCreate(&graph, 0);
+        hipGraphNode_t n0, e0, n1, e1, n2;
+        if (e == hipSuccess) e = hipGraphAddChildGraphNode(&n0, graph, nullptr, 0, parts[0]);
+        if (e == hipSuccess) e = hipGraphAddEventRecordNode(&e0, graph, &n0, 1, ctx->ev_start);
+        if (e == hipSuccess) e = hipGraphAddChildGraphNode(&n1, graph, &e0, 1, parts[1]);
+        if (e == hipSuccess) e = hipGraphAddEventRecordNode(&e1, graph, &n1, 1, ctx->ev_stop);
+        if (e == hipSuccess) e = hipGraphAddChildGraphNode(&n2, graph, &e1, 1, parts[2]);
+        for (auto p : parts) hipGraphDestroy(p);  // child nodes hold their own copies
+        if (e != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return hip_fail(ctx, e, "assembling the timed step graph");
+        }
     }
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
     ctx->graph = graph;
-    e = hipGraphInstantiate(&ctx->exec, graph, nullptr, nullptr, 0);
+    hipError_t e = hipGraphInstantiate(&ctx->exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         release_graph(ctx);
         return hip_fail(ctx, e, "hipGraphInstantiate");
@@ -601,7 +706,8 @@ int ugs_autotune(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, i
     float best = 1e30f;
     ugs_options best_opt = base;
     int rc = UGS_OK;
-    bool mismatch = false;
+    bool mismatch = false, have_ref = false;
+    size_t skipped = 0;
     for (size_t ci = 0; ci < cands.size() && rc == UGS_OK; ++ci) {
         ugs_options o = base;
         o.tile_w = cands[ci].tw;
@@ -612,7 +718,13 @@ int ugs_autotune(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, i
         // warm-up and capacity check
         if ((rc = full_step(ctx, g, cams, V, ws, ws_bytes, out, dout, dg, s, true))) break;
         int64_t Preq = 0;
-        if ((rc = ugs_check_overflow(ctx, ws, s, &Preq))) break;
+        rc = ugs_check_overflow(ctx, ws, s, &Preq);
+        if (rc == UGS_ERR_CAPACITY) {  // this tile shape needs more pairs than the workspace holds
+            rc = UGS_OK;
+            ++skipped;
+            continue;
+        }
+        if (rc) break;
         float tmin = 1e30f;
         for (int r = 0; r < 2 && rc == UGS_OK; ++r) {
             if (hipEventRecord(e0, s) != hipSuccess) { rc = UGS_ERR_HIP; break; }
@@ -640,8 +752,12 @@ int ugs_autotune(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, i
             rc = UGS_ERR_HIP;
             break;
         }
-        if (ci == 0) ref_hash = h;
-        else if (h != ref_hash) mismatch = true;
+        if (!have_ref) {
+            ref_hash = h;
+            have_ref = true;
+        } else if (h != ref_hash) {
+            mismatch = true;
+        }
         if (tmin < best) {
             best = tmin;
             best_opt = o;
@@ -649,6 +765,7 @@ int ugs_autotune(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, i
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    if (rc == UGS_OK && skipped == cands.size()) rc = UGS_ERR_CAPACITY;
     ctx->opt = (rc == UGS_OK) ? best_opt : base;
     ctx->have_problem = false;
     ctx->sorted = false;

@@ -15,202 +15,216 @@ constexpr int kProjThreads = 256;
 // UniGS inherits for colour).  Values are the closed-form normalisations
 // sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) times the Legendre factors.
 struct SHK {
-    static constexpr float c0 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
-    static constexpr float c1 = 0.48860251190291992f;   // sqrt(3)/(2 sqrt(pi))
-    static constexpr float c2a = 1.0925484305920792f;   // sqrt(15)/(2 sqrt(pi))
-    static constexpr float c2b = 0.31539156525252005f;  // sqrt(5)/(4 sqrt(pi))
-    static constexpr float c2c = 0.54627421529603959f;  // sqrt(15)/(4 sqrt(pi))
-    static constexpr float c3a = 0.59004358992664352f;  // sqrt(35/(2 pi))/4
-    static constexpr float c3b = 2.8906114426405538f;   // sqrt(105/pi)/2
-    static constexpr float c3c = 0.45704579946446572f;  // sqrt(21/(2 pi))/4
-    static constexpr float c3d = 0.37317633259011546f;  // sqrt(7/pi)/4
-    static constexpr float c3e = 1.4453057213202769f;   // sqrt(105/pi)/4
+    static constexpr double c0 = 0.28209479177387814;   // 1/(2 sqrt(pi))
+    static constexpr double c1 = 0.48860251190291992;   // sqrt(3)/(2 sqrt(pi))
+    static constexpr double c2a = 1.0925484305920792;   // sqrt(15)/(2 sqrt(pi))
+    static constexpr double c2b = 0.31539156525252005;  // sqrt(5)/(4 sqrt(pi))
+    static constexpr double c2c = 0.54627421529603959;  // sqrt(15)/(4 sqrt(pi))
+    static constexpr double c3a = 0.59004358992664352;  // sqrt(35/(2 pi))/4
+    static constexpr double c3b = 2.8906114426405538;   // sqrt(105/pi)/2
+    static constexpr double c3c = 0.45704579946446572;  // sqrt(21/(2 pi))/4
+    static constexpr double c3d = 0.37317633259011546;  // sqrt(7/pi)/4
+    static constexpr double c3e = 1.4453057213202769;   // sqrt(105/pi)/4
 };
 
-template <int DEG>
-__device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y)
+template <int DEG, typename F>
+__device__ __forceinline__ void sh_basis(F x, F y, F z, F *Y)
 {
-    Y[0] = SHK::c0;
+    Y[0] = F(SHK::c0);
     if constexpr (DEG >= 1) {
-        Y[1] = -SHK::c1 * y;
-        Y[2] = SHK::c1 * z;
-        Y[3] = -SHK::c1 * x;
+        Y[1] = -F(SHK::c1) * y;
+        Y[2] = F(SHK::c1) * z;
+        Y[3] = -F(SHK::c1) * x;
     }
     if constexpr (DEG >= 2) {
-        float xx = x * x, yy = y * y, zz = z * z;
-        Y[4] = SHK::c2a * x * y;
-        Y[5] = -SHK::c2a * y * z;
-        Y[6] = SHK::c2b * (2.f * zz - xx - yy);
-        Y[7] = -SHK::c2a * x * z;
-        Y[8] = SHK::c2c * (xx - yy);
+        F xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = F(SHK::c2a) * x * y;
+        Y[5] = -F(SHK::c2a) * y * z;
+        Y[6] = F(SHK::c2b) * (F(2) * zz - xx - yy);
+        Y[7] = -F(SHK::c2a) * x * z;
+        Y[8] = F(SHK::c2c) * (xx - yy);
     }
     if constexpr (DEG >= 3) {
-        float xx = x * x, yy = y * y, zz = z * z;
-        Y[9] = -SHK::c3a * y * (3.f * xx - yy);
-        Y[10] = SHK::c3b * x * y * z;
-        Y[11] = -SHK::c3c * y * (4.f * zz - xx - yy);
-        Y[12] = SHK::c3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
-        Y[13] = -SHK::c3c * x * (4.f * zz - xx - yy);
-        Y[14] = SHK::c3e * z * (xx - yy);
-        Y[15] = -SHK::c3a * x * (xx - 3.f * yy);
+        F xx = x * x, yy = y * y, zz = z * z;
+        Y[9] = -F(SHK::c3a) * y * (F(3) * xx - yy);
+        Y[10] = F(SHK::c3b) * x * y * z;
+        Y[11] = -F(SHK::c3c) * y * (F(4) * zz - xx - yy);
+        Y[12] = F(SHK::c3d) * z * (F(2) * zz - F(3) * xx - F(3) * yy);
+        Y[13] = -F(SHK::c3c) * x * (F(4) * zz - xx - yy);
+        Y[14] = F(SHK::c3e) * z * (xx - yy);
+        Y[15] = -F(SHK::c3a) * x * (xx - F(3) * yy);
     }
 }
 
 // d/d(x,y,z) of sum_c Y_c(x,y,z) w_c for a weight vector w (one colour channel's
 // coefficients scaled by its upstream gradient).
-template <int DEG>
-__device__ __forceinline__ void sh_basis_vjp(float x, float y, float z, const float *w, float &gx, float &gy,
-                                             float &gz)
+template <int DEG, typename F>
+__device__ __forceinline__ void sh_basis_vjp(F x, F y, F z, const F *w, F &gx, F &gy, F &gz)
 {
-    gx = gy = gz = 0.f;
+    gx = gy = gz = F(0);
     if constexpr (DEG >= 1) {
-        gy += -SHK::c1 * w[1];
-        gz += SHK::c1 * w[2];
-        gx += -SHK::c1 * w[3];
+        gy += -F(SHK::c1) * w[1];
+        gz += F(SHK::c1) * w[2];
+        gx += -F(SHK::c1) * w[3];
     }
     if constexpr (DEG >= 2) {
-        gx += SHK::c2a * y * w[4];
-        gy += SHK::c2a * x * w[4];
-        gy += -SHK::c2a * z * w[5];
-        gz += -SHK::c2a * y * w[5];
-        gx += -2.f * SHK::c2b * x * w[6];
-        gy += -2.f * SHK::c2b * y * w[6];
-        gz += 4.f * SHK::c2b * z * w[6];
-        gx += -SHK::c2a * z * w[7];
-        gz += -SHK::c2a * x * w[7];
-        gx += 2.f * SHK::c2c * x * w[8];
-        gy += -2.f * SHK::c2c * y * w[8];
+        gx += F(SHK::c2a) * y * w[4];
+        gy += F(SHK::c2a) * x * w[4];
+        gy += -F(SHK::c2a) * z * w[5];
+        gz += -F(SHK::c2a) * y * w[5];
+        gx += -F(2) * F(SHK::c2b) * x * w[6];
+        gy += -F(2) * F(SHK::c2b) * y * w[6];
+        gz += F(4) * F(SHK::c2b) * z * w[6];
+        gx += -F(SHK::c2a) * z * w[7];
+        gz += -F(SHK::c2a) * x * w[7];
+        gx += F(2) * F(SHK::c2c) * x * w[8];
+        gy += -F(2) * F(SHK::c2c) * y * w[8];
     }
     if constexpr (DEG >= 3) {
-        float xx = x * x, yy = y * y, zz = z * z;
-        gx += -6.f * SHK::c3a * x * y * w[9];
-        gy += -3.f * SHK::c3a * (xx - yy) * w[9];
-        gx += SHK::c3b * y * z * w[10];
-        gy += SHK::c3b * x * z * w[10];
-        gz += SHK::c3b * x * y * w[10];
-        gx += 2.f * SHK::c3c * x * y * w[11];
-        gy += -SHK::c3c * (4.f * zz - xx - 3.f * yy) * w[11];
-        gz += -8.f * SHK::c3c * y * z * w[11];
-        gx += -6.f * SHK::c3d * x * z * w[12];
-        gy += -6.f * SHK::c3d * y * z * w[12];
-        gz += SHK::c3d * (6.f * zz - 3.f * xx - 3.f * yy) * w[12];
-        gx += -SHK::c3c * (4.f * zz - 3.f * xx - yy) * w[13];
-        gy += 2.f * SHK::c3c * x * y * w[13];
-        gz += -8.f * SHK::c3c * x * z * w[13];
-        gx += 2.f * SHK::c3e * x * z * w[14];
-        gy += -2.f * SHK::c3e * y * z * w[14];
-        gz += SHK::c3e * (xx - yy) * w[14];
-        gx += -3.f * SHK::c3a * (xx - yy) * w[15];
-        gy += 6.f * SHK::c3a * x * y * w[15];
+        F xx = x * x, yy = y * y, zz = z * z;
+        gx += -F(6) * F(SHK::c3a) * x * y * w[9];
+        gy += -F(3) * F(SHK::c3a) * (xx - yy) * w[9];
+        gx += F(SHK::c3b) * y * z * w[10];
+        gy += F(SHK::c3b) * x * z * w[10];
+        gz += F(SHK::c3b) * x * y * w[10];
+        gx += F(2) * F(SHK::c3c) * x * y * w[11];
+        gy += -F(SHK::c3c) * (F(4) * zz - xx - F(3) * yy) * w[11];
+        gz += -F(8) * F(SHK::c3c) * y * z * w[11];
+        gx += -F(6) * F(SHK::c3d) * x * z * w[12];
+        gy += -F(6) * F(SHK::c3d) * y * z * w[12];
+        gz += F(SHK::c3d) * (F(6) * zz - F(3) * xx - F(3) * yy) * w[12];
+        gx += -F(SHK::c3c) * (F(4) * zz - F(3) * xx - yy) * w[13];
+        gy += F(2) * F(SHK::c3c) * x * y * w[13];
+        gz += -F(8) * F(SHK::c3c) * x * z * w[13];
+        gx += F(2) * F(SHK::c3e) * x * z * w[14];
+        gy += -F(2) * F(SHK::c3e) * y * z * w[14];
+        gz += F(SHK::c3e) * (xx - yy) * w[14];
+        gx += -F(3) * F(SHK::c3a) * (xx - yy) * w[15];
+        gy += F(6) * F(SHK::c3a) * x * y * w[15];
     }
 }
 
+__device__ __forceinline__ float m_exp(float x) { return __expf(x); }
+__device__ __forceinline__ double m_exp(double x) { return exp(x); }
+__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+template <typename F> __device__ __forceinline__ F m_min(F a, F b) { return a < b ? a : b; }
+template <typename F> __device__ __forceinline__ F m_max(F a, F b) { return a > b ? a : b; }
+template <typename F> __device__ __forceinline__ F m_sigmoid(F x) { return F(1) / (F(1) + m_exp(-x)); }
+
 // Rotation matrix (row-major) of the unit quaternion (w, x, y, z).
-__device__ __forceinline__ void rotmat(float w, float x, float y, float z, float *M)
+template <typename F>
+__device__ __forceinline__ void rotmat(F w, F x, F y, F z, F *M)
 {
-    M[0] = 1.f - 2.f * (y * y + z * z);
-    M[1] = 2.f * (x * y - w * z);
-    M[2] = 2.f * (x * z + w * y);
-    M[3] = 2.f * (x * y + w * z);
-    M[4] = 1.f - 2.f * (x * x + z * z);
-    M[5] = 2.f * (y * z - w * x);
-    M[6] = 2.f * (x * z - w * y);
-    M[7] = 2.f * (y * z + w * x);
-    M[8] = 1.f - 2.f * (x * x + y * y);
+    M[0] = F(1) - F(2) * (y * y + z * z);
+    M[1] = F(2) * (x * y - w * z);
+    M[2] = F(2) * (x * z + w * y);
+    M[3] = F(2) * (x * y + w * z);
+    M[4] = F(1) - F(2) * (x * x + z * z);
+    M[5] = F(2) * (y * z - w * x);
+    M[6] = F(2) * (x * z - w * y);
+    M[7] = F(2) * (y * z + w * x);
+    M[8] = F(1) - F(2) * (x * x + y * y);
 }
 
 // Gaussian-level quantities shared by every view.
+template <typename F>
 struct GaussState {
-    float mu[3], s[3], is2[3], qn, qh[4], Rg[9], Sig[6];  // Sig: 00 01 02 11 12 22
-    float o, k;
+    F mu[3], s[3], is2[3], qn, qh[4], Rg[9], Sig[6];  // Sig: 00 01 02 11 12 22
+    F o, k;
 };
 
-__device__ __forceinline__ void load_gauss(const ugs_gaussians &g, int64_t i, GaussState &G)
+template <typename F>
+__device__ __forceinline__ void load_gauss(const ugs_gaussians &g, int64_t i, GaussState<F> &G)
 {
     const int64_t N = g.N;
     for (int a = 0; a < 3; ++a) {
-        G.mu[a] = g.mean[a * N + i];
-        G.s[a] = __expf(g.log_scale[a * N + i]);
-        G.is2[a] = 1.f / (G.s[a] * G.s[a]);
+        G.mu[a] = F(g.mean[a * N + i]);
+        G.s[a] = m_exp(F(g.log_scale[a * N + i]));
+        G.is2[a] = F(1) / (G.s[a] * G.s[a]);
     }
-    float q0 = g.quat[i], q1 = g.quat[N + i], q2 = g.quat[2 * N + i], q3 = g.quat[3 * N + i];
-    G.qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-    float iq = 1.f / G.qn;
+    F q0 = F(g.quat[i]), q1 = F(g.quat[N + i]), q2 = F(g.quat[2 * N + i]), q3 = F(g.quat[3 * N + i]);
+    G.qn = m_sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    F iq = F(1) / G.qn;
     G.qh[0] = q0 * iq; G.qh[1] = q1 * iq; G.qh[2] = q2 * iq; G.qh[3] = q3 * iq;
     rotmat(G.qh[0], G.qh[1], G.qh[2], G.qh[3], G.Rg);
-    float s2[3] = {G.s[0] * G.s[0], G.s[1] * G.s[1], G.s[2] * G.s[2]};
-    const float *M = G.Rg;
+    F s2[3] = {G.s[0] * G.s[0], G.s[1] * G.s[1], G.s[2] * G.s[2]};
+    const F *M = G.Rg;
     auto sig = [&](int a, int b) { return M[3 * a] * s2[0] * M[3 * b] + M[3 * a + 1] * s2[1] * M[3 * b + 1] + M[3 * a + 2] * s2[2] * M[3 * b + 2]; };
     G.Sig[0] = sig(0, 0); G.Sig[1] = sig(0, 1); G.Sig[2] = sig(0, 2);
     G.Sig[3] = sig(1, 1); G.Sig[4] = sig(1, 2); G.Sig[5] = sig(2, 2);
-    G.o = sigmoidf_(g.opacity_logit[i]);
-    G.k = sigmoidf_(g.mask_logit[i]);
+    G.o = m_sigmoid(F(g.opacity_logit[i]));
+    G.k = m_sigmoid(F(g.mask_logit[i]));
 }
 
 // View-dependent projection state.
+template <typename F>
 struct ViewState {
-    float mc[3], z, tx, ty;
+    F mc[3], z, tx, ty;
     bool clx, cly;
-    float T0[3], T1[3];      // rows of J R
-    float cov00, cov01, cov11;
-    float ca, cb, cc;         // conic
-    float m2x, m2y;
-    float dir[3], dist;
-    float M[9];               // R Rg
-    float p0[3], wv[3], A, iA, Qp0x, Qp0y, Q00, Q01, Q11;
+    F T0[3], T1[3];      // rows of J R
+    F cov00, cov01, cov11;
+    F ca, cb, cc;         // conic
+    F m2x, m2y;
+    F dir[3], dist;
+    F M[9];               // R Rg
+    F p0[3], wv[3], A, iA, Qp0x, Qp0y, Q00, Q01, Q11;
 };
 
-__device__ __forceinline__ void project_view(const GaussState &G, const DevCam &cam, ViewState &S)
+template <typename F>
+__device__ __forceinline__ void project_view(const GaussState<F> &G, const DevCam &cam, ViewState<F> &S)
 {
-    const float *R = cam.R;
-    for (int a = 0; a < 3; ++a) S.mc[a] = R[3 * a] * G.mu[0] + R[3 * a + 1] * G.mu[1] + R[3 * a + 2] * G.mu[2] + cam.t[a];
-    float z = S.mc[2];
+    F R[9];
+    for (int k = 0; k < 9; ++k) R[k] = F(cam.R[k]);
+    const F fx = F(cam.fx), fy = F(cam.fy), limx = F(cam.limx), limy = F(cam.limy);
+    for (int a = 0; a < 3; ++a) S.mc[a] = R[3 * a] * G.mu[0] + R[3 * a + 1] * G.mu[1] + R[3 * a + 2] * G.mu[2] + F(cam.t[a]);
+    F z = S.mc[2];
     S.z = z;
-    float iz = 1.f / z;
-    float rx = S.mc[0] * iz, ry = S.mc[1] * iz;
-    S.clx = rx < -cam.limx || rx > cam.limx;
-    S.cly = ry < -cam.limy || ry > cam.limy;
-    S.tx = fminf(cam.limx, fmaxf(-cam.limx, rx)) * z;
-    S.ty = fminf(cam.limy, fmaxf(-cam.limy, ry)) * z;
-    float J00 = cam.fx * iz, J02 = -cam.fx * S.tx * iz * iz;
-    float J11 = cam.fy * iz, J12 = -cam.fy * S.ty * iz * iz;
+    F iz = F(1) / z;
+    F rx = S.mc[0] * iz, ry = S.mc[1] * iz;
+    S.clx = rx < -limx || rx > limx;
+    S.cly = ry < -limy || ry > limy;
+    S.tx = m_min(limx, m_max(-limx, rx)) * z;
+    S.ty = m_min(limy, m_max(-limy, ry)) * z;
+    F J00 = fx * iz, J02 = -fx * S.tx * iz * iz;
+    F J11 = fy * iz, J12 = -fy * S.ty * iz * iz;
     for (int b = 0; b < 3; ++b) {
         S.T0[b] = J00 * R[b] + J02 * R[6 + b];
         S.T1[b] = J11 * R[3 + b] + J12 * R[6 + b];
     }
-    const float *Sg = G.Sig;
-    auto quad = [&](const float *u, const float *v) {
-        float su0 = Sg[0] * u[0] + Sg[1] * u[1] + Sg[2] * u[2];
-        float su1 = Sg[1] * u[0] + Sg[3] * u[1] + Sg[4] * u[2];
-        float su2 = Sg[2] * u[0] + Sg[4] * u[1] + Sg[5] * u[2];
+    const F *Sg = G.Sig;
+    auto quad = [&](const F *u, const F *v) {
+        F su0 = Sg[0] * u[0] + Sg[1] * u[1] + Sg[2] * u[2];
+        F su1 = Sg[1] * u[0] + Sg[3] * u[1] + Sg[4] * u[2];
+        F su2 = Sg[2] * u[0] + Sg[4] * u[1] + Sg[5] * u[2];
         return v[0] * su0 + v[1] * su1 + v[2] * su2;
     };
-    S.cov00 = quad(S.T0, S.T0) + kLowPass;
+    S.cov00 = quad(S.T0, S.T0) + F(kLowPass);
     S.cov01 = quad(S.T0, S.T1);
-    S.cov11 = quad(S.T1, S.T1) + kLowPass;
-    float idet = 1.f / (S.cov00 * S.cov11 - S.cov01 * S.cov01);
+    S.cov11 = quad(S.T1, S.T1) + F(kLowPass);
+    F idet = F(1) / (S.cov00 * S.cov11 - S.cov01 * S.cov01);
     S.ca = S.cov11 * idet;
     S.cb = -S.cov01 * idet;
     S.cc = S.cov00 * idet;
-    S.m2x = cam.fx * S.mc[0] * iz + cam.cx;
-    S.m2y = cam.fy * S.mc[1] * iz + cam.cy;
-    float v0 = G.mu[0] - cam.C[0], v1 = G.mu[1] - cam.C[1], v2 = G.mu[2] - cam.C[2];
-    S.dist = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
-    float id = 1.f / S.dist;
+    S.m2x = fx * S.mc[0] * iz + F(cam.cx);
+    S.m2y = fy * S.mc[1] * iz + F(cam.cy);
+    F v0 = G.mu[0] - F(cam.C[0]), v1 = G.mu[1] - F(cam.C[1]), v2 = G.mu[2] - F(cam.C[2]);
+    S.dist = m_sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+    F id = F(1) / S.dist;
     S.dir[0] = v0 * id; S.dir[1] = v1 * id; S.dir[2] = v2 * id;
     // camera-frame axes of the ellipsoid and the depth quadric
     for (int a = 0; a < 3; ++a)
         for (int k = 0; k < 3; ++k) S.M[3 * a + k] = R[3 * a] * G.Rg[k] + R[3 * a + 1] * G.Rg[3 + k] + R[3 * a + 2] * G.Rg[6 + k];
-    S.p0[0] = S.mc[0] * iz; S.p0[1] = S.mc[1] * iz; S.p0[2] = 1.f;
-    S.A = 0.f;
+    S.p0[0] = S.mc[0] * iz; S.p0[1] = S.mc[1] * iz; S.p0[2] = F(1);
+    S.A = F(0);
     for (int k = 0; k < 3; ++k) {
         S.wv[k] = S.M[k] * S.p0[0] + S.M[3 + k] * S.p0[1] + S.M[6 + k];
         S.A += S.wv[k] * S.wv[k] * G.is2[k];
     }
-    S.iA = 1.f / S.A;
-    S.Qp0x = S.Qp0y = S.Q00 = S.Q01 = S.Q11 = 0.f;
+    S.iA = F(1) / S.A;
+    S.Qp0x = S.Qp0y = S.Q00 = S.Q01 = S.Q11 = F(0);
     for (int k = 0; k < 3; ++k) {
-        float e = S.wv[k] * G.is2[k];
+        F e = S.wv[k] * G.is2[k];
         S.Qp0x += S.M[k] * e;
         S.Qp0y += S.M[3 + k] * e;
         S.Q00 += S.M[k] * S.M[k] * G.is2[k];
@@ -230,7 +244,7 @@ __global__ void __launch_bounds__(kProjThreads) project_fwd_kernel(ugs_gaussians
     const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
     if (i >= N) return;
     constexpr int NC = (DEG + 1) * (DEG + 1);
-    GaussState G;
+    GaussState<float> G;
     load_gauss(g, i, G);
     bool alive = G.o >= kAlphaMin && !(prune_Tk > 0.f && fabsf(G.k - 1.f) > prune_Tk);
     float sh[NC][3];
@@ -245,7 +259,7 @@ __global__ void __launch_bounds__(kProjThreads) project_fwd_kernel(ugs_gaussians
         uint2 rc = make_uint2(0, 0);
         float zc = cam.R[6] * G.mu[0] + cam.R[7] * G.mu[1] + cam.R[8] * G.mu[2] + cam.t[2];
         if (alive && zc > cam.z_near) {
-            ViewState S;
+            ViewState<float> S;
             project_view(G, cam, S);
             float rx = sqrtf(S.cov00 * r2) * (1.f + 1e-4f) + 1e-3f;
             float ry = sqrtf(S.cov11 * r2) * (1.f + 1e-4f) + 1e-3f;
@@ -294,13 +308,14 @@ __global__ void __launch_bounds__(kProjThreads) project_bwd_kernel(ugs_gaussians
     const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
     if (i >= N) return;
     constexpr int NC = (DEG + 1) * (DEG + 1);
-    GaussState G;
+    using D = double;  // the chain rule runs in FP64: its terms scale like 1/s^2 and cancel
+    GaussState<D> G;
     load_gauss(g, i, G);
-    float dmu[3] = {0.f, 0.f, 0.f}, dRg[9], ds[3] = {0.f, 0.f, 0.f}, dSig[6], dis2[3] = {0.f, 0.f, 0.f};
-    for (int k = 0; k < 9; ++k) dRg[k] = 0.f;
-    for (int k = 0; k < 6; ++k) dSig[k] = 0.f;
-    float dop = 0.f;
-    float sh[NC][3], dsh[NC][3];
+    D dmu[3] = {D(0), D(0), D(0)}, dRg[9], ds[3] = {D(0), D(0), D(0)}, dSig[6], dis2[3] = {D(0), D(0), D(0)};
+    for (int k = 0; k < 9; ++k) dRg[k] = D(0);
+    for (int k = 0; k < 6; ++k) dSig[k] = D(0);
+    D dop = D(0), dk = D(0);
+    float sh[NC][3], dsh[NC][3];  // coefficients and their gradients stay FP32
     bool loaded = false;
     for (int v = 0; v < V; ++v) {
         const int64_t idx = (int64_t)v * N + i;
@@ -316,35 +331,37 @@ __global__ void __launch_bounds__(kProjThreads) project_bwd_kernel(ugs_gaussians
         }
         const float4 *gr = grec + idx * 4;
         float4 g0 = gr[0], g1 = gr[1], g2 = gr[2], g3 = gr[3];
-        ViewState S;
+        ViewState<D> S;
         project_view(G, cam, S);
-        const float *R = cam.R;
-        const float fx = cam.fx, fy = cam.fy, z = S.z, iz = 1.f / z;
+        D R[9];
+        for (int k = 0; k < 9; ++k) R[k] = D(cam.R[k]);
+        const D fx = D(cam.fx), fy = D(cam.fy), z = S.z, iz = D(1) / z;
         dop += g1.y;
-        float dmc[3] = {0.f, 0.f, 0.f};
+        dk += g1.z;
+        D dmc[3] = {D(0), D(0), D(0)};
 
         // colour (SH) and the view direction
         {
-            float Y[NC];
+            D Y[NC];
             sh_basis<DEG>(S.dir[0], S.dir[1], S.dir[2], Y);
-            float dcol[3] = {g3.y, g3.z, g3.w};
-            float ddx = 0.f, ddy = 0.f, ddz = 0.f;
+            D dcol[3] = {g3.y, g3.z, g3.w};
+            D ddx = D(0), ddy = D(0), ddz = D(0);
             for (int ch = 0; ch < 3; ++ch) {
-                float raw = 0.5f;
+                D raw = D(0.5);
                 for (int c = 0; c < NC; ++c) raw += Y[c] * sh[c][ch];
-                float dc = raw > 0.f ? dcol[ch] : 0.f;
-                if (dc == 0.f) continue;
-                float w[NC];
+                D dc = raw > D(0) ? dcol[ch] : D(0);
+                if (dc == D(0)) continue;
+                D w[NC];
                 for (int c = 0; c < NC; ++c) {
                     dsh[c][ch] += dc * Y[c];
                     w[c] = dc * sh[c][ch];
                 }
-                float gx, gy, gz;
+                D gx, gy, gz;
                 sh_basis_vjp<DEG>(S.dir[0], S.dir[1], S.dir[2], w, gx, gy, gz);
                 ddx += gx; ddy += gy; ddz += gz;
             }
-            float pr = S.dir[0] * ddx + S.dir[1] * ddy + S.dir[2] * ddz;
-            float id = 1.f / S.dist;
+            D pr = S.dir[0] * ddx + S.dir[1] * ddy + S.dir[2] * ddz;
+            D id = D(1) / S.dist;
             dmu[0] += (ddx - S.dir[0] * pr) * id;
             dmu[1] += (ddy - S.dir[1] * pr) * id;
             dmu[2] += (ddz - S.dir[2] * pr) * id;
@@ -355,72 +372,72 @@ __global__ void __launch_bounds__(kProjThreads) project_bwd_kernel(ugs_gaussians
         dmc[2] -= (g0.x * fx * S.mc[0] + g0.y * fy * S.mc[1]) * iz * iz;
         // conic -> 2D covariance: dS = -C dC C with dC = [[da, db/2], [db/2, dc]]
         {
-            float a = S.ca, b = S.cb, c = S.cc;
-            float da = g0.z, db = 0.5f * g0.w, dcn = g1.x;
-            float X00 = da * a + db * b, X01 = da * b + db * c, X10 = db * a + dcn * b, X11 = db * b + dcn * c;
-            float dS00 = -(a * X00 + b * X10), dS01 = -(a * X01 + b * X11), dS11 = -(b * X01 + c * X11);
+            D a = S.ca, b = S.cb, c = S.cc;
+            D da = g0.z, db = D(0.5) * g0.w, dcn = g1.x;
+            D X00 = da * a + db * b, X01 = da * b + db * c, X10 = db * a + dcn * b, X11 = db * b + dcn * c;
+            D dS00 = -(a * X00 + b * X10), dS01 = -(a * X01 + b * X11), dS11 = -(b * X01 + c * X11);
             // cov = T Sig T^T: dSig += T^T dS T, dT = 2 dS T Sig
-            const float *t0 = S.T0, *t1 = S.T1;
+            const D *t0 = S.T0, *t1 = S.T1;
             for (int p = 0, n = 0; p < 3; ++p)
                 for (int q = p; q < 3; ++q, ++n) {
-                    float val = t0[p] * dS00 * t0[q] + t0[p] * dS01 * t1[q] + t1[p] * dS01 * t0[q] + t1[p] * dS11 * t1[q];
+                    D val = t0[p] * dS00 * t0[q] + t0[p] * dS01 * t1[q] + t1[p] * dS01 * t0[q] + t1[p] * dS11 * t1[q];
                     dSig[n] += val;
                 }
-            const float *Sg = G.Sig;
-            float TS0[3], TS1[3];
+            const D *Sg = G.Sig;
+            D TS0[3], TS1[3];
             TS0[0] = t0[0] * Sg[0] + t0[1] * Sg[1] + t0[2] * Sg[2];
             TS0[1] = t0[0] * Sg[1] + t0[1] * Sg[3] + t0[2] * Sg[4];
             TS0[2] = t0[0] * Sg[2] + t0[1] * Sg[4] + t0[2] * Sg[5];
             TS1[0] = t1[0] * Sg[0] + t1[1] * Sg[1] + t1[2] * Sg[2];
             TS1[1] = t1[0] * Sg[1] + t1[1] * Sg[3] + t1[2] * Sg[4];
             TS1[2] = t1[0] * Sg[2] + t1[1] * Sg[4] + t1[2] * Sg[5];
-            float dT0[3], dT1[3];
+            D dT0[3], dT1[3];
             for (int q = 0; q < 3; ++q) {
-                dT0[q] = 2.f * (dS00 * TS0[q] + dS01 * TS1[q]);
-                dT1[q] = 2.f * (dS01 * TS0[q] + dS11 * TS1[q]);
+                dT0[q] = D(2) * (dS00 * TS0[q] + dS01 * TS1[q]);
+                dT1[q] = D(2) * (dS01 * TS0[q] + dS11 * TS1[q]);
             }
             // T0 = J00 R0 + J02 R2, T1 = J11 R1 + J12 R2
-            float dJ00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
-            float dJ02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
-            float dJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
-            float dJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
-            float iz2 = iz * iz, iz3 = iz2 * iz;
-            dmc[2] += -dJ00 * fx * iz2 - dJ11 * fy * iz2 + 2.f * dJ02 * fx * S.tx * iz3 + 2.f * dJ12 * fy * S.ty * iz3;
-            float dtx = -dJ02 * fx * iz2, dty = -dJ12 * fy * iz2;
+            D dJ00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
+            D dJ02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
+            D dJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
+            D dJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
+            D iz2 = iz * iz, iz3 = iz2 * iz;
+            dmc[2] += -dJ00 * fx * iz2 - dJ11 * fy * iz2 + D(2) * dJ02 * fx * S.tx * iz3 + D(2) * dJ12 * fy * S.ty * iz3;
+            D dtx = -dJ02 * fx * iz2, dty = -dJ12 * fy * iz2;
             if (!S.clx) dmc[0] += dtx; else dmc[2] += dtx * S.tx * iz;
             if (!S.cly) dmc[1] += dty; else dmc[2] += dty * S.ty * iz;
         }
         // depth coefficients: beta = (Qp0)_xy / (A f), gam = Q_xy / (A f f), z0 = mc.z
         {
-            float iA = S.iA;
-            float bx = S.Qp0x * iA / fx, by = S.Qp0y * iA / fy;
-            float gA = S.Q00 * iA / (fx * fx), gB = S.Q01 * iA / (fx * fy), gC = S.Q11 * iA / (fy * fy);
-            float dbx = g2.x, dby = g2.y, dgA = g2.z, dgB = g2.w, dgC = g3.x;
-            float dA = -iA * (dbx * bx + dby * by + dgA * gA + dgB * gB + dgC * gC);
-            float dQpx = dbx * iA / fx, dQpy = dby * iA / fy;
-            float dQ00 = dgA * iA / (fx * fx), dQ01 = dgB * iA / (fx * fy), dQ11 = dgC * iA / (fy * fy);
-            float dM[9];
-            for (int k = 0; k < 9; ++k) dM[k] = 0.f;
-            float dwv[3];
-            const float *M = S.M;
+            D iA = S.iA;
+            D bx = S.Qp0x * iA / fx, by = S.Qp0y * iA / fy;
+            D gA = S.Q00 * iA / (fx * fx), gB = S.Q01 * iA / (fx * fy), gC = S.Q11 * iA / (fy * fy);
+            D dbx = g2.x, dby = g2.y, dgA = g2.z, dgB = g2.w, dgC = g3.x;
+            D dA = -iA * (dbx * bx + dby * by + dgA * gA + dgB * gB + dgC * gC);
+            D dQpx = dbx * iA / fx, dQpy = dby * iA / fy;
+            D dQ00 = dgA * iA / (fx * fx), dQ01 = dgB * iA / (fx * fy), dQ11 = dgC * iA / (fy * fy);
+            D dM[9];
+            for (int k = 0; k < 9; ++k) dM[k] = D(0);
+            D dwv[3];
+            const D *M = S.M;
             for (int k = 0; k < 3; ++k) {
-                float e = G.is2[k], w = S.wv[k];
+                D e = G.is2[k], w = S.wv[k];
                 // A = sum_k wv_k^2 is2_k
-                dwv[k] = 2.f * dA * w * e;
+                dwv[k] = D(2) * dA * w * e;
                 dis2[k] += dA * w * w;
                 // Qp0_a = sum_k M_ak wv_k is2_k  (a = 0, 1)
-                float t = dQpx * M[k] + dQpy * M[3 + k];
+                D t = dQpx * M[k] + dQpy * M[3 + k];
                 dM[k] += dQpx * w * e;
                 dM[3 + k] += dQpy * w * e;
                 dwv[k] += t * e;
                 dis2[k] += t * w;
                 // Q00, Q01, Q11
-                dM[k] += 2.f * dQ00 * M[k] * e + dQ01 * M[3 + k] * e;
-                dM[3 + k] += 2.f * dQ11 * M[3 + k] * e + dQ01 * M[k] * e;
+                dM[k] += D(2) * dQ00 * M[k] * e + dQ01 * M[3 + k] * e;
+                dM[3 + k] += D(2) * dQ11 * M[3 + k] * e + dQ01 * M[k] * e;
                 dis2[k] += dQ00 * M[k] * M[k] + dQ01 * M[k] * M[3 + k] + dQ11 * M[3 + k] * M[3 + k];
             }
             // wv_k = sum_a M_ak p0_a
-            float dp0[2] = {0.f, 0.f};
+            D dp0[2] = {D(0), D(0)};
             for (int k = 0; k < 3; ++k) {
                 dM[k] += dwv[k] * S.p0[0];
                 dM[3 + k] += dwv[k] * S.p0[1];
@@ -441,26 +458,26 @@ __global__ void __launch_bounds__(kProjThreads) project_bwd_kernel(ugs_gaussians
     if (!loaded) return;
     // Sig = Rg S^2 Rg^T: with Mg = Rg S, dMg = 2 dSig Mg (full symmetric dSig)
     {
-        float D[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
+        D dS3[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
         for (int r = 0; r < 3; ++r)
             for (int q = 0; q < 3; ++q) {
-                float acc = 0.f;
-                for (int k = 0; k < 3; ++k) acc += D[3 * r + k] * G.Rg[3 * k + q];
-                float dMg = 2.f * acc * G.s[q];
+                D acc = D(0);
+                for (int k = 0; k < 3; ++k) acc += dS3[3 * r + k] * G.Rg[3 * k + q];
+                D dMg = D(2) * acc * G.s[q];
                 dRg[3 * r + q] += dMg * G.s[q];
                 ds[q] += G.Rg[3 * r + q] * dMg;
             }
     }
-    for (int k = 0; k < 3; ++k) ds[k] += dis2[k] * (-2.f) * G.is2[k] / G.s[k];
+    for (int k = 0; k < 3; ++k) ds[k] += dis2[k] * (-D(2)) * G.is2[k] / G.s[k];
     // rotation matrix -> unit quaternion -> quaternion
-    float w = G.qh[0], x = G.qh[1], y = G.qh[2], z = G.qh[3];
-    const float *d = dRg;
-    float gw = 2.f * (-z * d[1] + y * d[2] + z * d[3] - x * d[5] - y * d[6] + x * d[7]);
-    float gx = 2.f * (y * d[1] + z * d[2] + y * d[3] - 2.f * x * d[4] - w * d[5] + z * d[6] + w * d[7] - 2.f * x * d[8]);
-    float gy = 2.f * (-2.f * y * d[0] + x * d[1] + w * d[2] + x * d[3] + z * d[5] - w * d[6] + z * d[7] - 2.f * y * d[8]);
-    float gz = 2.f * (-2.f * z * d[0] - w * d[1] + x * d[2] + w * d[3] - 2.f * z * d[4] + y * d[5] + x * d[6] + y * d[7]);
-    float pq = gw * w + gx * x + gy * y + gz * z;
-    float iq = 1.f / G.qn;
+    D w = G.qh[0], x = G.qh[1], y = G.qh[2], z = G.qh[3];
+    const D *d = dRg;
+    D gw = D(2) * (-z * d[1] + y * d[2] + z * d[3] - x * d[5] - y * d[6] + x * d[7]);
+    D gx = D(2) * (y * d[1] + z * d[2] + y * d[3] - D(2) * x * d[4] - w * d[5] + z * d[6] + w * d[7] - D(2) * x * d[8]);
+    D gy = D(2) * (-D(2) * y * d[0] + x * d[1] + w * d[2] + x * d[3] + z * d[5] - w * d[6] + z * d[7] - D(2) * y * d[8]);
+    D gz = D(2) * (-D(2) * z * d[0] - w * d[1] + x * d[2] + w * d[3] - D(2) * z * d[4] + y * d[5] + x * d[6] + y * d[7]);
+    D pq = gw * w + gx * x + gy * y + gz * z;
+    D iq = D(1) / G.qn;
     dg.quat[i] += (gw - w * pq) * iq;
     dg.quat[N + i] += (gx - x * pq) * iq;
     dg.quat[2 * N + i] += (gy - y * pq) * iq;
@@ -469,7 +486,8 @@ __global__ void __launch_bounds__(kProjThreads) project_bwd_kernel(ugs_gaussians
         dg.mean[e * N + i] += dmu[e];
         dg.log_scale[e * N + i] += ds[e] * G.s[e];
     }
-    dg.opacity_logit[i] += dop * G.o * (1.f - G.o);
+    dg.opacity_logit[i] += dop * G.o * (D(1) - G.o);
+    dg.mask_logit[i] += dk * G.k * (D(1) - G.k);
     for (int c = 0; c < NC; ++c)
         for (int ch = 0; ch < 3; ++ch) dg.sh[((int64_t)c * 3 + ch) * N + i] += dsh[c][ch];
 }

@@ -40,6 +40,49 @@ __device__ __forceinline__ float wave_sum(float x)
 // Returns `s` in lane `lane` and `v` elsewhere.
 __device__ __forceinline__ float put_lane(float v, float s, int lane) { return __lane_id() == lane ? s : v; }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_add_sel(float a, float b, bool take_b)
+{
+    const float ta = dpp_step<CTRL, 0xf>(a);
+    const float tb = dpp_step<CTRL, 0xf>(b);
+    return take_b ? tb : ta;
+}
+
+// Transposed reduce-scatter over a wavefront: x[0..63] are 64 per-lane values;
+// on return lane l holds the sum over all 64 lanes of x[l].  Two cross-half
+// swap levels (v_permlane32_swap, v_permlane16_swap) halve the register count
+// at one swap and one add per register pair, then four DPP levels inside each
+// 16-lane row (rotate by 8, half mirror, quad permutes) finish with a select on
+// the lane's bit.  About 2.2 VALU instructions per value, against 7 for a
+// separate DPP tree per value.  All 64 lanes must be active.
+__device__ __forceinline__ float reduce_scatter64(float (&x)[64])
+{
+    const int lane = __lane_id();
+    float s[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[k]), __float_as_uint(x[k + 32]), false, false);
+        s[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    float u[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[k]), __float_as_uint(s[k + 16]), false, false);
+        u[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = dpp_add_sel<0x128>(u[k], u[k + 8], b3);  // row_ror:8
+    float w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = dpp_add_sel<0x141>(v[k], v[k + 4], b2);  // row_half_mirror
+    float y[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) y[k] = dpp_add_sel<0x4E>(w[k], w[k + 2], b1);   // quad_perm [2,3,0,1]
+    return dpp_add_sel<0xB1>(y[0], y[1], b0);                                    // quad_perm [1,0,3,2]
+}
+
 struct TileInfo {
     int v, px, py;
     bool inside;
@@ -187,10 +230,11 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
     const float *__restrict__ T_final, const uint32_t *__restrict__ n_contrib, const float *__restrict__ up_rgb,
     const float *__restrict__ gD_img, const float *__restrict__ up_kmap, const float *__restrict__ up_sem,
-    float *__restrict__ grec, float *__restrict__ dsem, float *__restrict__ dmask, int batch)
+    float *__restrict__ grec, float *__restrict__ dsem, int batch)
 {
     constexpr int NT = TW * TH;
     constexpr int CA = CO > 0 ? CO : 1;
+    constexpr int NGRP = (16 + CO + 63) / 64;
     extern __shared__ float4 smem[];
     __shared__ uint32_t s_max;
     float4 *srec = smem;
@@ -305,33 +349,25 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
                 v[0] = dm0;
                 v[1] = dm1;
             }
-            // reduce over the wavefront and scatter: lanes 0..15 own the record slots
-            float slot = 0.f;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                if (k == 6) continue;
-                slot = put_lane(slot, wave_sum(v[k]), k);
-            }
+            // per-fragment values: slots 0..15 are the gradient record (slot 6 the
+            // gradient factor), slots 16..16+C_o the semantic logits
+            v[6] = w * gK;
             const uint32_t id = vals[entry];
             const int64_t ridx = recbase + id;
-            if (lane < 16 && lane != 6) unsafeAtomicAdd(&grec[ridx * kRecFloats + lane], slot);
-            const float sk = wave_sum(w * gK);
-            if (lane == 0) {
-                const float k = r1.z;
-                unsafeAtomicAdd(&dmask[id], sk * k * (1.f - k));
-            }
-            if constexpr (CO > 0) {
-                float o0 = 0.f, o1 = 0.f;
 #pragma unroll
-                for (int c = 0; c < CO; ++c) {
-                    float sc = wave_sum(w * gO[c]);
-                    if (c < 64) o0 = put_lane(o0, sc, c);
-                    else o1 = put_lane(o1, sc, c - 64);
+            for (int grp = 0; grp < NGRP; ++grp) {
+                float x[64];
+#pragma unroll
+                for (int q = 0; q < 64; ++q) {
+                    const int slot = grp * 64 + q;
+                    if (slot < 16) x[q] = v[slot];
+                    else if (slot - 16 < CO) x[q] = w * gO[slot - 16];
+                    else x[q] = 0.f;
                 }
-                if (lane < C_o) unsafeAtomicAdd(&dsem[(int64_t)id * C_o + lane], o0);
-                if constexpr (CO > 64) {
-                    if (lane + 64 < C_o) unsafeAtomicAdd(&dsem[(int64_t)id * C_o + 64 + lane], o1);
-                }
+                const float tot = reduce_scatter64(x);
+                const int slot = grp * 64 + lane;
+                if (slot < 16) unsafeAtomicAdd(&grec[ridx * kRecFloats + slot], tot);
+                else if (slot - 16 < C_o) unsafeAtomicAdd(&dsem[(int64_t)id * C_o + (slot - 16)], tot);
             }
         }
         end = start;
@@ -367,7 +403,7 @@ hipError_t bwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
     auto gd = (const float *)(ws + L.gd);
     hipLaunchKernelGGL((render_bwd_kernel<TW, TH, CO>), dim3((unsigned)pb.total_tiles), dim3(TW * TH), lds, s, cams,
                        pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out.T_final, out.n_contrib, up.rgb, gd,
-                       up.kmap, up.sem, grec, dg.sem, dg.mask_logit, batch);
+                       up.kmap, up.sem, grec, dg.sem, batch);
     return hipGetLastError();
 }
 

@@ -40,7 +40,7 @@ struct DevCam {
 //   Cq = gam.a dx^2 + 2 gam.b dx dy + gam.c dy^2.
 // The per-view gradient record has the same 16 slots:
 //   g0 = (d mean2d.x, d mean2d.y, d conic.a, d conic.b)
-//   g1 = (d conic.c, d opacity, -, d z0)
+//   g1 = (d conic.c, d opacity, d k, d z0)
 //   g2 = (d beta.x, d beta.y, d gam.a, d gam.b)
 //   g3 = (d gam.c, d rgb.r, d rgb.g, d rgb.b)
 constexpr int kRecFloats = 16;

@@ -394,8 +394,9 @@ class Rasterizer:
 
     def autotune(self, g, cams, out, up, grads):
         P = self.project_and_sort(g, cams)
-        # the smallest tile needs the most pairs: leave room for it
-        self.ensure_workspace(g, cams, max(int(P * 3.0) + 4096, self.pair_cap))
+        # the smallest tile needs the most pairs: leave room for it (candidates
+        # that still overflow are skipped by the library)
+        self.ensure_workspace(g, cams, max(int(P * 4.0) + 4096, self.pair_cap))
         chosen = ugs_options()
         ms = C.c_float()
         rc = lib().ugs_autotune(self.ctx, C.byref(make_gaussians(g)), make_cameras(cams), len(cams), self.ws_ptr,
