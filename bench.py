@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", default=None, help="force a tile shape, e.g. 16x16")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the rasterizer's multi-GPU form (views sharded "
@@ -151,6 +153,13 @@ def main():
     Px = sum(c["W"] * c["H"] for c in cams)
     ups = scenes.upstream(cams, C_o, seed=1000 * wl)
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     g = U.to_device(g_np)
     cat = lambda k: torch.from_numpy(np.concatenate([u[k].reshape(-1) for u in ups])).cuda()
     up = dict(rgb=cat("rgb"), depth=cat("depth"), kmap=cat("kmap"), normal=cat("normal"),

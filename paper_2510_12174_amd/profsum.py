@@ -1,0 +1,77 @@
+"""Condenses rocprofv3 CSV output into the short text summaries kept under
+profiles/ (kernel-trace statistics, and HBM bytes per dispatch from FETCH_SIZE /
+WRITE_SIZE counter runs scaled by a plain copy kernel of known size).
+
+  python -m paper_2510_12174_amd.profsum stats <kernel_stats.csv> <command>
+  python -m paper_2510_12174_amd.profsum traffic <fetch counter csv> <write counter csv> \
+        <kernel substring> <key> <source file> <command>
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 1 << 30  # the calibration copy moves 1 GiB each way
+
+
+def _short(name, n=90):
+    name = name.replace("void ugs::(anonymous namespace)::", "").replace("ugs::(anonymous namespace)::", "")
+    return name if len(name) <= n else name[:n] + "..."
+
+
+def stats(path, command):
+    rows = list(csv.DictReader(open(path)))
+    out = [f"# rocprofv3 kernel-trace statistics", f"# command: {command}", "",
+           f"{'calls':>6} {'avg_ms':>10} {'total_ms':>10} {'pct':>6}  kernel"]
+    for r in sorted(rows, key=lambda r: -float(r.get("TotalDurationNs", 0))):
+        out.append(f"{int(r['Calls']):>6} {float(r['AverageNs']) / 1e6:>10.4f} {float(r['TotalDurationNs']) / 1e6:>10.3f} "
+                   f"{float(r.get('Percentage', 0)):>6.2f}  {_short(r['Name'])}")
+    return "\n".join(out) + "\n"
+
+
+def _per_kernel(path, counter):
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") != counter:
+            continue
+        k = r["Kernel_Name"]
+        key = (k, r.get("Dispatch_Id"))
+        acc.setdefault(k, {})
+        acc[k][key] = acc[k].get(key, 0.0) + float(r["Counter_Value"])
+    return {k: list(v.values()) for k, v in acc.items()}
+
+
+def traffic(fetch_csv, write_csv, kernel_sub, key, source, command):
+    f = _per_kernel(fetch_csv, "FETCH_SIZE")
+    w = _per_kernel(write_csv, "WRITE_SIZE")
+    copy_k = [k for k in f if "copy" in k.lower() or "elementwise" in k.lower()]
+    big = lambda d, k: max(d.get(k, [0.0]))
+    cf = max((big(f, k) for k in copy_k), default=0.0)       # KiB read by the 1 GiB copy
+    cw = max((big(w, k) for k in copy_k if k in w), default=0.0)
+    fs = COPY_BYTES / (cf * 1024) if cf else 1.0
+    ws = COPY_BYTES / (cw * 1024) if cw else 1.0
+    ks = [k for k in f if kernel_sub in k]
+    fk = [x for k in ks for x in f[k]]
+    wk = [x for k in ks for x in w.get(k, [])]
+    fb = sum(fk) / len(fk) * 1024 * fs if fk else None
+    wb = sum(wk) / len(wk) * 1024 * ws if wk else None
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2510_12174_amd", "csrc", source), "rb").read()).hexdigest()[:16]
+    entry = dict(source_sha=sha, fetch_bytes=fb, write_bytes=wb,
+                 bytes_per_launch=(fb or 0) + (wb or 0), copy_scale=dict(fetch=fs, write=ws),
+                 dispatches=len(fk), command=command)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    d = json.load(open(path)) if os.path.exists(path) else {}
+    d[key] = entry
+    json.dump(d, open(path, "w"), indent=1, sort_keys=True)
+    return entry
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        sys.stdout.write(stats(sys.argv[2], sys.argv[3]))
+    elif sys.argv[1] == "traffic":
+        print(json.dumps(traffic(*sys.argv[2:8]), indent=1))
