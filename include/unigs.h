@@ -204,7 +204,8 @@ int ugs_time_stage(ugs_ctx *ctx, int stage, void *ev_start, void *ev_stop);
  *   1 tile rectangles, uint32[V*N][2] = (tx0 | ty0 << 16, tx1 | ty1 << 16),
  *     half-open, project;
  *   2 tiles touched, uint32[V*N], project;
- *   3 sorted keys, uint64[P] = (global tile << 32) | depth bits, bin_sort;
+ *   3 sorted keys, uint32[P] = global tile id (each tile's run is in (depth,
+ *     index) order), bin_sort;
  *   4 sorted values (Gaussian index), uint32[P], bin_sort;
  *   5 tile ranges, uint32[total tiles][2] = [start, end), bin_sort;
  *   6 per-view gradient records, float[V*N][16], render_bwd;

@@ -200,9 +200,8 @@ WsLayout make_layout(const Problem &pb, int64_t pair_cap)
     L.pair_cap = pair_cap;
     L.nb_scan = (int)((L.VN + kScanBlock - 1) / kScanBlock);
     if (L.nb_scan < 1) L.nb_scan = 1;
-    L.nb_sort = kSortBlocks;
-    int bits = 32 + bit_length((uint64_t)(pb.total_tiles > 0 ? pb.total_tiles - 1 : 0));
-    L.sort_passes = (bits + 7) / 8;
+    L.depth_bits = 32 + bit_length((uint64_t)(pb.V > 0 ? pb.V - 1 : 0));
+    L.tile_bits = bit_length((uint64_t)(pb.total_tiles > 0 ? pb.total_tiles - 1 : 0));
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -216,10 +215,16 @@ WsLayout make_layout(const Problem &pb, int64_t pair_cap)
     L.grec = take(VN * 64);
     L.rect = take(VN * 8);
     L.touched = take(VN * 4);
-    L.offs = take(VN * 4);
+    L.voff = take(VN * 4);
+    L.poff = take(VN * 4);
+    L.tsorted = take(VN * 4);
+    L.dkey0 = take(VN * 8);
+    L.dkey1 = take(VN * 8);
+    L.didx0 = take(VN * 4);
+    L.didx1 = take(VN * 4);
     L.scan_part = take((size_t)L.nb_scan * 4);
-    L.keys0 = take(P * 8);
-    L.keys1 = take(P * 8);
+    L.keys0 = take(P * 4);
+    L.keys1 = take(P * 4);
     L.vals0 = take(P * 4);
     L.vals1 = take(P * 4);
     L.hist = take((size_t)256 * kSortBlocks * 4);
@@ -308,7 +313,7 @@ int do_project(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, int
     // pair capacity: what fits in the rest of the workspace
     WsLayout L0 = make_layout(pb, 0);
     if (ws_bytes < L0.total) return UGS_ERR_INVALID_ARG;
-    int64_t cap = (int64_t)((ws_bytes - L0.total) / 24);
+    int64_t cap = (int64_t)((ws_bytes - L0.total) / 16);
     while (cap > 0 && make_layout(pb, cap).total > ws_bytes) cap -= 64;
     if (cap < 0) cap = 0;
     if (cap > 0x7fffffffll) cap = 0x7fffffffll;
@@ -802,7 +807,7 @@ int ugs_debug_buffer(ugs_ctx *ctx, void *ws, int which, void *stream, void **dev
         DevCounters c;
         int rc = read_counters(ctx, ws, (hipStream_t)stream, &c);
         if (rc) return rc;
-        *count = c.overflow ? 0 : (int64_t)c.P;
+        *count = (int64_t)c.P_eff;
         *dev_ptr = b + (which == 3 ? (ctx->final_buf ? L.keys1 : L.keys0) : (ctx->final_buf ? L.vals1 : L.vals0));
         return UGS_OK;
     }

@@ -1,12 +1,18 @@
-// Stages S2-S4: tile binning, (tile, depth) key sort and per-tile ranges.
+// Stages S2-S4: tile binning, (tile, depth) ordering and per-tile ranges.
 //
-// The pair count P stays on the device: every kernel after the scan reads it
-// from the counters block and uses a fixed grid, so the whole sequence can be
-// captured in a HIP graph.  The sort is a stable least-significant-digit radix
-// sort (8-bit digits) over only the key bits in use (32 depth bits plus the
-// bits of the largest global tile id).  Because pairs are emitted in increasing
-// Gaussian index within a view and every pass is stable, equal (tile, depth)
-// keys stay in index order: the result is the unique (tile, depth, index) order.
+// Order of work:
+//   1. compact the visible (view, Gaussian) records (tiles touched > 0);
+//   2. sort them by (view, camera depth) -- a stable LSD radix sort over the
+//      depth bits and the view bits of a 64-bit key, on ~R records only;
+//   3. scan their tile counts in that order and emit one (tile, index) pair per
+//      covered tile: pairs come out in (view, depth, index) order;
+//   4. stable LSD radix sort of the pairs by global tile id (32-bit keys, only
+//      the bits in use: two 8-bit passes up to 65,536 tiles);
+//   5. per-tile [start, end) ranges.
+// Because every sort pass is stable and the compaction keeps index order, each
+// tile's list ends up in the unique (depth bits, index) order.  The pair count
+// stays on the device: every kernel after the scans reads it from the counters
+// block and uses a fixed grid, so the whole sequence can be captured in a graph.
 #include "ugs_internal.h"
 
 namespace ugs {
@@ -39,22 +45,36 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t *lds
     return pre + inc - x;
 }
 
-__global__ void __launch_bounds__(kScanThreads) scan_reduce(const uint32_t *__restrict__ in, int64_t n,
-                                                          uint32_t *__restrict__ part)
+// Scan input: element i of `in` (0 beyond the device count), or its flag (> 0).
+struct ScanIn {
+    const uint32_t *in;
+    int64_t n;                // host bound (grid size)
+    const uint32_t *n_dev;    // optional device bound
+    int flag;                 // 1: scan (in[i] > 0), 0: scan in[i]
+    __device__ __forceinline__ uint32_t at(int64_t i) const
+    {
+        if (i >= n || (n_dev && i >= (int64_t)*n_dev)) return 0u;
+        uint32_t v = in[i];
+        return flag ? (v > 0u ? 1u : 0u) : v;
+    }
+};
+
+__global__ void __launch_bounds__(kScanThreads) scan_reduce(ScanIn si, uint32_t *__restrict__ part)
 {
     __shared__ uint32_t lds4[4];
     int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
     uint32_t s = 0;
-    for (int k = 0; k < 4; ++k)
-        if (base + k < n) s += in[base + k];
+    for (int k = 0; k < 4; ++k) s += si.at(base + k);
     uint32_t tot;
     block_excl_scan256(s, lds4, tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// Single block: exclusive scan of the block partials; stores P and the overflow flag.
+// Single block: exclusive scan of the block partials.  Stores the total in
+// *total; with cap >= 0 also the overflow flag and the usable count.
 __global__ void __launch_bounds__(1024) scan_top(uint32_t *__restrict__ part, int nb, int64_t cap,
-                                                 DevCounters *__restrict__ cnt)
+                                                 uint32_t *__restrict__ total, uint32_t *__restrict__ overflow,
+                                                 uint32_t *__restrict__ usable, DevCounters *__restrict__ cnt_reset)
 {
     __shared__ unsigned long long lds[16];
     const int t = threadIdx.x, lane = __lane_id(), wave = t >> 6;
@@ -84,80 +104,112 @@ __global__ void __launch_bounds__(1024) scan_top(uint32_t *__restrict__ part, in
             run += v;
         }
     if (t == 0) {
-        bool over = tot > (unsigned long long)cap;
-        cnt->P = (uint32_t)(tot < 0xffffffffull ? tot : 0xffffffffull);
-        cnt->overflow = over ? 1u : 0u;
-        cnt->n_eval = 0;
-        cnt->n_contrib = 0;
+        *total = (uint32_t)(tot < 0xffffffffull ? tot : 0xffffffffull);
+        if (overflow) {
+            bool over = tot > (unsigned long long)cap;
+            *overflow = over ? 1u : 0u;
+            *usable = over ? 0u : (uint32_t)tot;
+        }
+        if (cnt_reset) {
+            cnt_reset->n_eval = 0;
+            cnt_reset->n_contrib = 0;
+        }
     }
 }
 
-__global__ void __launch_bounds__(kScanThreads) scan_down(const uint32_t *__restrict__ in, int64_t n,
-                                                        const uint32_t *__restrict__ part,
+__global__ void __launch_bounds__(kScanThreads) scan_down(ScanIn si, const uint32_t *__restrict__ part,
                                                         uint32_t *__restrict__ out)
 {
     __shared__ uint32_t lds4[4];
     int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
     uint32_t v[4], s = 0;
     for (int k = 0; k < 4; ++k) {
-        v[k] = base + k < n ? in[base + k] : 0u;
+        v[k] = si.at(base + k);
         s += v[k];
     }
     uint32_t tot;
     uint32_t ex = block_excl_scan256(s, lds4, tot) + part[blockIdx.x];
     for (int k = 0; k < 4; ++k) {
-        if (base + k < n) out[base + k] = ex;
+        if (base + k < si.n) out[base + k] = ex;
         ex += v[k];
     }
 }
 
-// One thread per (view, Gaussian): writes its pairs at its scanned offset.
-__global__ void __launch_bounds__(256) emit_pairs(const DevCam *__restrict__ cams, int64_t N, int64_t VN,
-                                                  const uint32_t *__restrict__ touched,
-                                                  const uint32_t *__restrict__ offs, const uint2 *__restrict__ rect,
-                                                  const float4 *__restrict__ rec, int64_t cap,
-                                                  const DevCounters *__restrict__ cnt,
-                                                  unsigned long long *__restrict__ keys, uint32_t *__restrict__ vals)
+// Visible records -> (view << 32 | depth bits, record index), in index order.
+__global__ void __launch_bounds__(256) compact_visible(int64_t N, int64_t VN, const uint32_t *__restrict__ touched,
+                                                       const uint32_t *__restrict__ voff,
+                                                       const float4 *__restrict__ rec,
+                                                       unsigned long long *__restrict__ dkey,
+                                                       uint32_t *__restrict__ didx)
 {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= VN) return;
-    const uint32_t nt = touched[idx];
-    if (nt == 0 || cnt->overflow) return;
-    const uint64_t off = offs[idx];
-    if (off + nt > (uint64_t)cap) return;
-    const int v = (int)(idx / N);
-    const uint32_t gid = (uint32_t)(idx - (int64_t)v * N);
-    const DevCam &cam = cams[v];
-    const uint2 rc = rect[idx];
-    const int tx0 = rc.x & 0xffff, ty0 = rc.x >> 16, tx1 = rc.y & 0xffff, ty1 = rc.y >> 16;
-    const uint32_t dbits = __float_as_uint(rec[idx * 4 + 1].w);
-    uint64_t o = off;
-    for (int ty = ty0; ty < ty1; ++ty)
-        for (int tx = tx0; tx < tx1; ++tx) {
-            uint64_t tile = cam.tile_base + (uint32_t)(ty * cam.tiles_x + tx);
-            keys[o] = (tile << 32) | dbits;
-            vals[o] = gid;
-            ++o;
-        }
+    if (idx >= VN || touched[idx] == 0) return;
+    const uint32_t r = voff[idx];
+    const uint64_t view = (uint64_t)(idx / N);
+    dkey[r] = (view << 32) | __float_as_uint(rec[idx * 4 + 1].w);
+    didx[r] = (uint32_t)idx;
 }
 
-__device__ __forceinline__ uint32_t pair_count(const DevCounters *cnt) { return cnt->overflow ? 0u : cnt->P; }
+// Tile counts in depth order (grid-stride up to the device count R).
+__global__ void __launch_bounds__(256) gather_counts(const uint32_t *__restrict__ didx,
+                                                     const uint32_t *__restrict__ touched,
+                                                     const uint32_t *__restrict__ R, uint32_t *__restrict__ out)
+{
+    const uint32_t n = *R;
+    for (uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (uint64_t)gridDim.x * 256)
+        out[r] = touched[didx[r]];
+}
+
+// One thread per depth-sorted record: its pairs at its scanned offset.
+__global__ void __launch_bounds__(256) emit_pairs(const DevCam *__restrict__ cams, int64_t N,
+                                                  const uint32_t *__restrict__ didx,
+                                                  const uint32_t *__restrict__ tsorted,
+                                                  const uint32_t *__restrict__ poff, const uint2 *__restrict__ rect,
+                                                  int64_t cap, const DevCounters *__restrict__ cnt,
+                                                  uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    if (cnt->overflow) return;
+    const uint32_t R = cnt->R;
+    for (uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x; r < R; r += (uint64_t)gridDim.x * 256) {
+        const uint32_t nt = tsorted[r];
+        const uint64_t off = poff[r];
+        if (nt == 0 || off + nt > (uint64_t)cap) continue;
+        const uint32_t idx = didx[r];
+        const int v = (int)(idx / (uint64_t)N);
+        const uint32_t gid = (uint32_t)(idx - (uint64_t)v * N);
+        const DevCam &cam = cams[v];
+        const uint2 rc = rect[idx];
+        const int tx0 = rc.x & 0xffff, ty0 = rc.x >> 16, tx1 = rc.y & 0xffff, ty1 = rc.y >> 16;
+        uint64_t o = off;
+        for (int ty = ty0; ty < ty1; ++ty) {
+            const uint32_t row = cam.tile_base + (uint32_t)(ty * cam.tiles_x);
+            for (int tx = tx0; tx < tx1; ++tx) {
+                keys[o] = row + (uint32_t)tx;
+                vals[o] = gid;
+                ++o;
+            }
+        }
+    }
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift)
+{
+    return (uint32_t)(key >> shift) & 255u;
+}
 
 // Per-block digit histogram of the block's contiguous chunk.
-__global__ void __launch_bounds__(kSortThreads) radix_hist(const unsigned long long *__restrict__ keys,
-                                                           const DevCounters *__restrict__ cnt, int shift,
-                                                           uint32_t *__restrict__ hist)
+template <typename K>
+__global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__ keys, const uint32_t *__restrict__ n_dev,
+                                                           int shift, uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const uint32_t P = pair_count(cnt);
+    const uint32_t P = *n_dev;
     const uint32_t per = ((P + kSortBlocks - 1) / kSortBlocks + 255) & ~255u;
     const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = min((uint64_t)P, b0 + per);
-    for (uint64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) {
-        uint32_t d = (uint32_t)(keys[i] >> shift) & 255u;
-        atomicAdd(&h[d], 1u);
-    }
+    for (uint64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) atomicAdd(&h[digit_of(keys[i], shift)], 1u);
     __syncthreads();
     hist[threadIdx.x * kSortBlocks + blockIdx.x] = h[threadIdx.x];
 }
@@ -185,30 +237,32 @@ __global__ void __launch_bounds__(kSortThreads) radix_scan_digit(uint32_t *__res
 // Stable scatter: each block walks its chunk in order, 256 keys at a time; ranks
 // within a wave come from eight ballots (lanes sharing the digit), ranks across
 // waves and tiles from per-digit running counters in LDS.
-__global__ void __launch_bounds__(kSortThreads) radix_scatter(
-    const unsigned long long *__restrict__ kin, const uint32_t *__restrict__ vin, unsigned long long *__restrict__ kout,
-    uint32_t *__restrict__ vout, const DevCounters *__restrict__ cnt, int shift, const uint32_t *__restrict__ hist,
-    const uint32_t *__restrict__ digit_tot)
+template <typename K>
+__global__ void __launch_bounds__(kSortThreads) radix_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                              K *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                              const uint32_t *__restrict__ n_dev, int shift,
+                                                              const uint32_t *__restrict__ hist,
+                                                              const uint32_t *__restrict__ digit_tot)
 {
     __shared__ uint32_t base[256], run[256], lds4[4];
     __shared__ uint32_t wcnt[4][256], wpre[4][256];
-    const int t = threadIdx.x, lane = __lane_id(), wave = t >> 6;
+    const int t = threadIdx.x, wave = t >> 6;
     uint32_t dt = digit_tot[t], tot;
     uint32_t dex = block_excl_scan256(dt, lds4, tot);
     base[t] = dex + hist[t * kSortBlocks + blockIdx.x];
     run[t] = 0;
     for (int w = 0; w < 4; ++w) wcnt[w][t] = 0;
     __syncthreads();
-    const uint32_t P = pair_count(cnt);
+    const uint32_t P = *n_dev;
     const uint32_t per = ((P + kSortBlocks - 1) / kSortBlocks + 255) & ~255u;
     const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = min((uint64_t)P, b0 + per);
     const uint64_t lt = __lanemask_lt();
     for (uint64_t tb = b0; tb < b1; tb += kSortThreads) {
         const uint64_t i = tb + t;
         const bool valid = i < b1;
-        unsigned long long key = valid ? kin[i] : 0ull;
-        uint32_t val = valid ? vin[i] : 0u;
-        uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const K key = valid ? kin[i] : K(0);
+        const uint32_t val = valid ? vin[i] : 0u;
+        const uint32_t d = digit_of(key, shift);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -237,20 +291,49 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(
     }
 }
 
-__global__ void __launch_bounds__(256) tile_ranges(const unsigned long long *__restrict__ keys,
-                                                   const DevCounters *__restrict__ cnt, uint2 *__restrict__ ranges)
+__global__ void __launch_bounds__(256) tile_ranges(const uint32_t *__restrict__ keys,
+                                                   const uint32_t *__restrict__ n_dev, uint2 *__restrict__ ranges)
 {
-    const uint32_t P = pair_count(cnt);
+    const uint32_t P = *n_dev;
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (uint64_t)gridDim.x * 256) {
-        uint32_t tile = (uint32_t)(keys[i] >> 32);
-        if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != tile) ranges[tile].x = (uint32_t)i;
-        if (i + 1 == P || (uint32_t)(keys[i + 1] >> 32) != tile) ranges[tile].y = (uint32_t)(i + 1);
+        uint32_t tile = keys[i];
+        if (i == 0 || keys[i - 1] != tile) ranges[tile].x = (uint32_t)i;
+        if (i + 1 == P || keys[i + 1] != tile) ranges[tile].y = (uint32_t)(i + 1);
     }
 }
 
 __global__ void __launch_bounds__(256) fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
+void scan(const ScanIn &si, int nb, uint32_t *part, uint32_t *out, int64_t cap, uint32_t *total, uint32_t *overflow,
+          uint32_t *usable, DevCounters *reset, hipStream_t s)
+{
+    hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, si, part);
+    hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, part, nb, cap, total, overflow, usable, reset);
+    hipLaunchKernelGGL(scan_down, dim3(nb), dim3(kScanThreads), 0, s, si, (const uint32_t *)part, out);
+}
+
+// Sorts (keys, vals) in place over bits [0, bits); returns the buffer index
+// (0: k0/v0, 1: k1/v1) holding the result.
+template <typename K>
+int radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t *n_dev, int bits, uint32_t *hist,
+               uint32_t *dtot, hipStream_t s)
+{
+    K *k[2] = {k0, k1};
+    uint32_t *v[2] = {v0, v1};
+    int cur = 0;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(radix_hist<K>, dim3(kSortBlocks), dim3(kSortThreads), 0, s, (const K *)k[cur], n_dev, shift,
+                           hist);
+        hipLaunchKernelGGL(radix_scan_digit, dim3(256), dim3(kSortThreads), 0, s, hist, dtot);
+        hipLaunchKernelGGL(radix_scatter<K>, dim3(kSortBlocks), dim3(kSortThreads), 0, s, (const K *)k[cur],
+                           (const uint32_t *)v[cur], k[cur ^ 1], v[cur ^ 1], n_dev, shift, (const uint32_t *)hist,
+                           (const uint32_t *)dtot);
+        cur ^= 1;
+    }
+    return cur;
 }
 
 }  // namespace
@@ -268,36 +351,47 @@ hipError_t launch_binsort(const Problem &pb, const WsLayout &L, char *ws, hipStr
 {
     auto cams = (const DevCam *)(ws + L.cams);
     auto touched = (uint32_t *)(ws + L.touched);
-    auto offs = (uint32_t *)(ws + L.offs);
+    auto voff = (uint32_t *)(ws + L.voff);
+    auto poff = (uint32_t *)(ws + L.poff);
+    auto tsorted = (uint32_t *)(ws + L.tsorted);
     auto part = (uint32_t *)(ws + L.scan_part);
     auto cnt = (DevCounters *)(ws + L.counters);
     auto rect = (const uint2 *)(ws + L.rect);
     auto rec = (const float4 *)(ws + L.rec);
-    unsigned long long *keys[2] = {(unsigned long long *)(ws + L.keys0), (unsigned long long *)(ws + L.keys1)};
-    uint32_t *vals[2] = {(uint32_t *)(ws + L.vals0), (uint32_t *)(ws + L.vals1)};
+    auto dk0 = (unsigned long long *)(ws + L.dkey0), dk1 = (unsigned long long *)(ws + L.dkey1);
+    auto di0 = (uint32_t *)(ws + L.didx0), di1 = (uint32_t *)(ws + L.didx1);
+    auto k0 = (uint32_t *)(ws + L.keys0), k1 = (uint32_t *)(ws + L.keys1);
+    auto v0 = (uint32_t *)(ws + L.vals0), v1 = (uint32_t *)(ws + L.vals1);
     auto hist = (uint32_t *)(ws + L.hist);
     auto dtot = (uint32_t *)(ws + L.digit_tot);
     auto ranges = (uint2 *)(ws + L.ranges);
     const int64_t VN = L.VN;
+    const unsigned vn_blocks = (unsigned)((VN + 255) / 256 > 0 ? (VN + 255) / 256 : 1);
+    const unsigned gs_blocks = vn_blocks < 8192 ? vn_blocks : 8192;
     hipError_t e;
-    hipLaunchKernelGGL(scan_reduce, dim3(L.nb_scan), dim3(kScanThreads), 0, s, touched, VN, part);
-    hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, part, L.nb_scan, L.pair_cap, cnt);
-    if (VN > 0) {
-        hipLaunchKernelGGL(scan_down, dim3(L.nb_scan), dim3(kScanThreads), 0, s, touched, VN, part, offs);
-        hipLaunchKernelGGL(emit_pairs, dim3((unsigned)((VN + 255) / 256)), dim3(256), 0, s, cams, L.N, VN, touched,
-                           offs, rect, rec, L.pair_cap, cnt, keys[0], vals[0]);
-    }
-    int cur = 0;
-    for (int pass = 0; pass < L.sort_passes; ++pass) {
-        int shift = 8 * pass;
-        hipLaunchKernelGGL(radix_hist, dim3(kSortBlocks), dim3(kSortThreads), 0, s, keys[cur], cnt, shift, hist);
-        hipLaunchKernelGGL(radix_scan_digit, dim3(256), dim3(kSortThreads), 0, s, hist, dtot);
-        hipLaunchKernelGGL(radix_scatter, dim3(kSortBlocks), dim3(kSortThreads), 0, s, keys[cur], vals[cur],
-                           keys[cur ^ 1], vals[cur ^ 1], cnt, shift, hist, dtot);
-        cur ^= 1;
-    }
+
+    // 1. compact visible records
+    scan(ScanIn{touched, VN, nullptr, 1}, L.nb_scan, part, voff, -1, &cnt->R, nullptr, nullptr, cnt, s);
+    if (VN > 0)
+        hipLaunchKernelGGL(compact_visible, dim3(vn_blocks), dim3(256), 0, s, L.N, VN, (const uint32_t *)touched,
+                           (const uint32_t *)voff, rec, dk0, di0);
+    // 2. sort by (view, depth)
+    const int dcur = radix_sort<unsigned long long>(dk0, di0, dk1, di1, &cnt->R, L.depth_bits, hist, dtot, s);
+    uint32_t *didx = dcur ? di1 : di0;
+    // 3. tile counts in depth order, pair offsets, emission
+    hipLaunchKernelGGL(gather_counts, dim3(gs_blocks), dim3(256), 0, s, (const uint32_t *)didx,
+                       (const uint32_t *)touched, (const uint32_t *)&cnt->R, tsorted);
+    scan(ScanIn{tsorted, VN, &cnt->R, 0}, L.nb_scan, part, poff, L.pair_cap, &cnt->P, &cnt->overflow, &cnt->P_eff,
+         nullptr, s);
+    hipLaunchKernelGGL(emit_pairs, dim3(gs_blocks), dim3(256), 0, s, cams, L.N, (const uint32_t *)didx,
+                       (const uint32_t *)tsorted, (const uint32_t *)poff, rect, L.pair_cap,
+                       (const DevCounters *)cnt, k0, v0);
+    // 4. stable sort of the pairs by tile
+    const int cur = radix_sort<uint32_t>(k0, v0, k1, v1, &cnt->P_eff, L.tile_bits, hist, dtot, s);
+    // 5. ranges
     if ((e = launch_fill_u32((uint32_t *)ranges, 0u, 2 * L.total_tiles, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(tile_ranges, dim3(4096), dim3(256), 0, s, keys[cur], cnt, ranges);
+    hipLaunchKernelGGL(tile_ranges, dim3(4096), dim3(256), 0, s, (const uint32_t *)(cur ? k1 : k0),
+                       (const uint32_t *)&cnt->P_eff, ranges);
     *final_buf = cur;
     return hipGetLastError();
 }

@@ -81,9 +81,10 @@ __device__ __forceinline__ void normal_state(const float *D, const DevCam &cam, 
 }
 
 template <int TW, int TH>
-__device__ __forceinline__ bool pixel_of(const DevCam *cams, int V, int &view, int &u, int &v)
+__device__ __forceinline__ bool pixel_of(const DevCam *cams, int V, uint32_t ntiles, int &view, int &u, int &v)
 {
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+    if (tile >= ntiles) return false;
     view = view_of_tile(cams, V, tile);
     const DevCam &cam = cams[view];
     const uint32_t lt = tile - cam.tile_base;
@@ -93,12 +94,12 @@ __device__ __forceinline__ bool pixel_of(const DevCam *cams, int V, int &view, i
 }
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW *TH) normal_fwd_kernel(const DevCam *__restrict__ cams, int V,
+__global__ void __launch_bounds__(TW *TH) normal_fwd_kernel(const DevCam *__restrict__ cams, int V, uint32_t ntiles,
                                                            const float *__restrict__ depth, float *__restrict__ normal,
                                                            int s1, int s2, float lam, int orient)
 {
     int view, u, v;
-    if (!pixel_of<TW, TH>(cams, V, view, u, v)) return;
+    if (!pixel_of<TW, TH>(cams, V, ntiles, view, u, v)) return;
     const DevCam &cam = cams[view];
     const int64_t HW = (int64_t)cam.W * cam.H, p = (int64_t)v * cam.W + u;
     NState S;
@@ -117,14 +118,14 @@ __global__ void __launch_bounds__(TW *TH) normal_fwd_kernel(const DevCam *__rest
 
 // Pass 1: adjoints of (vx1, vy1, vx2, vy2) in the camera frame, planar [12][pixels].
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW *TH) normal_adj_kernel(const DevCam *__restrict__ cams, int V,
+__global__ void __launch_bounds__(TW *TH) normal_adj_kernel(const DevCam *__restrict__ cams, int V, uint32_t ntiles,
                                                            const float *__restrict__ depth,
                                                            const float *__restrict__ dnormal, int64_t total_pix,
                                                            float *__restrict__ adj, int s1, int s2, float lam,
                                                            int orient)
 {
     int view, u, v;
-    if (!pixel_of<TW, TH>(cams, V, view, u, v)) return;
+    if (!pixel_of<TW, TH>(cams, V, ntiles, view, u, v)) return;
     const DevCam &cam = cams[view];
     const int64_t HW = (int64_t)cam.W * cam.H, p = (int64_t)v * cam.W + u, gp = cam.pix_off + p;
     float out[12];
@@ -162,13 +163,13 @@ __global__ void __launch_bounds__(TW *TH) normal_adj_kernel(const DevCam *__rest
 // Pass 2: gather the stencil adjoints that reference this pixel and project on
 // dP/dD = R^T p; adds the direct depth gradient and writes G_D.
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW *TH) normal_gather_kernel(const DevCam *__restrict__ cams, int V,
+__global__ void __launch_bounds__(TW *TH) normal_gather_kernel(const DevCam *__restrict__ cams, int V, uint32_t ntiles,
                                                               const float *__restrict__ adj, int64_t total_pix,
                                                               const float *__restrict__ ddepth, float *__restrict__ gd,
                                                               int s1, int s2)
 {
     int view, u, v;
-    if (!pixel_of<TW, TH>(cams, V, view, u, v)) return;
+    if (!pixel_of<TW, TH>(cams, V, ntiles, view, u, v)) return;
     const DevCam &cam = cams[view];
     const int W = cam.W, H = cam.H;
     const int64_t base = cam.pix_off;
@@ -205,8 +206,8 @@ template <int TW, int TH>
 hipError_t nfwd(const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out, const ugs_options &o,
                 hipStream_t s)
 {
-    hipLaunchKernelGGL((normal_fwd_kernel<TW, TH>), dim3((unsigned)pb.total_tiles), dim3(TW * TH), 0, s,
-                       (const DevCam *)(ws + L.cams), pb.V, out.depth, out.normal, o.step1, o.step2, o.lambda,
+    hipLaunchKernelGGL((normal_fwd_kernel<TW, TH>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), 0, s,
+                       (const DevCam *)(ws + L.cams), pb.V, (uint32_t)pb.total_tiles, out.depth, out.normal, o.step1, o.step2, o.lambda,
                        o.orient_sign);
     return hipGetLastError();
 }
@@ -218,10 +219,10 @@ hipError_t nbwd(const Problem &pb, const WsLayout &L, char *ws, const ugs_output
     auto cams = (const DevCam *)(ws + L.cams);
     auto adj = (float *)(ws + L.nadj);
     auto gd = (float *)(ws + L.gd);
-    hipLaunchKernelGGL((normal_adj_kernel<TW, TH>), dim3((unsigned)pb.total_tiles), dim3(TW * TH), 0, s, cams, pb.V,
-                       out.depth, up.normal, pb.total_pix, adj, o.step1, o.step2, o.lambda, o.orient_sign);
-    hipLaunchKernelGGL((normal_gather_kernel<TW, TH>), dim3((unsigned)pb.total_tiles), dim3(TW * TH), 0, s, cams,
-                       pb.V, (const float *)adj, pb.total_pix, up.depth, gd, o.step1, o.step2);
+    hipLaunchKernelGGL((normal_adj_kernel<TW, TH>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), 0, s, cams, pb.V,
+                       (uint32_t)pb.total_tiles, out.depth, up.normal, pb.total_pix, adj, o.step1, o.step2, o.lambda, o.orient_sign);
+    hipLaunchKernelGGL((normal_gather_kernel<TW, TH>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), 0, s, cams,
+                       pb.V, (uint32_t)pb.total_tiles, (const float *)adj, pb.total_pix, up.depth, gd, o.step1, o.step2);
     return hipGetLastError();
 }
 

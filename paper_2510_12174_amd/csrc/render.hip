@@ -98,8 +98,11 @@ __device__ __forceinline__ TileInfo tile_info(const DevCam *cams, int V, uint32_
     const DevCam &cam = cams[ti.v];
     uint32_t lt = tile - cam.tile_base;
     int tx = (int)(lt % (uint32_t)cam.tiles_x), ty = (int)(lt / (uint32_t)cam.tiles_x);
-    ti.px = tx * TW + (int)(threadIdx.x % TW);
-    ti.py = ty * TH + (int)(threadIdx.x / TW);
+    // each wavefront covers a compact 8 x 8 (or 8-row) block of the tile
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    constexpr int WX = TW / 8;  // wavefronts per tile row
+    ti.px = tx * TW + (wave % WX) * 8 + (lane & 7);
+    ti.py = ty * TH + (wave / WX) * 8 + (lane >> 3);
     ti.inside = ti.px < cam.W && ti.py < cam.H;
     ti.HW = (int64_t)cam.W * cam.H;
     ti.pix = (int64_t)ti.py * cam.W + ti.px;
@@ -130,13 +133,14 @@ template <int TW, int TH, int CO>
 __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
-    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count)
+    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles)
 {
     constexpr int NT = TW * TH;
     extern __shared__ float4 smem[];
     float4 *srec = smem;
     float *ssem = (float *)(smem + 4 * batch);
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+    if (tile >= ntiles) return;
     const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
     const uint2 range = ranges[tile];
     const float fx = (float)ti.px, fy = (float)ti.py;
@@ -230,7 +234,7 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
     const float *__restrict__ T_final, const uint32_t *__restrict__ n_contrib, const float *__restrict__ up_rgb,
     const float *__restrict__ gD_img, const float *__restrict__ up_kmap, const float *__restrict__ up_sem,
-    float *__restrict__ grec, float *__restrict__ dsem, int batch)
+    float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles)
 {
     constexpr int NT = TW * TH;
     constexpr int CA = CO > 0 ? CO : 1;
@@ -239,7 +243,8 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     __shared__ uint32_t s_max;
     float4 *srec = smem;
     float *ssem = (float *)(smem + 4 * batch);
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+    if (tile >= ntiles) return;
     const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
     const uint2 range = ranges[tile];
     const float fx = (float)ti.px, fy = (float)ti.py;
@@ -276,6 +281,9 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     if (last) atomicMax(&s_max, last);
     __syncthreads();
     const uint32_t end_all = s_max;
+    uint32_t wave_last = last;
+    for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, o, 64));
+    wave_last = __builtin_amdgcn_readfirstlane(wave_last);
     float A = 0.f;
 
     for (uint32_t end = end_all; end > range.x;) {
@@ -286,6 +294,7 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
         __syncthreads();
         for (int j = n - 1; j >= 0; --j) {
             const uint32_t entry = start + (uint32_t)j;
+            if (entry >= wave_last) continue;  // beyond every pixel of this wavefront
             const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
             const float dx = fx - r0.x, dy = fy - r0.y;
             const float power = -0.5f * (r0.z * dx * dx + r1.x * dy * dy) - r0.w * dx * dy;
@@ -384,8 +393,9 @@ hipError_t fwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
     auto vals = (const uint32_t *)(ws + (final_buf ? L.vals1 : L.vals0));
     auto rec = (const float4 *)(ws + L.rec);
     auto cnt = (DevCounters *)(ws + L.counters);
-    hipLaunchKernelGGL((render_fwd_kernel<TW, TH, CO>), dim3((unsigned)pb.total_tiles), dim3(TW * TH), lds, s, cams,
-                       pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out, batch, cnt, (int)counters);
+    hipLaunchKernelGGL((render_fwd_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s, cams,
+                       pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out, batch, cnt, (int)counters,
+                       (uint32_t)pb.total_tiles);
     return hipGetLastError();
 }
 
@@ -401,9 +411,9 @@ hipError_t bwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
     auto rec = (const float4 *)(ws + L.rec);
     auto grec = (float *)(ws + L.grec);
     auto gd = (const float *)(ws + L.gd);
-    hipLaunchKernelGGL((render_bwd_kernel<TW, TH, CO>), dim3((unsigned)pb.total_tiles), dim3(TW * TH), lds, s, cams,
+    hipLaunchKernelGGL((render_bwd_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s, cams,
                        pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out.T_final, out.n_contrib, up.rgb, gd,
-                       up.kmap, up.sem, grec, dg.sem, batch);
+                       up.kmap, up.sem, grec, dg.sem, batch, (uint32_t)pb.total_tiles);
     return hipGetLastError();
 }
 

@@ -46,17 +46,18 @@ struct DevCam {
 constexpr int kRecFloats = 16;
 
 struct DevCounters {
-    uint32_t P;          // pairs emitted (or required when overflowing)
+    uint32_t P;          // pairs required
     uint32_t overflow;   // non-zero when P exceeded the capacity
-    uint32_t pad0, pad1;
+    uint32_t R;          // visible (view, Gaussian) records
+    uint32_t P_eff;      // pairs emitted and sorted (0 on overflow)
     unsigned long long n_eval, n_contrib;
 };
 
 struct WsLayout {
-    size_t cams, rec, rect, touched, offs, scan_part, keys0, keys1, vals0, vals1, hist, digit_tot, ranges, grec, gd,
-        nadj, counters, total;
+    size_t cams, rec, rect, touched, voff, poff, tsorted, dkey0, dkey1, didx0, didx1, scan_part, keys0, keys1, vals0,
+        vals1, hist, digit_tot, ranges, grec, gd, nadj, counters, total;
     int64_t N, VN, total_tiles, total_pix, pair_cap;
-    int V, nb_scan, nb_sort, sort_passes;
+    int V, nb_scan, depth_bits, tile_bits;
 };
 
 constexpr int kScanBlock = 1024;  // elements per scan block (256 threads x 4)
@@ -96,6 +97,27 @@ __device__ __forceinline__ int view_of_tile(const DevCam *cams, int V, uint32_t 
     for (int k = 1; k < V; ++k)
         if (tile >= cams[k].tile_base) v = k;
     return v;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin by workgroup id.  Tile kernels
+// map workgroup b so that each XCD (with its own L2) works through runs of
+// kXcdChunk consecutive tiles (a few tile rows, which share most of their
+// Gaussians), while the runs themselves alternate between XCDs so that every
+// XCD gets a similar share of every view:
+//   xcd = b % 8, k = b / 8, tile = ((k / C) * 8 + xcd) * C + k % C.
+// The grid is rounded up to a whole number of 8 * C blocks; ids at or beyond T
+// return at once.
+constexpr int kXcds = 8;
+constexpr uint32_t kXcdChunk = 32;
+inline unsigned xcd_grid(int64_t tiles)
+{
+    const int64_t g = (int64_t)kXcds * kXcdChunk;
+    return (unsigned)(g * ((tiles + g - 1) / g));
+}
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t tiles)
+{
+    const uint32_t xcd = b % kXcds, k = b / kXcds;
+    return ((k / kXcdChunk) * kXcds + xcd) * kXcdChunk + k % kXcdChunk;
 }
 
 __device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + __expf(-x)); }

@@ -353,7 +353,7 @@ class Rasterizer:
         _chk(lib().ugs_time_stage(self.ctx, st, C.c_void_p(ev_start), C.c_void_p(ev_stop)), "ugs_time_stage")
 
     DEBUG = {"records": (0, "float32", 16), "rects": (1, "int32", 2), "touched": (2, "int32", 1),
-             "keys": (3, "int64", 1), "vals": (4, "int32", 1), "ranges": (5, "int32", 2),
+             "keys": (3, "int32", 1), "vals": (4, "int32", 1), "ranges": (5, "int32", 2),
              "grad_records": (6, "float32", 16), "depth_grad": (7, "float32", 1)}
 
     def debug_buffer(self, name):

@@ -79,7 +79,7 @@ def test_workspace_size_and_limits(U):
     assert L.ugs_workspace_size(ctx, 1000, 8, 3, cams, 1, 100000, C.byref(n)) == U.UGS_OK
     small = n.value
     assert L.ugs_workspace_size(ctx, 1000, 8, 3, cams, 1, 200000, C.byref(n)) == U.UGS_OK
-    assert abs((n.value - small) - 100000 * 24) <= 4 * 256  # 2 x 8 B keys + 2 x 4 B values per pair
+    assert abs((n.value - small) - 100000 * 16) <= 4 * 256  # 2 x 4 B keys + 2 x 4 B values per pair
     assert L.ugs_workspace_size(ctx, 1000, 200, 3, cams, 1, 10, C.byref(n)) == U.UGS_ERR_UNSUPPORTED
     assert L.ugs_workspace_size(ctx, 1000, 8, 4, cams, 1, 10, C.byref(n)) == U.UGS_ERR_UNSUPPORTED
     assert L.ugs_workspace_size(ctx, -1, 8, 3, cams, 1, 10, C.byref(n)) == U.UGS_ERR_INVALID_ARG

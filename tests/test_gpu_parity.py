@@ -105,7 +105,7 @@ def test_binsort_bit_exact(O, kind, tile):
     rect = rast.debug_buffer("rects").cpu().numpy().view(np.uint32).astype(np.int64)
     rec = rast.debug_buffer("records").cpu().numpy()
     touched = rast.debug_buffer("touched").cpu().numpy()
-    keys = rast.debug_buffer("keys").cpu().numpy().view(np.uint64)
+    keys = rast.debug_buffer("keys").cpu().numpy().view(np.uint32).astype(np.uint64)
     vals = rast.debug_buffer("vals").cpu().numpy().view(np.uint32)
     ranges = rast.debug_buffer("ranges").cpu().numpy().view(np.uint32)
     r4 = np.stack([rect[:, 0] & 0xFFFF, rect[:, 0] >> 16, rect[:, 1] & 0xFFFF, rect[:, 1] >> 16], 1)
@@ -116,7 +116,7 @@ def test_binsort_bit_exact(O, kind, tile):
     bases = _tile_bases(cams, tile)
     k_ref, v_ref, counts = O.bin_sort(r4, depth, tiles_x, bases, g["N"])
     assert np.array_equal(counts, touched.astype(np.int64))
-    assert np.array_equal(keys, k_ref)
+    assert np.array_equal(keys, k_ref >> np.uint64(32))
     assert np.array_equal(vals, v_ref)
     tiles = (k_ref >> np.uint64(32)).astype(np.int64)
     total_tiles = bases[-1] + tiles_x[-1] * ((cams[-1]["H"] + th - 1) // th)
