@@ -244,47 +244,55 @@ __global__ void __launch_bounds__(kProjThreads) project_fwd_kernel(ugs_gaussians
     const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
     if (i >= N) return;
     constexpr int NC = (DEG + 1) * (DEG + 1);
-    GaussState<float> G;
+    // FP64 here: the 2D covariance of a thin splat is nearly singular, so its
+    // inverse and the depth coefficients need the extra precision; the record
+    // is rounded to FP32 once.
+    using D = double;
+    GaussState<D> G;
     load_gauss(g, i, G);
-    bool alive = G.o >= kAlphaMin && !(prune_Tk > 0.f && fabsf(G.k - 1.f) > prune_Tk);
+    const bool alive = G.o >= D(kAlphaMin) && !(prune_Tk > 0.f && fabs(G.k - D(1)) > D(prune_Tk));
     float sh[NC][3];
     if (alive)
         for (int c = 0; c < NC; ++c)
             for (int ch = 0; ch < 3; ++ch) sh[c][ch] = g.sh[((int64_t)c * 3 + ch) * N + i];
-    const float r2 = alive ? 2.f * __logf(255.f * G.o) : 0.f;
+    const D r2 = alive ? D(2) * log(D(255) * G.o) : D(0);
     for (int v = 0; v < V; ++v) {
         const DevCam &cam = cams[v];
         const int64_t idx = (int64_t)v * N + i;
         uint32_t nt = 0;
         uint2 rc = make_uint2(0, 0);
-        float zc = cam.R[6] * G.mu[0] + cam.R[7] * G.mu[1] + cam.R[8] * G.mu[2] + cam.t[2];
-        if (alive && zc > cam.z_near) {
-            ViewState<float> S;
+        const D zc = D(cam.R[6]) * G.mu[0] + D(cam.R[7]) * G.mu[1] + D(cam.R[8]) * G.mu[2] + D(cam.t[2]);
+        if (alive && zc > D(cam.z_near)) {
+            ViewState<D> S;
             project_view(G, cam, S);
-            float rx = sqrtf(S.cov00 * r2) * (1.f + 1e-4f) + 1e-3f;
-            float ry = sqrtf(S.cov11 * r2) * (1.f + 1e-4f) + 1e-3f;
-            float u0 = fmaxf(ceilf(S.m2x - rx), 0.f), u1 = fminf(floorf(S.m2x + rx), (float)(cam.W - 1));
-            float v0 = fmaxf(ceilf(S.m2y - ry), 0.f), v1 = fminf(floorf(S.m2y + ry), (float)(cam.H - 1));
+            const D rx = sqrt(S.cov00 * r2) * D(1.0001) + D(1e-3);
+            const D ry = sqrt(S.cov11 * r2) * D(1.0001) + D(1e-3);
+            const D u0 = fmax(ceil(S.m2x - rx), D(0)), u1 = fmin(floor(S.m2x + rx), D(cam.W - 1));
+            const D v0 = fmax(ceil(S.m2y - ry), D(0)), v1 = fmin(floor(S.m2y + ry), D(cam.H - 1));
             if (u0 <= u1 && v0 <= v1 && isfinite(S.m2x) && isfinite(S.m2y)) {
-                int tx0 = (int)u0 / tile_w, tx1 = (int)u1 / tile_w + 1;
-                int ty0 = (int)v0 / tile_h, ty1 = (int)v1 / tile_h + 1;
+                const int tx0 = (int)u0 / tile_w, tx1 = (int)u1 / tile_w + 1;
+                const int ty0 = (int)v0 / tile_h, ty1 = (int)v1 / tile_h + 1;
                 nt = (uint32_t)((tx1 - tx0) * (ty1 - ty0));
                 rc = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
-                float Y[NC];
+                D Y[NC];
                 sh_basis<DEG>(S.dir[0], S.dir[1], S.dir[2], Y);
                 float col[3];
                 for (int ch = 0; ch < 3; ++ch) {
-                    float acc = 0.5f;
-                    for (int c = 0; c < NC; ++c) acc += Y[c] * sh[c][ch];
-                    col[ch] = fmaxf(acc, 0.f);
+                    D acc = D(0.5);
+                    for (int c = 0; c < NC; ++c) acc += Y[c] * D(sh[c][ch]);
+                    col[ch] = (float)fmax(acc, D(0));
                 }
-                float iA = S.iA;
+                // Cholesky factor of the conic (inverse 2D covariance): the
+                // exponent becomes a sum of two squares per fragment
+                const D det = S.cov00 * S.cov11 - S.cov01 * S.cov01;
+                const D l11 = sqrt(S.cov11 / det), l21 = -S.cov01 / (det * l11), l22 = D(1) / sqrt(S.cov11);
+                const D iA = S.iA, fx = D(cam.fx), fy = D(cam.fy);
                 float4 *r = rec + idx * 4;
-                r[0] = make_float4(S.m2x, S.m2y, S.ca, S.cb);
-                r[1] = make_float4(S.cc, G.o, G.k, S.z);
-                r[2] = make_float4(S.Qp0x * iA / cam.fx, S.Qp0y * iA / cam.fy, S.Q00 * iA / (cam.fx * cam.fx),
-                                   S.Q01 * iA / (cam.fx * cam.fy));
-                r[3] = make_float4(S.Q11 * iA / (cam.fy * cam.fy), col[0], col[1], col[2]);
+                r[0] = make_float4((float)S.m2x, (float)S.m2y, (float)l11, (float)l21);
+                r[1] = make_float4((float)l22, (float)G.o, (float)G.k, (float)S.z);
+                r[2] = make_float4((float)(S.Qp0x * iA / fx), (float)(S.Qp0y * iA / fy), (float)(S.Q00 * iA / (fx * fx)),
+                                   (float)(S.Q01 * iA / (fx * fy)));
+                r[3] = make_float4((float)(S.Q11 * iA / (fy * fy)), col[0], col[1], col[2]);
                 if (zero_grad) {
                     float4 zf = make_float4(0.f, 0.f, 0.f, 0.f);
                     float4 *gr = grec + idx * 4;
@@ -370,12 +378,28 @@ __global__ void __launch_bounds__(kProjThreads) project_bwd_kernel(ugs_gaussians
         dmc[0] += g0.x * fx * iz;
         dmc[1] += g0.y * fy * iz;
         dmc[2] -= (g0.x * fx * S.mc[0] + g0.y * fy * S.mc[1]) * iz * iz;
-        // conic -> 2D covariance: dS = -C dC C with dC = [[da, db/2], [db/2, dc]]
+        // Cholesky factor of the conic -> 2D covariance (entries s00, s01, s11):
+        //   l11 = sqrt(s11 / det), l21 = -s01 / (det l11), l22 = 1 / sqrt(s11),
+        //   det = s00 s11 - s01^2.
         {
-            D a = S.ca, b = S.cb, c = S.cc;
-            D da = g0.z, db = D(0.5) * g0.w, dcn = g1.x;
-            D X00 = da * a + db * b, X01 = da * b + db * c, X10 = db * a + dcn * b, X11 = db * b + dcn * c;
-            D dS00 = -(a * X00 + b * X10), dS01 = -(a * X01 + b * X11), dS11 = -(b * X01 + c * X11);
+            const D s00 = S.cov00, s01 = S.cov01, s11 = S.cov11;
+            const D det = s00 * s11 - s01 * s01;
+            const D l11 = sqrt(s11 / det), l21 = -s01 / (det * l11), l22 = D(1) / sqrt(s11);
+            const D dl11 = g0.z, dl21 = g0.w, dl22 = g1.x;
+            // partials of det and of l11
+            const D ddet[3] = {s11, D(-2) * s01, s00};
+            const D dl11_[3] = {D(-0.5) * l11 * s11 / det, l11 * s01 / det, D(0.5) * l11 * (D(1) / s11 - s00 / det)};
+            // l21 = -s01 / u with u = det * l11
+            const D u = det * l11;
+            D dP[3];  // gradient wrt the parameters (s00, s01, s11)
+            for (int q = 0; q < 3; ++q) {
+                const D du = ddet[q] * l11 + det * dl11_[q];
+                const D dl21_q = -(q == 1 ? D(1) : D(0)) / u + s01 * du / (u * u);
+                const D dl22_q = q == 2 ? D(-0.5) * l22 / s11 : D(0);
+                dP[q] = dl11 * dl11_[q] + dl21 * dl21_q + dl22 * dl22_q;
+            }
+            // full-entry symmetric gradient of the 2D covariance matrix
+            const D dS00 = dP[0], dS01 = D(0.5) * dP[1], dS11 = dP[2];
             // cov = T Sig T^T: dSig += T^T dS T, dT = 2 dS T Sig
             const D *t0 = S.T0, *t1 = S.T1;
             for (int p = 0, n = 0; p < 3; ++p)

@@ -163,7 +163,8 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
             for (int j = 0; j < n; ++j) {
                 const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
                 const float dx = fx - r0.x, dy = fy - r0.y;
-                const float power = -0.5f * (r0.z * dx * dx + r1.x * dy * dy) - r0.w * dx * dy;
+                const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
+                const float power = -0.5f * (t1 * t1 + t2 * t2);
                 const float alpha = fminf(kAlphaMax, r1.y * __expf(power));
                 ++n_eval;
                 if (alpha < kAlphaMin) continue;
@@ -297,7 +298,8 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
             if (entry >= wave_last) continue;  // beyond every pixel of this wavefront
             const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
             const float dx = fx - r0.x, dy = fy - r0.y;
-            const float power = -0.5f * (r0.z * dx * dx + r1.x * dy * dy) - r0.w * dx * dy;
+            const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
+            const float power = -0.5f * (t1 * t1 + t2 * t2);
             const float G = __expf(power);
             const float oG = r1.y * G;
             const float alpha = fminf(kAlphaMax, oG);
@@ -348,12 +350,12 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
                 float dm0 = -ddx, dm1 = -ddy;
                 if (oG < kAlphaMax) {
                     const float dpow = dalpha * oG;
-                    v[5] = dalpha * G;                 // opacity
-                    v[2] = -0.5f * dx * dx * dpow;     // conic.a
-                    v[3] = -dx * dy * dpow;            // conic.b
-                    v[4] = -0.5f * dy * dy * dpow;     // conic.c
-                    dm0 += (r0.z * dx + r0.w * dy) * dpow;
-                    dm1 += (r0.w * dx + r1.x * dy) * dpow;
+                    v[5] = dalpha * G;         // opacity
+                    v[2] = -t1 * dx * dpow;    // l11
+                    v[3] = -t1 * dy * dpow;    // l21
+                    v[4] = -t2 * dy * dpow;    // l22
+                    dm0 += t1 * r0.z * dpow;
+                    dm1 += (t1 * r0.w + t2 * r1.x) * dpow;
                 }
                 v[0] = dm0;
                 v[1] = dm1;

@@ -30,17 +30,20 @@ struct DevCam {
 };
 
 // Per-(view, Gaussian) render record, 4 x float4 = 64 B:
-//   r0 = (mean2d.x, mean2d.y, conic.a, conic.b)
-//   r1 = (conic.c, opacity, k, z0)
+//   r0 = (mean2d.x, mean2d.y, l11, l21)
+//   r1 = (l22, opacity, k, z0)
 //   r2 = (beta.x, beta.y, gam.a, gam.b)
 //   r3 = (gam.c, rgb.r, rgb.g, rgb.b)
-// conic (a, b, c): power = -0.5 (a dx^2 + c dy^2) - b dx dy, with (dx, dy) the
-// pixel minus mean2d.  Depth of the ray-ellipsoid midpoint at that pixel:
+// (l11, l21, l22) is the lower Cholesky factor of the conic (inverse 2D
+// covariance): with (dx, dy) the pixel minus mean2d,
+//   power = -0.5 ((l11 dx + l21 dy)^2 + (l22 dy)^2),
+// a sum of squares that stays accurate in FP32 for thin splats.  Depth of the
+// ray-ellipsoid midpoint at that pixel:
 //   d = z0 (1 + B) / (1 + 2B + Cq),  B = beta . (dx, dy),
 //   Cq = gam.a dx^2 + 2 gam.b dx dy + gam.c dy^2.
 // The per-view gradient record has the same 16 slots:
-//   g0 = (d mean2d.x, d mean2d.y, d conic.a, d conic.b)
-//   g1 = (d conic.c, d opacity, d k, d z0)
+//   g0 = (d mean2d.x, d mean2d.y, d l11, d l21)
+//   g1 = (d l22, d opacity, d k, d z0)
 //   g2 = (d beta.x, d beta.y, d gam.a, d gam.b)
 //   g3 = (d gam.c, d rgb.r, d rgb.g, d rgb.b)
 constexpr int kRecFloats = 16;

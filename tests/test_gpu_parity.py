@@ -87,10 +87,12 @@ def test_project_stage(O):
     assert np.abs(rec[vis, 6] - P["k"][vis]).max() < 1e-6
     assert rel(rec[vis, 7], P["depth"][vis]).max() < 1e-6
     assert np.abs(rec[vis, 13:16] - P["rgb"][vis]).max() < 1e-5
-    # conic relative to its scale
-    for j, c in ((2, 0), (3, 1), (4, 2)):
-        scale = np.abs(P["conic"][vis]).max(axis=1)
-        assert (np.abs(rec[vis, j] - P["conic"][vis, c]) / scale).max() < 1e-4
+    # Cholesky factor of the conic, relative to its scale
+    a, b, c = (P["conic"][vis, k] for k in range(3))
+    chol = np.stack([np.sqrt(a), b / np.sqrt(a), np.sqrt(c - b * b / a)], 1)
+    scale = np.abs(chol).max(axis=1)
+    for j in range(3):
+        assert (np.abs(rec[vis, 2 + j] - chol[:, j]) / scale).max() < 1e-5
     # every Gaussian the oracle sees is binned
     assert not np.any(P["visible"].astype(bool) & (touched == 0) & (P["radius"][:, 0] > 2)
                       & (np.abs(P["mean2d"][:, 0] - 100) < 50) & (np.abs(P["mean2d"][:, 1] - 75) < 40))
