@@ -160,7 +160,10 @@ __global__ void __launch_bounds__(256) gather_counts(const uint32_t *__restrict_
         out[r] = touched[didx[r]];
 }
 
-// One thread per depth-sorted record: its pairs at its scanned offset.
+// Pair emission, one wavefront per run of 64 depth-sorted records: the lanes
+// first load one record each, then write every record's pairs together (lane q
+// writes pairs q, q + 64, ...), so the stores are coalesced whatever the
+// footprint sizes.
 __global__ void __launch_bounds__(256) emit_pairs(const DevCam *__restrict__ cams, int64_t N,
                                                   const uint32_t *__restrict__ didx,
                                                   const uint32_t *__restrict__ tsorted,
@@ -170,23 +173,38 @@ __global__ void __launch_bounds__(256) emit_pairs(const DevCam *__restrict__ cam
 {
     if (cnt->overflow) return;
     const uint32_t R = cnt->R;
-    for (uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x; r < R; r += (uint64_t)gridDim.x * 256) {
-        const uint32_t nt = tsorted[r];
-        const uint64_t off = poff[r];
-        if (nt == 0 || off + nt > (uint64_t)cap) continue;
-        const uint32_t idx = didx[r];
-        const int v = (int)(idx / (uint64_t)N);
-        const uint32_t gid = (uint32_t)(idx - (uint64_t)v * N);
-        const DevCam &cam = cams[v];
-        const uint2 rc = rect[idx];
-        const int tx0 = rc.x & 0xffff, ty0 = rc.x >> 16, tx1 = rc.y & 0xffff, ty1 = rc.y >> 16;
-        uint64_t o = off;
-        for (int ty = ty0; ty < ty1; ++ty) {
-            const uint32_t row = cam.tile_base + (uint32_t)(ty * cam.tiles_x);
-            for (int tx = tx0; tx < tx1; ++tx) {
-                keys[o] = row + (uint32_t)tx;
-                vals[o] = gid;
-                ++o;
+    const int lane = __lane_id();
+    const uint64_t wave0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * 256) >> 6;
+    for (uint64_t base = wave0 * 64; base < R; base += nwaves * 64) {
+        const uint64_t r = base + lane;
+        uint32_t nt = 0, off = 0, gid = 0, tb = 0, tw = 1, rx = 0, ry = 0, w = 1;
+        if (r < R) {
+            nt = tsorted[r];
+            off = poff[r];
+            const uint32_t idx = didx[r];
+            const int v = (int)(idx / (uint64_t)N);
+            gid = (uint32_t)(idx - (uint64_t)v * N);
+            const DevCam &cam = cams[v];
+            const uint2 rc = rect[idx];
+            rx = rc.x & 0xffff;
+            ry = rc.x >> 16;
+            w = (rc.y & 0xffff) - rx;
+            tb = cam.tile_base;
+            tw = (uint32_t)cam.tiles_x;
+            if ((uint64_t)off + nt > (uint64_t)cap) nt = 0;
+        }
+        const int m = (int)min((uint64_t)64, (uint64_t)R - base);
+        for (int k = 0; k < m; ++k) {
+            const uint32_t knt = __shfl(nt, k, 64);
+            if (knt == 0) continue;
+            const uint32_t koff = __shfl(off, k, 64), kgid = __shfl(gid, k, 64), ktb = __shfl(tb, k, 64);
+            const uint32_t ktw = __shfl(tw, k, 64), krx = __shfl(rx, k, 64), kry = __shfl(ry, k, 64);
+            const uint32_t kw = __shfl(w, k, 64);
+            for (uint32_t q = lane; q < knt; q += 64) {
+                const uint32_t ty = q / kw, tx = q - ty * kw;
+                keys[koff + q] = ktb + (kry + ty) * ktw + krx + tx;
+                vals[koff + q] = kgid;
             }
         }
     }
@@ -198,45 +216,48 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift)
     return (uint32_t)(key >> shift) & 255u;
 }
 
-// Per-block digit histogram of the block's contiguous chunk.
+// The sort runs with one wavefront per block (kSortThreads = 64) and a fixed
+// grid of kSortBlocks blocks, each owning a contiguous chunk of the input.
+// Per-block digit histogram of the block's chunk.
 template <typename K>
 __global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__ keys, const uint32_t *__restrict__ n_dev,
                                                            int shift, uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    for (int d = threadIdx.x; d < 256; d += kSortThreads) h[d] = 0;
     __syncthreads();
     const uint32_t P = *n_dev;
-    const uint32_t per = ((P + kSortBlocks - 1) / kSortBlocks + 255) & ~255u;
+    const uint32_t per = ((P + kSortBlocks - 1) / kSortBlocks + 63) & ~63u;
     const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = min((uint64_t)P, b0 + per);
     for (uint64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) atomicAdd(&h[digit_of(keys[i], shift)], 1u);
     __syncthreads();
-    hist[threadIdx.x * kSortBlocks + blockIdx.x] = h[threadIdx.x];
+    for (int d = threadIdx.x; d < 256; d += kSortThreads) hist[(size_t)d * kSortBlocks + blockIdx.x] = h[d];
 }
 
 // One block per digit: exclusive scan of that digit's per-block counts.
-__global__ void __launch_bounds__(kSortThreads) radix_scan_digit(uint32_t *__restrict__ hist,
-                                                                 uint32_t *__restrict__ digit_tot)
+__global__ void __launch_bounds__(256) radix_scan_digit(uint32_t *__restrict__ hist, uint32_t *__restrict__ digit_tot)
 {
     __shared__ uint32_t lds4[4];
+    constexpr int PER = kSortBlocks / 256;
     uint32_t *row = hist + (size_t)blockIdx.x * kSortBlocks;
-    uint32_t v[4], s = 0;
-    for (int k = 0; k < 4; ++k) {
-        v[k] = row[threadIdx.x * 4 + k];
+    uint32_t v[PER], s = 0;
+    for (int k = 0; k < PER; ++k) {
+        v[k] = row[threadIdx.x * PER + k];
         s += v[k];
     }
     uint32_t tot;
     uint32_t ex = block_excl_scan256(s, lds4, tot);
-    for (int k = 0; k < 4; ++k) {
-        row[threadIdx.x * 4 + k] = ex;
+    for (int k = 0; k < PER; ++k) {
+        row[threadIdx.x * PER + k] = ex;
         ex += v[k];
     }
     if (threadIdx.x == 0) digit_tot[blockIdx.x] = tot;
 }
 
-// Stable scatter: each block walks its chunk in order, 256 keys at a time; ranks
-// within a wave come from eight ballots (lanes sharing the digit), ranks across
-// waves and tiles from per-digit running counters in LDS.
+// Stable scatter by one wavefront: walks its chunk in order, 64 keys at a time.
+// A key's rank is the number of lanes below it with the same digit (eight
+// ballots) plus the digit's running count in LDS, which the lowest lane of each
+// digit group advances afterwards; a single wavefront needs no barriers.
 template <typename K>
 __global__ void __launch_bounds__(kSortThreads) radix_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                               K *__restrict__ kout, uint32_t *__restrict__ vout,
@@ -244,17 +265,31 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(const K *__restric
                                                               const uint32_t *__restrict__ hist,
                                                               const uint32_t *__restrict__ digit_tot)
 {
-    __shared__ uint32_t base[256], run[256], lds4[4];
-    __shared__ uint32_t wcnt[4][256], wpre[4][256];
-    const int t = threadIdx.x, wave = t >> 6;
-    uint32_t dt = digit_tot[t], tot;
-    uint32_t dex = block_excl_scan256(dt, lds4, tot);
-    base[t] = dex + hist[t * kSortBlocks + blockIdx.x];
-    run[t] = 0;
-    for (int w = 0; w < 4; ++w) wcnt[w][t] = 0;
+    __shared__ uint32_t base[256], dex[256];
+    const int t = threadIdx.x;
+    // digit bases: exclusive scan of the digit totals (4 per lane) + this block's offset
+    {
+        uint32_t d4[4], s = 0;
+        for (int k = 0; k < 4; ++k) {
+            d4[k] = digit_tot[4 * t + k];
+            s += d4[k];
+        }
+        uint32_t inc = s;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(inc, o, 64);
+            if (t >= o) inc += y;
+        }
+        uint32_t ex = inc - s;
+        for (int k = 0; k < 4; ++k) {
+            dex[4 * t + k] = ex;
+            ex += d4[k];
+        }
+    }
+    __syncthreads();
+    for (int d = t; d < 256; d += kSortThreads) base[d] = dex[d] + hist[(size_t)d * kSortBlocks + blockIdx.x];
     __syncthreads();
     const uint32_t P = *n_dev;
-    const uint32_t per = ((P + kSortBlocks - 1) / kSortBlocks + 255) & ~255u;
+    const uint32_t per = ((P + kSortBlocks - 1) / kSortBlocks + 63) & ~63u;
     const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = min((uint64_t)P, b0 + per);
     const uint64_t lt = __lanemask_lt();
     for (uint64_t tb = b0; tb < b1; tb += kSortThreads) {
@@ -270,21 +305,12 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(const K *__restric
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
         const uint32_t rank = __popcll(peers & lt);
-        if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
-        __syncthreads();
-        {
-            uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
-            uint32_t r = run[t];
-            wpre[0][t] = r;
-            wpre[1][t] = r + c0;
-            wpre[2][t] = r + c0 + c1;
-            wpre[3][t] = r + c0 + c1 + c2;
-            run[t] = r + c0 + c1 + c2 + c3;
-            wcnt[0][t] = 0; wcnt[1][t] = 0; wcnt[2][t] = 0; wcnt[3][t] = 0;
-        }
-        __syncthreads();
+        uint32_t pos = 0;
+        if (valid) pos = base[d] + rank;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) base[d] += __popcll(peers);
+        __builtin_amdgcn_wave_barrier();
         if (valid) {
-            uint32_t pos = base[d] + wpre[wave][d] + rank;
             kout[pos] = key;
             vout[pos] = val;
         }
@@ -327,7 +353,7 @@ int radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t *n_dev, 
     for (int shift = 0; shift < bits; shift += 8) {
         hipLaunchKernelGGL(radix_hist<K>, dim3(kSortBlocks), dim3(kSortThreads), 0, s, (const K *)k[cur], n_dev, shift,
                            hist);
-        hipLaunchKernelGGL(radix_scan_digit, dim3(256), dim3(kSortThreads), 0, s, hist, dtot);
+        hipLaunchKernelGGL(radix_scan_digit, dim3(256), dim3(256), 0, s, hist, dtot);
         hipLaunchKernelGGL(radix_scatter<K>, dim3(kSortBlocks), dim3(kSortThreads), 0, s, (const K *)k[cur],
                            (const uint32_t *)v[cur], k[cur ^ 1], v[cur ^ 1], n_dev, shift, (const uint32_t *)hist,
                            (const uint32_t *)dtot);

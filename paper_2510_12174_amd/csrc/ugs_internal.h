@@ -64,8 +64,8 @@ struct WsLayout {
 };
 
 constexpr int kScanBlock = 1024;  // elements per scan block (256 threads x 4)
-constexpr int kSortBlocks = 1024; // fixed radix-sort grid
-constexpr int kSortThreads = 256;
+constexpr int kSortBlocks = 4096; // fixed radix-sort grid (one wavefront per block)
+constexpr int kSortThreads = 64;
 
 struct Problem {
     int64_t N;
