@@ -105,6 +105,12 @@ typedef struct {
     int orient_sign;     /* +1: flip normals to face the camera; -1: the literal
                             Eq. direction_correction (keep if N . d_view <= 0) */
     float prune_Tk;      /* > 0: skip Gaussians with |k - 1| > prune_Tk (section 3.3) */
+    int depth_mode;      /* fragment depth d_i composited into the depth map:
+                            0 (default): the camera depth of the midpoint of the
+                              ray-ellipsoid intersections (section 3.2, Eq. midpoint);
+                            1: the camera depth of the Gaussian's centre, the
+                              "Center Point" row of the supplementary's module
+                              ablation table.  Gradients follow the chosen form. */
 } ugs_options;
 
 typedef struct ugs_ctx ugs_ctx;

@@ -82,6 +82,9 @@ typedef struct {
     int orient_sign;
     double prune_Tk; /* <= 0 disables the pruning skip */
     double eps_n;
+    int depth_mode;  /* 0: ray-ellipsoid midpoint depth (section 3.2); 1: the
+                        Gaussian centre's camera depth (the "Center Point" row of
+                        the supplementary's module ablation table) */
 } orc_opt;
 
 /* Per-Gaussian projected state for one view. */
@@ -453,11 +456,15 @@ static int pixel_frags(const ctx_t *c, int u, int v, frag_t *F, pixinfo_t *info)
         F[n].G = G;
         F[n].clamped = oG >= ALPHA_MAX;
         ncl += F[n].clamped;
-        double mu[3];
-        gauss_mean(c->g, id, mu);
-        depth_t D;
-        depth_literal(c, P, mu, u, v, &D);
-        F[n].d = D.d;
+        if (c->opt->depth_mode == 1) {
+            F[n].d = P->z;
+        } else {
+            double mu[3];
+            gauss_mean(c->g, id, mu);
+            depth_t D;
+            depth_literal(c, P, mu, u, v, &D);
+            F[n].d = D.d;
+        }
         T = tT;
         ++n;
     }
@@ -748,7 +755,10 @@ static void pixel_backward(const ctx_t *c, int u, int v, const frag_t *F, int n,
         for (int ch = 0; ch < Co; ++ch) atomic_add(&dsem[id * Co + ch], w * gO[ch]);
         /* depth: supplementary S1.2 chain */
         double dd = w * gD;
-        if (dd != 0.0) {
+        if (dd != 0.0 && c->opt->depth_mode == 1) {
+            /* d = mu_c.z = R[2,:] mu + t_z */
+            for (int r = 0; r < 3; ++r) atomic_add(&a[A_DMU + r], dd * c->cam->R[6 + r]);
+        } else if (dd != 0.0) {
             double mu[3];
             gauss_mean(g, id, mu);
             depth_t D;

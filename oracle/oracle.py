@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-OPTS_DEFAULT = dict(step1=1, step2=2, lambda_=0.5, orient_sign=1, prune_Tk=0.0, eps_n=1e-9)
+OPTS_DEFAULT = dict(step1=1, step2=2, lambda_=0.5, orient_sign=1, prune_Tk=0.0, eps_n=1e-9, depth_mode=0)
 
 NS_BORDER, NS_ZERO, NS_VALID = 0, 1, 2
 
@@ -50,7 +50,8 @@ class _Gs(C.Structure):
 
 class _Opt(C.Structure):
     _fields_ = [("step1", C.c_int), ("step2", C.c_int), ("lambda_", C.c_double),
-                ("orient_sign", C.c_int), ("prune_Tk", C.c_double), ("eps_n", C.c_double)]
+                ("orient_sign", C.c_int), ("prune_Tk", C.c_double), ("eps_n", C.c_double),
+                ("depth_mode", C.c_int)]
 
 
 _lib = None
@@ -101,7 +102,7 @@ def _opt(opts=None):
         for k, v in opts.items():
             o["lambda_" if k == "lambda" else k] = v
     return _Opt(int(o["step1"]), int(o["step2"]), float(o["lambda_"]), int(o["orient_sign"]),
-                float(o["prune_Tk"]), float(o["eps_n"]))
+                float(o["prune_Tk"]), float(o["eps_n"]), int(o["depth_mode"]))
 
 
 def _scene(g):

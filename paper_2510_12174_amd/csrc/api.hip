@@ -86,6 +86,7 @@ int check_options(const ugs_options *o)
     if (!(o->lambda >= 0.f && o->lambda <= 1.f)) return UGS_ERR_INVALID_ARG;
     if (o->orient_sign != 1 && o->orient_sign != -1) return UGS_ERR_INVALID_ARG;
     if (!(o->prune_Tk >= 0.f)) return UGS_ERR_INVALID_ARG;
+    if (o->depth_mode != 0 && o->depth_mode != 1) return UGS_ERR_INVALID_ARG;
     return UGS_OK;
 }
 
@@ -160,6 +161,7 @@ void make_problem(const ugs_options &o, int64_t N, int C_o, int sh_deg, const ug
     pb.tile_w = o.tile_w;
     pb.tile_h = o.tile_h;
     pb.prune_Tk = o.prune_Tk;
+    pb.depth_mode = o.depth_mode;
     int64_t tiles = 0, pix = 0;
     for (int v = 0; v < V; ++v) {
         const ugs_camera &c = cams[v];
@@ -524,6 +526,7 @@ void ugs_default_options(ugs_options *o)
     o->lambda = 0.5f;
     o->orient_sign = 1;
     o->prune_Tk = 0.f;
+    o->depth_mode = 0;
 }
 
 int ugs_create(ugs_ctx **out, const ugs_options *opt)

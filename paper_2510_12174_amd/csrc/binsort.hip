@@ -217,7 +217,12 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift)
 }
 
 // The sort runs with one wavefront per block (kSortThreads = 64) and a fixed
-// grid of kSortBlocks blocks, each owning a contiguous chunk of the input.
+// grid of kSortBlocks blocks, each owning a contiguous chunk of the input.  A
+// single wavefront per block keeps too few loads in flight to cover HBM latency
+// if it walks its chunk 64 keys at a time, so both kernels below load
+// kSortUnroll groups of 64 keys before using any of them.
+constexpr int kSortUnroll = 8;
+
 // Per-block digit histogram of the block's chunk.
 template <typename K>
 __global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__ keys, const uint32_t *__restrict__ n_dev,
@@ -229,7 +234,17 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__
     const uint32_t P = *n_dev;
     const uint32_t per = ((P + kSortBlocks - 1) / kSortBlocks + 63) & ~63u;
     const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = min((uint64_t)P, b0 + per);
-    for (uint64_t i = b0 + threadIdx.x; i < b1; i += kSortThreads) atomicAdd(&h[digit_of(keys[i], shift)], 1u);
+    for (uint64_t tb = b0; tb < b1; tb += kSortThreads * kSortUnroll) {
+        K key[kSortUnroll];
+#pragma unroll
+        for (int u = 0; u < kSortUnroll; ++u) {
+            const uint64_t i = tb + u * kSortThreads + threadIdx.x;
+            key[u] = i < b1 ? keys[i] : K(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kSortUnroll; ++u)
+            if (tb + u * kSortThreads + threadIdx.x < b1) atomicAdd(&h[digit_of(key[u], shift)], 1u);
+    }
     __syncthreads();
     for (int d = threadIdx.x; d < 256; d += kSortThreads) hist[(size_t)d * kSortBlocks + blockIdx.x] = h[d];
 }
@@ -254,7 +269,8 @@ __global__ void __launch_bounds__(256) radix_scan_digit(uint32_t *__restrict__ h
     if (threadIdx.x == 0) digit_tot[blockIdx.x] = tot;
 }
 
-// Stable scatter by one wavefront: walks its chunk in order, 64 keys at a time.
+// Stable scatter by one wavefront: walks its chunk in order, 64 keys at a time
+// (loaded kSortUnroll groups ahead).
 // A key's rank is the number of lanes below it with the same digit (eight
 // ballots) plus the digit's running count in LDS, which the lowest lane of each
 // digit group advances afterwards; a single wavefront needs no barriers.
@@ -292,27 +308,36 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(const K *__restric
     const uint32_t per = ((P + kSortBlocks - 1) / kSortBlocks + 63) & ~63u;
     const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = min((uint64_t)P, b0 + per);
     const uint64_t lt = __lanemask_lt();
-    for (uint64_t tb = b0; tb < b1; tb += kSortThreads) {
-        const uint64_t i = tb + t;
-        const bool valid = i < b1;
-        const K key = valid ? kin[i] : K(0);
-        const uint32_t val = valid ? vin[i] : 0u;
-        const uint32_t d = digit_of(key, shift);
-        uint64_t peers = __ballot(valid);
+    for (uint64_t tb = b0; tb < b1; tb += kSortThreads * kSortUnroll) {
+        K key[kSortUnroll];
+        uint32_t val[kSortUnroll];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            uint64_t m = __ballot((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? m : ~m;
+        for (int u = 0; u < kSortUnroll; ++u) {
+            const uint64_t i = tb + u * kSortThreads + t;
+            key[u] = i < b1 ? kin[i] : K(0);
+            val[u] = i < b1 ? vin[i] : 0u;
         }
-        const uint32_t rank = __popcll(peers & lt);
-        uint32_t pos = 0;
-        if (valid) pos = base[d] + rank;
-        __builtin_amdgcn_wave_barrier();
-        if (valid && rank == 0) base[d] += __popcll(peers);
-        __builtin_amdgcn_wave_barrier();
-        if (valid) {
-            kout[pos] = key;
-            vout[pos] = val;
+#pragma unroll
+        for (int u = 0; u < kSortUnroll; ++u) {
+            const uint64_t i = tb + u * kSortThreads + t;
+            const bool valid = i < b1;
+            const uint32_t d = digit_of(key[u], shift);
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                uint64_t m = __ballot((d >> b) & 1u);
+                peers &= ((d >> b) & 1u) ? m : ~m;
+            }
+            const uint32_t rank = __popcll(peers & lt);
+            uint32_t pos = 0;
+            if (valid) pos = base[d] + rank;
+            __builtin_amdgcn_wave_barrier();
+            if (valid && rank == 0) base[d] += __popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+            if (valid) {
+                kout[pos] = key[u];
+                vout[pos] = val[u];
+            }
         }
     }
 }

@@ -48,39 +48,56 @@ __device__ __forceinline__ float dpp_add_sel(float a, float b, bool take_b)
     return take_b ? tb : ta;
 }
 
-// Transposed reduce-scatter over a wavefront: x[0..63] are 64 per-lane values;
-// on return lane l holds the sum over all 64 lanes of x[l].  Two cross-half
-// swap levels (v_permlane32_swap, v_permlane16_swap) halve the register count
-// at one swap and one add per register pair, then four DPP levels inside each
-// 16-lane row (rotate by 8, half mirror, quad permutes) finish with a select on
-// the lane's bit.  About 2.2 VALU instructions per value, against 7 for a
-// separate DPP tree per value.  All 64 lanes must be active.
-__device__ __forceinline__ float reduce_scatter64(float (&x)[64])
+// One level of the transposed reduce-scatter inside a 16-lane row: registers
+// k and k + N/2 are added to their DPP-permuted copies and each lane keeps the
+// sum selected by its lane bit; a single register is just added (the result is
+// then duplicated across the lane pair).
+template <int CTRL, int N>
+__device__ __forceinline__ void dpp_level(const float (&in)[N], float (&out)[N > 1 ? N / 2 : 1], bool bit)
 {
-    const int lane = __lane_id();
-    float s[32];
+    if constexpr (N > 1) {
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-        auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[k]), __float_as_uint(x[k + 32]), false, false);
+        for (int k = 0; k < N / 2; ++k) out[k] = dpp_add_sel<CTRL>(in[k], in[k + N / 2], bit);
+    } else {
+        out[0] = dpp_step<CTRL, 0xf>(in[0]);
+    }
+}
+
+// Transposed reduce-scatter over a wavefront: x[0..NV-1] are NV per-lane values
+// (NV = 8, 16, 32 or 64); on return each lane l holds the sum over all 64 lanes
+// of x[l >> (6 - log2 NV)], so value q sits in the 64/NV lanes starting at
+// q * 64/NV.  Two cross-half swap levels (v_permlane32_swap, v_permlane16_swap)
+// halve the register count at one swap and one add per register pair, then four
+// DPP levels inside each 16-lane row (rotate by 8, half mirror, quad permutes)
+// finish with a select on the lane's bit; once one register is left the
+// remaining levels are plain adds.  For NV = 64 this is about 2.2 VALU
+// instructions per value, against 7 for a separate DPP tree per value, and the
+// cost scales with NV.  All 64 lanes must be active.
+template <int NV>
+__device__ __forceinline__ float reduce_scatter(const float (&x)[NV])
+{
+    static_assert(NV == 8 || NV == 16 || NV == 32 || NV == 64, "reduce_scatter: NV must be 8, 16, 32 or 64");
+    constexpr int N1 = NV / 2, N2 = NV / 4;
+    const int lane = __lane_id();
+    float s[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[k]), __float_as_uint(x[k + N1]), false, false);
         s[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    float u[16];
+    float u[N2];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[k]), __float_as_uint(s[k + 16]), false, false);
+    for (int k = 0; k < N2; ++k) {
+        auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[k]), __float_as_uint(s[k + N2]), false, false);
         u[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
-    float v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = dpp_add_sel<0x128>(u[k], u[k + 8], b3);  // row_ror:8
-    float w[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = dpp_add_sel<0x141>(v[k], v[k + 4], b2);  // row_half_mirror
-    float y[2];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) y[k] = dpp_add_sel<0x4E>(w[k], w[k + 2], b1);   // quad_perm [2,3,0,1]
-    return dpp_add_sel<0xB1>(y[0], y[1], b0);                                    // quad_perm [1,0,3,2]
+    constexpr int N3 = N2 > 1 ? N2 / 2 : 1, N4 = N3 > 1 ? N3 / 2 : 1, N5 = N4 > 1 ? N4 / 2 : 1;
+    float v[N3], w[N4], y[N5], z[1];
+    dpp_level<0x128, N2>(u, v, lane & 8);  // row_ror:8
+    dpp_level<0x141, N3>(v, w, lane & 4);  // row_half_mirror
+    dpp_level<0x4E, N4>(w, y, lane & 2);   // quad_perm [2,3,0,1]
+    dpp_level<0xB1, N5>(y, z, lane & 1);   // quad_perm [1,0,3,2]
+    return z[0];
 }
 
 struct TileInfo {
@@ -133,7 +150,7 @@ template <int TW, int TH, int CO>
 __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
-    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles)
+    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles, int centre_depth)
 {
     constexpr int NT = TW * TH;
     extern __shared__ float4 smem[];
@@ -176,7 +193,7 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
                 const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
                 const float B = r2.x * dx + r2.y * dy;
                 const float Cq = r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy;
-                const float d = r1.w * (1.f + B) / (1.f + 2.f * B + Cq);
+                const float d = centre_depth ? r1.w : r1.w * (1.f + B) / (1.f + 2.f * B + Cq);
                 const double w = (double)alpha * T;
                 const float wf = (float)w;
                 cr += wf * r3.y;
@@ -229,17 +246,43 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
     }
 }
 
+// Reduces and adds one fragment's 16 + C_o gradient values (slots 0..15 the
+// gradient record, slots 16.. the semantic logits, zero beyond C_o) in groups of
+// 64, 32, 16 or 8 slots, largest first, so that no reduction work is spent on
+// padding beyond the next multiple of 8.  One lane per slot issues the atomic.
+template <int OFF, int REM, int CO, int CA>
+__device__ __forceinline__ void emit_groups(const float (&v)[16], float w, const float (&gO)[CA], int lane,
+                                            float *__restrict__ grec_i, float *__restrict__ dsem_i, int C_o)
+{
+    constexpr int G = REM >= 64 ? 64 : REM >= 32 ? 32 : REM >= 16 ? 16 : 8;
+    constexpr int SH = G == 64 ? 0 : G == 32 ? 1 : G == 16 ? 2 : 3;  // log2(64 / G)
+    float x[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        const int slot = OFF + q;
+        if (slot < 16) x[q] = v[slot];
+        else if (slot - 16 < CO) x[q] = w * gO[slot - 16];
+        else x[q] = 0.f;
+    }
+    const float tot = reduce_scatter<G>(x);
+    if ((lane & ((1 << SH) - 1)) == 0) {
+        const int slot = OFF + (lane >> SH);
+        if (slot < 16) unsafeAtomicAdd(&grec_i[slot], tot);
+        else if (slot - 16 < C_o) unsafeAtomicAdd(&dsem_i[slot - 16], tot);
+    }
+    if constexpr (REM > G) emit_groups<OFF + G, REM - G, CO, CA>(v, w, gO, lane, grec_i, dsem_i, C_o);
+}
+
 template <int TW, int TH, int CO>
 __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
     const float *__restrict__ T_final, const uint32_t *__restrict__ n_contrib, const float *__restrict__ up_rgb,
     const float *__restrict__ gD_img, const float *__restrict__ up_kmap, const float *__restrict__ up_sem,
-    float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles)
+    float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, int centre_depth)
 {
     constexpr int NT = TW * TH;
     constexpr int CA = CO > 0 ? CO : 1;
-    constexpr int NGRP = (16 + CO + 63) / 64;
     extern __shared__ float4 smem[];
     __shared__ uint32_t s_max;
     float4 *srec = smem;
@@ -317,7 +360,7 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
                 const float B = r2.x * dx + r2.y * dy;
                 const float Cq = r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy;
                 const float iden = 1.f / (1.f + 2.f * B + Cq);
-                const float d = r1.w * (1.f + B) * iden;
+                const float d = centre_depth ? r1.w : r1.w * (1.f + B) * iden;
                 float s = gR * r3.y + gG * r3.z + gB * r3.w + gDp * d + gK * r1.z;
                 if constexpr (CO > 0) {
                     const float4 *s4 = (const float4 *)(ssem + j * CO);
@@ -333,21 +376,25 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
                 v[13] = w * gR;
                 v[14] = w * gG;
                 v[15] = w * gB;
-                // depth: d = z0 (1 + B) / (1 + 2B + Cq)
                 const float dd = w * gDp;
-                const float z0 = r1.w;
-                const float dB = dd * z0 * (Cq - 1.f) * iden * iden;
-                const float dC = -dd * z0 * (1.f + B) * iden * iden;
-                v[7] = dd * (1.f + B) * iden;     // z0
-                v[8] = dB * dx;                    // beta.x
-                v[9] = dB * dy;                    // beta.y
-                v[10] = dC * dx * dx;              // gam.a
-                v[11] = 2.f * dC * dx * dy;        // gam.b
-                v[12] = dC * dy * dy;              // gam.c
-                // d depth / d(dx, dy); the pixel offset is (pixel - mean2d)
-                float ddx = dB * r2.x + dC * 2.f * (r2.z * dx + r2.w * dy);
-                float ddy = dB * r2.y + dC * 2.f * (r2.w * dx + r3.x * dy);
-                float dm0 = -ddx, dm1 = -ddy;
+                float dm0 = 0.f, dm1 = 0.f;
+                if (centre_depth) {
+                    v[7] = dd;  // d = z0
+                } else {
+                    // depth: d = z0 (1 + B) / (1 + 2B + Cq)
+                    const float z0 = r1.w;
+                    const float dB = dd * z0 * (Cq - 1.f) * iden * iden;
+                    const float dC = -dd * z0 * (1.f + B) * iden * iden;
+                    v[7] = dd * (1.f + B) * iden;     // z0
+                    v[8] = dB * dx;                    // beta.x
+                    v[9] = dB * dy;                    // beta.y
+                    v[10] = dC * dx * dx;              // gam.a
+                    v[11] = 2.f * dC * dx * dy;        // gam.b
+                    v[12] = dC * dy * dy;              // gam.c
+                    // d depth / d(dx, dy); the pixel offset is (pixel - mean2d)
+                    dm0 = -(dB * r2.x + dC * 2.f * (r2.z * dx + r2.w * dy));
+                    dm1 = -(dB * r2.y + dC * 2.f * (r2.w * dx + r3.x * dy));
+                }
                 if (oG < kAlphaMax) {
                     const float dpow = dalpha * oG;
                     v[5] = dalpha * G;         // opacity
@@ -365,21 +412,7 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
             v[6] = w * gK;
             const uint32_t id = vals[entry];
             const int64_t ridx = recbase + id;
-#pragma unroll
-            for (int grp = 0; grp < NGRP; ++grp) {
-                float x[64];
-#pragma unroll
-                for (int q = 0; q < 64; ++q) {
-                    const int slot = grp * 64 + q;
-                    if (slot < 16) x[q] = v[slot];
-                    else if (slot - 16 < CO) x[q] = w * gO[slot - 16];
-                    else x[q] = 0.f;
-                }
-                const float tot = reduce_scatter64(x);
-                const int slot = grp * 64 + lane;
-                if (slot < 16) unsafeAtomicAdd(&grec[ridx * kRecFloats + slot], tot);
-                else if (slot - 16 < C_o) unsafeAtomicAdd(&dsem[(int64_t)id * C_o + (slot - 16)], tot);
-            }
+            emit_groups<0, 16 + CO, CO>(v, w, gO, lane, grec + ridx * kRecFloats, dsem + (int64_t)id * C_o, C_o);
         }
         end = start;
     }
@@ -397,7 +430,7 @@ hipError_t fwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
     auto cnt = (DevCounters *)(ws + L.counters);
     hipLaunchKernelGGL((render_fwd_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s, cams,
                        pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out, batch, cnt, (int)counters,
-                       (uint32_t)pb.total_tiles);
+                       (uint32_t)pb.total_tiles, pb.depth_mode);
     return hipGetLastError();
 }
 
@@ -415,7 +448,7 @@ hipError_t bwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
     auto gd = (const float *)(ws + L.gd);
     hipLaunchKernelGGL((render_bwd_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s, cams,
                        pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out.T_final, out.n_contrib, up.rgb, gd,
-                       up.kmap, up.sem, grec, dg.sem, batch, (uint32_t)pb.total_tiles);
+                       up.kmap, up.sem, grec, dg.sem, batch, (uint32_t)pb.total_tiles, pb.depth_mode);
     return hipGetLastError();
 }
 

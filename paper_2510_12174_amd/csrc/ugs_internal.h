@@ -73,6 +73,7 @@ struct Problem {
     int tile_w, tile_h;
     int64_t total_tiles, total_pix;
     float prune_Tk;
+    int depth_mode;  // 0: ray-ellipsoid midpoint, 1: Gaussian centre
 };
 
 // ---- launchers (each enqueues on `s`; return the launch error) ----

@@ -65,7 +65,8 @@ class ugs_upstream(C.Structure):
 
 class ugs_options(C.Structure):
     _fields_ = [("tile_w", C.c_int), ("tile_h", C.c_int), ("batch", C.c_int), ("step1", C.c_int),
-                ("step2", C.c_int), ("lambda_", C.c_float), ("orient_sign", C.c_int), ("prune_Tk", C.c_float)]
+                ("step2", C.c_int), ("lambda_", C.c_float), ("orient_sign", C.c_int), ("prune_Tk", C.c_float),
+                ("depth_mode", C.c_int)]
 
 
 _lib = None

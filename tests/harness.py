@@ -88,7 +88,8 @@ def gpu_run(g, cams, opts, ups=None, tile=(16, 16), batch=0, per_view=False, ras
     gd = U.to_device(g)
     C_o = int(g["C_o"])
     if rast is None:
-        rast = U.Rasterizer(tile_w=tile[0], tile_h=tile[1], batch=batch, prune_Tk=float(opts.get("prune_Tk", 0.0)))
+        rast = U.Rasterizer(tile_w=tile[0], tile_h=tile[1], batch=batch, prune_Tk=float(opts.get("prune_Tk", 0.0)),
+                            depth_mode=int(opts.get("depth_mode", 0)))
     if not per_view:
         out = rast.forward(gd, cams)
         grads = None

@@ -36,8 +36,9 @@ def _tile_bases(cams, tile):
     return out
 
 
-def _check_forward(O, kind, tile=(16, 16), normals_e2e=False):
+def _check_forward(O, kind, tile=(16, 16), normals_e2e=False, extra=None):
     g, cams, opts = Hn.small_workload(kind)
+    opts = dict(opts, **(extra or {}))
     Hn.say(f"[{kind}] N={g['N']} views={len(cams)} C_o={g['C_o']} tile={tile}")
     outs, _, rast = Hn.gpu_run(g, cams, opts, tile=tile)
     ora = Hn.oracle_forward(O, g, cams, opts)
@@ -128,8 +129,9 @@ def test_binsort_bit_exact(O, kind, tile):
     assert np.array_equal(ranges.astype(np.int64), ref_ranges)
 
 
-def _check_backward(O, kind, tile=(16, 16), per_view=False, with_normals=True):
+def _check_backward(O, kind, tile=(16, 16), per_view=False, with_normals=True, extra=None):
     g, cams, opts = Hn.small_workload(kind)
+    opts = dict(opts, **(extra or {}))
     ora = Hn.oracle_forward(O, g, cams, opts)
     ms = Hn.masks(O, g, cams, opts, ora)
     ups = Hn.scenes.upstream(cams, g["C_o"], seed=77)
@@ -152,6 +154,16 @@ def test_backward_parity(O, kind):
     factor, semantics; normals only where the forward normal is end-to-end
     comparable, i.e. workload 1)."""
     err, _, _ = _check_backward(O, kind, with_normals=(kind == "w1"))
+    for k, e in err.items():
+        assert e <= 1.0, (k, e)
+
+
+@pytest.mark.parametrize("kind", ["w1", "w3s"])
+def test_centre_depth_mode_parity(O, kind):
+    """Centre-point depth (depth_mode 1): images and gradients against the
+    oracle run in the same mode."""
+    _check_forward(O, kind, extra=dict(depth_mode=1))
+    err, _, _ = _check_backward(O, kind, with_normals=(kind == "w1"), extra=dict(depth_mode=1))
     for k, e in err.items():
         assert e <= 1.0, (k, e)
 

@@ -330,6 +330,45 @@ def test_gradients_match_fd_tiny(oracle_mod, sh_deg, seed):
     assert ok > 0.8 * len(picks)
 
 
+def test_centre_depth_mode_closed_form(oracle_mod):
+    """Centre-point depth (the "Center Point" ablation of the supplementary's
+    module table): with every Gaussian centre at camera depth z the depth map is
+    z (1 - T_final) exactly; the midpoint form differs on the same scene."""
+    O = oracle_mod
+    g, cams, opts = scenes.tiny_scene(n=40, seed=7, sh_deg=1, C_o=3)
+    cam = cams[0]
+    R = np.asarray(cam["R"], np.float64)
+    t = np.asarray(cam["t"], np.float64)
+    g = dict(g)
+    mu = np.asarray(g["mean"], np.float64)
+    # move each centre along the camera's optical axis so that mu_c.z = 2.5
+    zc = R[2] @ mu + t[2]
+    mu = mu + np.outer(R[2], 2.5 - zc)
+    g["mean"] = mu.astype(np.float32)
+    zc32 = R[2] @ np.asarray(g["mean"], np.float64) + t[2]
+    o1 = O.render(g, cam, dict(opts, depth_mode=1))
+    assert (o1["n_frag"] > 0).sum() > 100
+    # exact statement: D = sum_i w_i z_i with every z_i equal to its float32-rounded value
+    assert np.allclose(zc32, 2.5, atol=1e-6)
+    assert np.abs(o1["depth"] - zc32.mean() * (1 - o1["T_final"])).max() < 1e-6
+    o0 = O.render(g, cam, opts)
+    assert np.abs(o0["depth"] - o1["depth"]).max() > 1e-3
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_centre_depth_mode_gradients_match_fd(oracle_mod, seed):
+    """Adjoint of the centre-depth form (d = R[2,:] mu + t_z) against central
+    differences, all parameters of a tiny scene, all outputs."""
+    O = oracle_mod
+    g, cams, opts = scenes.tiny_scene(n=5, seed=seed, sh_deg=1, C_o=3)
+    opts = dict(opts, depth_mode=1)
+    ups = scenes.upstream(cams, g["C_o"], seed=seed)
+    picks = [(k, j) for k in ("mean", "quat", "log_scale", "opacity_logit", "mask_logit", "sh", "sem")
+             for j in range(np.asarray(g[k]).size)]
+    ok = _fd_check(O, g, cams, opts, ups, picks)
+    assert ok > 0.8 * len(picks)
+
+
 def test_gradients_match_fd_workload1(oracle_mod):
     """Same check on the 2,000-Gaussian 128x128 workload, 70 sampled parameters
     stratified over every parameter kind."""
