@@ -418,6 +418,242 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     }
 }
 
+// ------------------------------------------------------------------------
+// Backward with the semantic contractions on the matrix cores (C_o padded to
+// 16 or 32).  Per wavefront (64 pixels, lane = pixel) and per group of 16
+// list entries, two FP32 products replace the per-lane semantic work:
+//   S[f][p]    = sum_c o_f[c] G_p[c]   (the semantic part of s_i, Alg.
+//                backward_render), before the group's reverse walk;
+//   dO[f][c]  += sum_p w_f[p] G_p[c]   (the semantic-logit gradient, the
+//                transpose of the semantic rendering equation), after it.
+// G_p is the upstream semantic gradient of pixel p; both of its operand
+// layouts are loaded once per tile and stay in registers.  The walk reads S
+// from, and writes w back in place to, a per-wavefront 16 x 68 LDS buffer whose
+// stride makes the MFMA-output stores, the walk and the transposed MFMA-operand
+// loads all free of bank conflicts.  The remaining 16 record slots go through
+// the wave reduce-scatter as in the plain kernel.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGrp = 16;     // list entries per MFMA group
+constexpr int kWbStride = 68; // floats per row of the S / w buffer
+
+__host__ __device__ constexpr int mfma_sem_stride(int CO) { return CO + 4; }
+
+__host__ __device__ constexpr size_t bwd_mfma_lds(int batch, int CO, int NW)
+{
+    return (size_t)batch * (64 + 4 * mfma_sem_stride(CO) + 4) + (size_t)NW * kGrp * kWbStride * 4;
+}
+
+template <int TW, int TH, int CO>
+__global__ void __launch_bounds__(TW *TH) render_bwd_mfma_kernel(
+    const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
+    const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
+    const float *__restrict__ T_final, const uint32_t *__restrict__ n_contrib, const float *__restrict__ up_rgb,
+    const float *__restrict__ gD_img, const float *__restrict__ up_kmap, const float *__restrict__ up_sem,
+    float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, int centre_depth)
+{
+    static_assert(CO == 16 || CO == 32, "MFMA backward: C_o padded to 16 or 32");
+    constexpr int NT = TW * TH, NW = NT / 64;
+    constexpr int KS = CO / 4;   // K steps over channels (S product)
+    constexpr int NCB = CO / 16; // 16-channel blocks (dO product)
+    constexpr int SS = mfma_sem_stride(CO);
+    extern __shared__ float4 smem[];
+    __shared__ uint32_t s_max;
+    float4 *srec = smem;
+    float *ssem = (float *)(smem + 4 * batch);
+    uint32_t *sid = (uint32_t *)(ssem + (size_t)batch * SS);
+    const int wave = (int)(threadIdx.x >> 6);
+    float *wb = (float *)(sid + batch) + wave * (kGrp * kWbStride);
+    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+    if (tile >= ntiles) return;
+    const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    const uint2 range = ranges[tile];
+    const float fx = (float)ti.px, fy = (float)ti.py;
+    const int64_t recbase = (int64_t)ti.v * N;
+    const int lane = __lane_id();
+    const int l16 = lane & 15, h16 = lane >> 4;
+
+    // upstream semantic gradients of the wavefront's 8 x 8 pixels, in the two
+    // MFMA operand layouts: SB[pb][s] = G[16 pb + l16][4 s + h16] (B of the S
+    // product, pixel = column) and DB[cb][s] = G[4 s + h16][16 cb + l16] (B of
+    // the dO product, pixel = reduction index)
+    const int W = cams[ti.v].W, H = cams[ti.v].H;
+    const int qx0 = ti.px - (lane & 7), qy0 = ti.py - (lane >> 3);
+    auto up_at = [&](int p, int c) -> float {
+        const int x = qx0 + (p & 7), y = qy0 + (p >> 3);
+        if (!up_sem || c >= C_o || x >= W || y >= H) return 0.f;
+        return up_sem[(int64_t)C_o * ti.off + (int64_t)c * ti.HW + (int64_t)y * W + x];
+    };
+    float SB[4][KS], DB[NCB][16];
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+        for (int st = 0; st < KS; ++st) SB[pb][st] = up_at(16 * pb + l16, 4 * st + h16);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int st = 0; st < 16; ++st) DB[cb][st] = up_at(4 * st + h16, 16 * cb + l16);
+
+    float T = 1.f, gR = 0.f, gG = 0.f, gB = 0.f, gDp = 0.f, gK = 0.f;
+    uint32_t last = 0;
+    if (ti.inside) {
+        const int64_t p = ti.pix, HW = ti.HW, off = ti.off;
+        T = T_final[off + p];
+        const uint32_t rel = n_contrib[off + p];
+        last = rel ? range.x + rel : 0u;
+        if (up_rgb) {
+            gR = up_rgb[3 * off + p];
+            gG = up_rgb[3 * off + HW + p];
+            gB = up_rgb[3 * off + 2 * HW + p];
+        }
+        gDp = gD_img[off + p];
+        if (up_kmap) gK = up_kmap[off + p];
+    }
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    if (last) atomicMax(&s_max, last);
+    __syncthreads();
+    const uint32_t end_all = s_max;
+    uint32_t wave_last = last;
+    for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, o, 64));
+    wave_last = __builtin_amdgcn_readfirstlane(wave_last);
+    float A = 0.f;
+
+    for (uint32_t end = end_all; end > range.x;) {
+        const uint32_t start = end - range.x > (uint32_t)batch ? end - (uint32_t)batch : range.x;
+        const int n = (int)(end - start);
+        __syncthreads();
+        for (int q = threadIdx.x; q < n * 4; q += NT) {
+            const uint32_t id = vals[start + (q >> 2)];
+            srec[q] = rec[(recbase + id) * 4 + (q & 3)];
+        }
+        for (int q = threadIdx.x; q < n * CO; q += NT) {
+            const int e = q / CO, c = q - e * CO;
+            const uint32_t id = vals[start + e];
+            ssem[e * SS + c] = c < C_o ? sem[(int64_t)id * C_o + c] : 0.f;
+        }
+        for (int q = threadIdx.x; q < n; q += NT) sid[q] = vals[start + q];
+        __syncthreads();
+        const int ngrp = (n + kGrp - 1) / kGrp;
+        for (int grp = ngrp - 1; grp >= 0; --grp) {
+            const int j0 = grp * kGrp;
+            if (start + (uint32_t)j0 >= wave_last) continue;  // beyond every pixel of this wavefront
+            // S[f][p] for the group's 16 entries (rows past n hold stale data; their w is 0)
+            mf4 as[4];
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) as[pb] = mf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < KS; ++st) {
+                const float a = ssem[(j0 + l16) * SS + 4 * st + h16];
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb) as[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, SB[pb][st], as[pb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) wb[(4 * h16 + r) * kWbStride + 16 * pb + l16] = as[pb][r];
+            __builtin_amdgcn_wave_barrier();
+            // reverse walk over the group
+            for (int jj = kGrp - 1; jj >= 0; --jj) {
+                const int j = j0 + jj;
+                const uint32_t entry = start + (uint32_t)j;
+                const float s_sem = wb[jj * kWbStride + lane];
+                float w = 0.f;
+                if (j < n && entry < wave_last) {
+                    const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
+                    const float dx = fx - r0.x, dy = fy - r0.y;
+                    const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
+                    const float power = -0.5f * (t1 * t1 + t2 * t2);
+                    const float G = __expf(power);
+                    const float oG = r1.y * G;
+                    const float alpha = fminf(kAlphaMax, oG);
+                    const bool contrib = entry < last && alpha >= kAlphaMin;
+                    if (__any(contrib)) {
+                        float v[16];
+#pragma unroll
+                        for (int k = 0; k < 16; ++k) v[k] = 0.f;
+                        if (contrib) {
+                            const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
+                            const float om = 1.f - alpha;
+                            T = T / om;
+                            w = alpha * T;
+                            const float B = r2.x * dx + r2.y * dy;
+                            const float Cq = r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy;
+                            const float iden = 1.f / (1.f + 2.f * B + Cq);
+                            const float d = centre_depth ? r1.w : r1.w * (1.f + B) * iden;
+                            const float s = gR * r3.y + gG * r3.z + gB * r3.w + gDp * d + gK * r1.z + s_sem;
+                            const float dalpha = T * s - A / om;
+                            A += w * s;
+                            v[13] = w * gR;
+                            v[14] = w * gG;
+                            v[15] = w * gB;
+                            const float dd = w * gDp;
+                            float dm0 = 0.f, dm1 = 0.f;
+                            if (centre_depth) {
+                                v[7] = dd;
+                            } else {
+                                const float z0 = r1.w;
+                                const float dB = dd * z0 * (Cq - 1.f) * iden * iden;
+                                const float dC = -dd * z0 * (1.f + B) * iden * iden;
+                                v[7] = dd * (1.f + B) * iden;
+                                v[8] = dB * dx;
+                                v[9] = dB * dy;
+                                v[10] = dC * dx * dx;
+                                v[11] = 2.f * dC * dx * dy;
+                                v[12] = dC * dy * dy;
+                                dm0 = -(dB * r2.x + dC * 2.f * (r2.z * dx + r2.w * dy));
+                                dm1 = -(dB * r2.y + dC * 2.f * (r2.w * dx + r3.x * dy));
+                            }
+                            if (oG < kAlphaMax) {
+                                const float dpow = dalpha * oG;
+                                v[5] = dalpha * G;
+                                v[2] = -t1 * dx * dpow;
+                                v[3] = -t1 * dy * dpow;
+                                v[4] = -t2 * dy * dpow;
+                                dm0 += t1 * r0.z * dpow;
+                                dm1 += (t1 * r0.w + t2 * r1.x) * dpow;
+                            }
+                            v[0] = dm0;
+                            v[1] = dm1;
+                        }
+                        v[6] = w * gK;
+                        const float tot = reduce_scatter<16>(v);
+                        if ((lane & 3) == 0)
+                            unsafeAtomicAdd(&grec[(recbase + sid[j]) * kRecFloats + (lane >> 2)], tot);
+                    }
+                }
+                wb[jj * kWbStride + lane] = w;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // dO[f][c] += sum_p w[f][p] G[p][c]
+            mf4 ad[NCB];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) ad[cb] = mf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < 16; ++st) {
+                const float a = wb[l16 * kWbStride + 4 * st + h16];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) ad[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, DB[cb][st], ad[cb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int f = j0 + 4 * h16 + r;
+                if (f < n) {
+                    const int64_t row = (int64_t)sid[f] * C_o;
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        const int c = 16 * cb + l16;
+                        const float val = ad[cb][r];
+                        if (c < C_o && val != 0.f) unsafeAtomicAdd(&dsem[row + c], val);
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        end = start;
+    }
+}
+
 template <int TW, int TH, int CO>
 hipError_t fwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
                         const ugs_outputs &out, int batch, bool counters, int final_buf, hipStream_t s)
@@ -439,16 +675,27 @@ hipError_t bwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
                         const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg, int batch,
                         int final_buf, hipStream_t s)
 {
-    size_t lds = (size_t)batch * (64 + 4 * CO);
     auto cams = (const DevCam *)(ws + L.cams);
     auto ranges = (const uint2 *)(ws + L.ranges);
     auto vals = (const uint32_t *)(ws + (final_buf ? L.vals1 : L.vals0));
     auto rec = (const float4 *)(ws + L.rec);
     auto grec = (float *)(ws + L.grec);
     auto gd = (const float *)(ws + L.gd);
-    hipLaunchKernelGGL((render_bwd_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s, cams,
-                       pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out.T_final, out.n_contrib, up.rgb, gd,
-                       up.kmap, up.sem, grec, dg.sem, batch, (uint32_t)pb.total_tiles, pb.depth_mode);
+    if constexpr (CO == 16 || CO == 32) {
+        // whole MFMA groups per batch, at most 64 KB of LDS per workgroup
+        constexpr int NW = TW * TH / 64;
+        int b = (batch + kGrp - 1) / kGrp * kGrp;
+        while (b > kGrp && bwd_mfma_lds(b, CO, NW) > 64 * 1024) b -= kGrp;
+        hipLaunchKernelGGL((render_bwd_mfma_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH),
+                           bwd_mfma_lds(b, CO, NW), s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o,
+                           out.T_final, out.n_contrib, up.rgb, gd, up.kmap, up.sem, grec, dg.sem, b,
+                           (uint32_t)pb.total_tiles, pb.depth_mode);
+    } else {
+        size_t lds = (size_t)batch * (64 + 4 * CO);
+        hipLaunchKernelGGL((render_bwd_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s,
+                           cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out.T_final, out.n_contrib, up.rgb, gd,
+                           up.kmap, up.sem, grec, dg.sem, batch, (uint32_t)pb.total_tiles, pb.depth_mode);
+    }
     return hipGetLastError();
 }
 

@@ -29,6 +29,14 @@ def small_workload(kind, seed=0):
         cam = scenes.camera(200, 150, 187.5, 187.5, 100, 75,
                             np.array([[0.0, -1.0, 0.0], [0.0, 0.0, -1.0], [1.0, 0.0, 0.0]]), [0, 0, 2.5])
         return scenes.make_scene(2, r=seed, N=20000, views=[cam])
+    if kind == "w2c12":
+        # 12 semantic channels: padded to 16 inside the kernels, so the padding
+        # lanes of every channel block are exercised
+        g, cams, o = small_workload("w2s", seed)
+        g = dict(g)
+        g["sem"] = np.ascontiguousarray(np.asarray(g["sem"]).reshape(g["N"], -1)[:, :12])
+        g["C_o"] = 12
+        return g, cams, o
     if kind == "w3s":
         cam = scenes.camera(240, 136, 225, 225, 120, 68,
                             np.array([[0.0, -1.0, 0.0], [0.0, 0.0, -1.0], [1.0, 0.0, 0.0]]), [0, 0, 2.5])
