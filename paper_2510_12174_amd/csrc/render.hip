@@ -100,6 +100,67 @@ __device__ __forceinline__ float reduce_scatter(const float (&x)[NV])
     return z[0];
 }
 
+// 1/x: hardware reciprocal (1 ulp) refined by one Newton step.
+__device__ __forceinline__ float rcp_nr(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.f), r);
+}
+
+// One reverse step of Alg. backward_render for one pixel and one list entry.
+// Restores T (T <- T / (1 - alpha)), advances the running sum A of w_j s_j
+// over the later fragments, and fills v[0..15] with this pixel's share of the
+// entry's gradient record (mean2d 0-1, Cholesky conic 2-4, opacity 5,
+// gradient factor 6, depth coefficients z0 7, beta 8-9, gamma 10-12, colour
+// 13-15); returns the blending weight w.  s_sem is the semantic part of s_i.
+// The depth is d = z0 (1 + B) / (1 + 2B + Cq) (the ray-ellipsoid midpoint in
+// the per-record quadric form); kd = 0 selects the centre depth d = z0.
+// Branch-free: a lane with contrib == false gets w = 0 and v = 0 and keeps T
+// and A.
+__device__ __forceinline__ float frag_adjoint(bool contrib, float4 r0, float4 r1, float4 r2, float4 r3, float dx,
+                                              float dy, float t1, float t2, float G, float oG, float alpha,
+                                              float s_sem, float gR, float gG, float gB, float gDp, float gK,
+                                              float kd, float &T, float &A, float (&v)[16])
+{
+    const float rom = rcp_nr(1.f - alpha);
+    const float Tn = contrib ? T * rom : T;
+    const float w = contrib ? alpha * Tn : 0.f;
+    const float B = kd * (r2.x * dx + r2.y * dy);
+    const float Cq = kd * (r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy);
+    const float iden = rcp_nr(1.f + 2.f * B + Cq);
+    const float z0 = r1.w;
+    const float d = z0 * (1.f + B) * iden;
+    const float s = gR * r3.y + gG * r3.z + gB * r3.w + gDp * d + gK * r1.z + s_sem;
+    const float dalpha = contrib ? Tn * s - A * rom : 0.f;
+    A += w * s;
+    T = Tn;
+    v[13] = w * gR;
+    v[14] = w * gG;
+    v[15] = w * gB;
+    v[6] = w * gK;
+    const float dd = w * gDp;
+    const float i2 = iden * iden;
+    const float dB = kd * dd * z0 * (Cq - 1.f) * i2;
+    const float dC = -kd * dd * z0 * (1.f + B) * i2;
+    v[7] = dd * (1.f + B) * iden;
+    v[8] = dB * dx;
+    v[9] = dB * dy;
+    v[10] = dC * dx * dx;
+    v[11] = 2.f * dC * dx * dy;
+    v[12] = dC * dy * dy;
+    // alpha = min(0.99, o G): no gradient through the clamp
+    const bool free_ = oG < kAlphaMax;
+    const float dpow = free_ ? dalpha * oG : 0.f;
+    v[5] = free_ ? dalpha * G : 0.f;
+    v[2] = -t1 * dx * dpow;
+    v[3] = -t1 * dy * dpow;
+    v[4] = -t2 * dy * dpow;
+    // the pixel offset is (pixel - mean2d): d/d(mean2d) = -d/d(dx, dy)
+    v[0] = t1 * r0.z * dpow - (dB * r2.x + dC * 2.f * (r2.z * dx + r2.w * dy));
+    v[1] = (t1 * r0.w + t2 * r1.x) * dpow - (dB * r2.y + dC * 2.f * (r2.w * dx + r3.x * dy));
+    return w;
+}
+
 struct TileInfo {
     int v, px, py;
     bool inside;
@@ -170,6 +231,7 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
     for (int c = 0; c < (CO > 0 ? CO : 1); ++c) acc[c] = 0.f;
     uint32_t last = 0, n_eval = 0, n_con = 0;
     bool done = !ti.inside;
+    const float kd = centre_depth ? 0.f : 1.f;
 
     for (uint32_t start = range.x; start < range.y; start += (uint32_t)batch) {
         if (__syncthreads_count(done) == NT) break;
@@ -191,9 +253,9 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
                     break;
                 }
                 const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
-                const float B = r2.x * dx + r2.y * dy;
-                const float Cq = r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy;
-                const float d = centre_depth ? r1.w : r1.w * (1.f + B) / (1.f + 2.f * B + Cq);
+                const float B = kd * (r2.x * dx + r2.y * dy);
+                const float Cq = kd * (r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy);
+                const float d = r1.w * (1.f + B) * rcp_nr(1.f + 2.f * B + Cq);
                 const double w = (double)alpha * T;
                 const float wf = (float)w;
                 cr += wf * r3.y;
@@ -329,6 +391,7 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, o, 64));
     wave_last = __builtin_amdgcn_readfirstlane(wave_last);
     float A = 0.f;
+    const float kd = centre_depth ? 0.f : 1.f;
 
     for (uint32_t end = end_all; end > range.x;) {
         const uint32_t start = end - range.x > (uint32_t)batch ? end - (uint32_t)batch : range.x;
@@ -348,68 +411,20 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
             const float alpha = fminf(kAlphaMax, oG);
             const bool contrib = entry < last && alpha >= kAlphaMin;
             if (!__any(contrib)) continue;
-            float v[16];
+            float s_sem = 0.f;
+            if constexpr (CO > 0) {
+                const float4 *s4 = (const float4 *)(ssem + j * CO);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) v[k] = 0.f;
-            float w = 0.f;
-            if (contrib) {
-                const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
-                const float om = 1.f - alpha;
-                T = T / om;
-                w = alpha * T;
-                const float B = r2.x * dx + r2.y * dy;
-                const float Cq = r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy;
-                const float iden = 1.f / (1.f + 2.f * B + Cq);
-                const float d = centre_depth ? r1.w : r1.w * (1.f + B) * iden;
-                float s = gR * r3.y + gG * r3.z + gB * r3.w + gDp * d + gK * r1.z;
-                if constexpr (CO > 0) {
-                    const float4 *s4 = (const float4 *)(ssem + j * CO);
-#pragma unroll
-                    for (int c = 0; c < CO / 4; ++c) {
-                        float4 o = s4[c];
-                        s += gO[4 * c] * o.x + gO[4 * c + 1] * o.y + gO[4 * c + 2] * o.z + gO[4 * c + 3] * o.w;
-                    }
+                for (int c = 0; c < CO / 4; ++c) {
+                    float4 o = s4[c];
+                    s_sem += gO[4 * c] * o.x + gO[4 * c + 1] * o.y + gO[4 * c + 2] * o.z + gO[4 * c + 3] * o.w;
                 }
-                const float dalpha = T * s - A / om;
-                A += w * s;
-                // colour
-                v[13] = w * gR;
-                v[14] = w * gG;
-                v[15] = w * gB;
-                const float dd = w * gDp;
-                float dm0 = 0.f, dm1 = 0.f;
-                if (centre_depth) {
-                    v[7] = dd;  // d = z0
-                } else {
-                    // depth: d = z0 (1 + B) / (1 + 2B + Cq)
-                    const float z0 = r1.w;
-                    const float dB = dd * z0 * (Cq - 1.f) * iden * iden;
-                    const float dC = -dd * z0 * (1.f + B) * iden * iden;
-                    v[7] = dd * (1.f + B) * iden;     // z0
-                    v[8] = dB * dx;                    // beta.x
-                    v[9] = dB * dy;                    // beta.y
-                    v[10] = dC * dx * dx;              // gam.a
-                    v[11] = 2.f * dC * dx * dy;        // gam.b
-                    v[12] = dC * dy * dy;              // gam.c
-                    // d depth / d(dx, dy); the pixel offset is (pixel - mean2d)
-                    dm0 = -(dB * r2.x + dC * 2.f * (r2.z * dx + r2.w * dy));
-                    dm1 = -(dB * r2.y + dC * 2.f * (r2.w * dx + r3.x * dy));
-                }
-                if (oG < kAlphaMax) {
-                    const float dpow = dalpha * oG;
-                    v[5] = dalpha * G;         // opacity
-                    v[2] = -t1 * dx * dpow;    // l11
-                    v[3] = -t1 * dy * dpow;    // l21
-                    v[4] = -t2 * dy * dpow;    // l22
-                    dm0 += t1 * r0.z * dpow;
-                    dm1 += (t1 * r0.w + t2 * r1.x) * dpow;
-                }
-                v[0] = dm0;
-                v[1] = dm1;
             }
+            float v[16];
+            const float w = frag_adjoint(contrib, r0, r1, srec[4 * j + 2], srec[4 * j + 3], dx, dy, t1, t2, G, oG,
+                                         alpha, s_sem, gR, gG, gB, gDp, gK, kd, T, A, v);
             // per-fragment values: slots 0..15 are the gradient record (slot 6 the
             // gradient factor), slots 16..16+C_o the semantic logits
-            v[6] = w * gK;
             const uint32_t id = vals[entry];
             const int64_t ridx = recbase + id;
             emit_groups<0, 16 + CO, CO>(v, w, gO, lane, grec + ridx * kRecFloats, dsem + (int64_t)id * C_o, C_o);
@@ -518,6 +533,7 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_mfma_kernel(
     for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, o, 64));
     wave_last = __builtin_amdgcn_readfirstlane(wave_last);
     float A = 0.f;
+    const float kd = centre_depth ? 0.f : 1.f;
 
     for (uint32_t end = end_all; end > range.x;) {
         const uint32_t start = end - range.x > (uint32_t)batch ? end - (uint32_t)batch : range.x;
@@ -570,53 +586,8 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_mfma_kernel(
                     const bool contrib = entry < last && alpha >= kAlphaMin;
                     if (__any(contrib)) {
                         float v[16];
-#pragma unroll
-                        for (int k = 0; k < 16; ++k) v[k] = 0.f;
-                        if (contrib) {
-                            const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
-                            const float om = 1.f - alpha;
-                            T = T / om;
-                            w = alpha * T;
-                            const float B = r2.x * dx + r2.y * dy;
-                            const float Cq = r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy;
-                            const float iden = 1.f / (1.f + 2.f * B + Cq);
-                            const float d = centre_depth ? r1.w : r1.w * (1.f + B) * iden;
-                            const float s = gR * r3.y + gG * r3.z + gB * r3.w + gDp * d + gK * r1.z + s_sem;
-                            const float dalpha = T * s - A / om;
-                            A += w * s;
-                            v[13] = w * gR;
-                            v[14] = w * gG;
-                            v[15] = w * gB;
-                            const float dd = w * gDp;
-                            float dm0 = 0.f, dm1 = 0.f;
-                            if (centre_depth) {
-                                v[7] = dd;
-                            } else {
-                                const float z0 = r1.w;
-                                const float dB = dd * z0 * (Cq - 1.f) * iden * iden;
-                                const float dC = -dd * z0 * (1.f + B) * iden * iden;
-                                v[7] = dd * (1.f + B) * iden;
-                                v[8] = dB * dx;
-                                v[9] = dB * dy;
-                                v[10] = dC * dx * dx;
-                                v[11] = 2.f * dC * dx * dy;
-                                v[12] = dC * dy * dy;
-                                dm0 = -(dB * r2.x + dC * 2.f * (r2.z * dx + r2.w * dy));
-                                dm1 = -(dB * r2.y + dC * 2.f * (r2.w * dx + r3.x * dy));
-                            }
-                            if (oG < kAlphaMax) {
-                                const float dpow = dalpha * oG;
-                                v[5] = dalpha * G;
-                                v[2] = -t1 * dx * dpow;
-                                v[3] = -t1 * dy * dpow;
-                                v[4] = -t2 * dy * dpow;
-                                dm0 += t1 * r0.z * dpow;
-                                dm1 += (t1 * r0.w + t2 * r1.x) * dpow;
-                            }
-                            v[0] = dm0;
-                            v[1] = dm1;
-                        }
-                        v[6] = w * gK;
+                        w = frag_adjoint(contrib, r0, r1, srec[4 * j + 2], srec[4 * j + 3], dx, dy, t1, t2, G, oG,
+                                         alpha, s_sem, gR, gG, gB, gDp, gK, kd, T, A, v);
                         const float tot = reduce_scatter<16>(v);
                         if ((lane & 3) == 0)
                             unsafeAtomicAdd(&grec[(recbase + sid[j]) * kRecFloats + (lane >> 2)], tot);
