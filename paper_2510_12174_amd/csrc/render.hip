@@ -436,27 +436,45 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
 // ------------------------------------------------------------------------
 // Backward with the semantic contractions on the matrix cores (C_o padded to
 // 16 or 32).  Per wavefront (64 pixels, lane = pixel) and per group of 16
-// list entries, two FP32 products replace the per-lane semantic work:
+// list entries, two products replace the per-lane semantic work:
 //   S[f][p]    = sum_c o_f[c] G_p[c]   (the semantic part of s_i, Alg.
 //                backward_render), before the group's reverse walk;
 //   dO[f][c]  += sum_p w_f[p] G_p[c]   (the semantic-logit gradient, the
 //                transpose of the semantic rendering equation), after it.
-// G_p is the upstream semantic gradient of pixel p; both of its operand
-// layouts are loaded once per tile and stay in registers.  The walk reads S
-// from, and writes w back in place to, a per-wavefront 16 x 68 LDS buffer whose
-// stride makes the MFMA-output stores, the walk and the transposed MFMA-operand
-// loads all free of bank conflicts.  The remaining 16 record slots go through
-// the wave reduce-scatter as in the plain kernel.
+// G_p is the upstream semantic gradient of pixel p.  Both products run on
+// bf16 MFMAs with every FP32 operand split as x = hi + lo (hi = bf16(x),
+// lo = bf16(x - hi)) and three products per tile (hi hi + hi lo + lo hi)
+// accumulated in FP32: the dropped lo lo term and the residual of the split
+// are below 2^-16 relative, far inside the FP32-level tolerance, at a sixth of
+// the matrix-core time of FP32 MFMAs.  The G operands are split once per tile
+// and stay in registers; the semantic features are split when staged.  The
+// walk reads S from, and writes w back in place to, a per-wavefront 16 x 68
+// FP32 LDS buffer.  The 16 record slots go through the wave reduce-scatter
+// as in the plain kernel.
 typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int kGrp = 16;     // list entries per MFMA group
-constexpr int kWbStride = 68; // floats per row of the S / w buffer
+constexpr int kGrp = 16;      // list entries per MFMA group
+constexpr int kWbStride = 68;  // floats per row of the S / w buffer
+constexpr int kSemRow = 72;    // bf16 per staged feature row: 32 hi, 32 lo, 8 pad
 
-__host__ __device__ constexpr int mfma_sem_stride(int CO) { return CO + 4; }
-
-__host__ __device__ constexpr size_t bwd_mfma_lds(int batch, int CO, int NW)
+__host__ __device__ constexpr size_t bwd_mfma_lds(int batch, int NW)
 {
-    return (size_t)batch * (64 + 4 * mfma_sem_stride(CO) + 4) + (size_t)NW * kGrp * kWbStride * 4;
+    return (size_t)batch * (64 + 2 * kSemRow + 4) + (size_t)NW * kGrp * kWbStride * 4;
+}
+
+__device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo)
+{
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}
+
+__device__ __forceinline__ mf4 mfma3(const bf8 &ah, const bf8 &al, const bf8 &bh, const bf8 &bl, mf4 c)
+{
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    return c;
 }
 
 template <int TW, int TH, int CO>
@@ -468,15 +486,13 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_mfma_kernel(
     float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, int centre_depth)
 {
     static_assert(CO == 16 || CO == 32, "MFMA backward: C_o padded to 16 or 32");
-    constexpr int NT = TW * TH, NW = NT / 64;
-    constexpr int KS = CO / 4;   // K steps over channels (S product)
-    constexpr int NCB = CO / 16; // 16-channel blocks (dO product)
-    constexpr int SS = mfma_sem_stride(CO);
+    constexpr int NT = TW * TH;
+    constexpr int NCB = CO / 16;  // 16-channel blocks of the dO product
     extern __shared__ float4 smem[];
     __shared__ uint32_t s_max;
     float4 *srec = smem;
-    float *ssem = (float *)(smem + 4 * batch);
-    uint32_t *sid = (uint32_t *)(ssem + (size_t)batch * SS);
+    __bf16 *ssem = (__bf16 *)(smem + 4 * batch);  // [batch][kSemRow]: hi c0..31, lo c0..31
+    uint32_t *sid = (uint32_t *)(ssem + (size_t)batch * kSemRow);
     const int wave = (int)(threadIdx.x >> 6);
     float *wb = (float *)(sid + batch) + wave * (kGrp * kWbStride);
     const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
@@ -488,10 +504,10 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_mfma_kernel(
     const int lane = __lane_id();
     const int l16 = lane & 15, h16 = lane >> 4;
 
-    // upstream semantic gradients of the wavefront's 8 x 8 pixels, in the two
-    // MFMA operand layouts: SB[pb][s] = G[16 pb + l16][4 s + h16] (B of the S
-    // product, pixel = column) and DB[cb][s] = G[4 s + h16][16 cb + l16] (B of
-    // the dO product, pixel = reduction index)
+    // upstream semantic gradients of the wavefront's 8 x 8 pixels, split, in the
+    // two B-operand layouts: SB[pb] = G[16 pb + l16][8 h16 + e] (S product,
+    // pixel = column, channel = reduction index) and DB[kk][cb] =
+    // G[32 kk + 8 h16 + e][16 cb + l16] (dO product, pixel = reduction index)
     const int W = cams[ti.v].W, H = cams[ti.v].H;
     const int qx0 = ti.px - (lane & 7), qy0 = ti.py - (lane >> 3);
     auto up_at = [&](int p, int c) -> float {
@@ -499,15 +515,27 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_mfma_kernel(
         if (!up_sem || c >= C_o || x >= W || y >= H) return 0.f;
         return up_sem[(int64_t)C_o * ti.off + (int64_t)c * ti.HW + (int64_t)y * W + x];
     };
-    float SB[4][KS], DB[NCB][16];
+    bf8 SBh[4], SBl[4], DBh[2][NCB], DBl[2][NCB];
 #pragma unroll
     for (int pb = 0; pb < 4; ++pb)
 #pragma unroll
-        for (int st = 0; st < KS; ++st) SB[pb][st] = up_at(16 * pb + l16, 4 * st + h16);
+        for (int e = 0; e < 8; ++e) {
+            __bf16 h, l;
+            split_bf16(up_at(16 * pb + l16, 8 * h16 + e), h, l);
+            SBh[pb][e] = h;
+            SBl[pb][e] = l;
+        }
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
+    for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-        for (int st = 0; st < 16; ++st) DB[cb][st] = up_at(4 * st + h16, 16 * cb + l16);
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                __bf16 h, l;
+                split_bf16(up_at(32 * kk + 8 * h16 + e, 16 * cb + l16), h, l);
+                DBh[kk][cb][e] = h;
+                DBl[kk][cb][e] = l;
+            }
 
     float T = 1.f, gR = 0.f, gG = 0.f, gB = 0.f, gDp = 0.f, gK = 0.f;
     uint32_t last = 0;
@@ -543,10 +571,14 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_mfma_kernel(
             const uint32_t id = vals[start + (q >> 2)];
             srec[q] = rec[(recbase + id) * 4 + (q & 3)];
         }
-        for (int q = threadIdx.x; q < n * CO; q += NT) {
-            const int e = q / CO, c = q - e * CO;
+        // features, split: 32 channels per row (zero beyond C_o)
+        for (int q = threadIdx.x; q < n * 32; q += NT) {
+            const int e = q >> 5, c = q & 31;
             const uint32_t id = vals[start + e];
-            ssem[e * SS + c] = c < C_o ? sem[(int64_t)id * C_o + c] : 0.f;
+            __bf16 h, l;
+            split_bf16(c < C_o ? sem[(int64_t)id * C_o + c] : 0.f, h, l);
+            ssem[e * kSemRow + c] = h;
+            ssem[e * kSemRow + 32 + c] = l;
         }
         for (int q = threadIdx.x; q < n; q += NT) sid[q] = vals[start + q];
         __syncthreads();
@@ -555,19 +587,16 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_mfma_kernel(
             const int j0 = grp * kGrp;
             if (start + (uint32_t)j0 >= wave_last) continue;  // beyond every pixel of this wavefront
             // S[f][p] for the group's 16 entries (rows past n hold stale data; their w is 0)
-            mf4 as[4];
+            {
+                const __bf16 *row = ssem + (j0 + l16) * kSemRow + 8 * h16;
+                const bf8 ah = *(const bf8 *)row, al = *(const bf8 *)(row + 32);
 #pragma unroll
-            for (int pb = 0; pb < 4; ++pb) as[pb] = mf4{0.f, 0.f, 0.f, 0.f};
+                for (int pb = 0; pb < 4; ++pb) {
+                    const mf4 d = mfma3(ah, al, SBh[pb], SBl[pb], mf4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
-            for (int st = 0; st < KS; ++st) {
-                const float a = ssem[(j0 + l16) * SS + 4 * st + h16];
-#pragma unroll
-                for (int pb = 0; pb < 4; ++pb) as[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, SB[pb][st], as[pb], 0, 0, 0);
+                    for (int r = 0; r < 4; ++r) wb[(4 * h16 + r) * kWbStride + 16 * pb + l16] = d[r];
+                }
             }
-#pragma unroll
-            for (int pb = 0; pb < 4; ++pb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) wb[(4 * h16 + r) * kWbStride + 16 * pb + l16] = as[pb][r];
             __builtin_amdgcn_wave_barrier();
             // reverse walk over the group
             for (int jj = kGrp - 1; jj >= 0; --jj) {
@@ -596,15 +625,25 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_mfma_kernel(
                 wb[jj * kWbStride + lane] = w;
             }
             __builtin_amdgcn_wave_barrier();
-            // dO[f][c] += sum_p w[f][p] G[p][c]
+            // dO[f][c] += sum_p w[f][p] G[p][c]: A = w rows, split on the fly
             mf4 ad[NCB];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) ad[cb] = mf4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int st = 0; st < 16; ++st) {
-                const float a = wb[l16 * kWbStride + 4 * st + h16];
+            for (int kk = 0; kk < 2; ++kk) {
+                const float *src = wb + l16 * kWbStride + 32 * kk + 8 * h16;
+                const float4 x0 = *(const float4 *)src, x1 = *(const float4 *)(src + 4);
+                const float xs[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+                bf8 ah, al;
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) ad[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, DB[cb][st], ad[cb], 0, 0, 0);
+                for (int e = 0; e < 8; ++e) {
+                    __bf16 h, l;
+                    split_bf16(xs[e], h, l);
+                    ah[e] = h;
+                    al[e] = l;
+                }
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) ad[cb] = mfma3(ah, al, DBh[kk][cb], DBl[kk][cb], ad[cb]);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -656,9 +695,9 @@ hipError_t bwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
         // whole MFMA groups per batch, at most 64 KB of LDS per workgroup
         constexpr int NW = TW * TH / 64;
         int b = (batch + kGrp - 1) / kGrp * kGrp;
-        while (b > kGrp && bwd_mfma_lds(b, CO, NW) > 64 * 1024) b -= kGrp;
+        while (b > kGrp && bwd_mfma_lds(b, NW) > 64 * 1024) b -= kGrp;
         hipLaunchKernelGGL((render_bwd_mfma_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH),
-                           bwd_mfma_lds(b, CO, NW), s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o,
+                           bwd_mfma_lds(b, NW), s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o,
                            out.T_final, out.n_contrib, up.rgb, gd, up.kmap, up.sem, grec, dg.sem, b,
                            (uint32_t)pb.total_tiles, pb.depth_mode);
     } else {
