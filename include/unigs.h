@@ -184,7 +184,9 @@ int ugs_step_replay(ugs_ctx *ctx, void *stream);
 
 /* Times the candidate (tile shape, batch) configurations on the given problem
  * (one forward+backward each, after a warm-up), checks that every candidate's
- * forward outputs are bit-identical to the first one's, keeps the fastest in the
+ * forward outputs are bit-identical to the first one's (the semantic map to
+ * rounding: for 9..32 channels its sums run on the matrix cores in groups of
+ * list entries that depend on the tile shape), keeps the fastest in the
  * context options and returns it in *chosen (and its time in *ms if non-NULL).
  * Synchronous.  Uses `out` and `dg` as scratch (dg is zeroed afterwards).
  * Candidates whose pair count exceeds the workspace capacity are skipped

@@ -286,7 +286,28 @@ __global__ void hash_floats(const float *p, int64_t n, unsigned long long salt, 
     if (__lane_id() == 0 && h) atomicXor(out, h);
 }
 
-__global__ void zero_u64(unsigned long long *p) { *p = 0; }
+__global__ void zero_u64(unsigned long long *p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// Sum and absolute sum (FP64) of n floats: a rounding-tolerant fingerprint.
+__global__ void sum_floats(const float *p, int64_t n, double *out)
+{
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        a += (double)p[i];
+        b += fabs((double)p[i]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    if (__lane_id() == 0) {
+        atomicAdd(&out[0], a);
+        atomicAdd(&out[1], b);
+    }
+}
 
 int upload_cams(ugs_ctx *ctx, const std::vector<DevCam> &dcs, hipStream_t s)
 {
@@ -711,6 +732,7 @@ int ugs_autotune(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, i
     HIPCHK(ctx, hipEventCreate(&e0));
     HIPCHK(ctx, hipEventCreate(&e1));
     unsigned long long ref_hash = 0;
+    double ref_sum = 0.0, ref_abs = 0.0;
     float best = 1e30f;
     ugs_options best_opt = base;
     int rc = UGS_OK;
@@ -743,27 +765,36 @@ int ugs_autotune(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, i
             tmin = std::min(tmin, t);
         }
         if (rc) break;
-        // fingerprint the tile-independent forward outputs
+        // fingerprint the tile-independent forward outputs: bit for bit, except
+        // the semantic map, whose matrix-core sums group list entries per tile
+        // (compared by its FP64 sum, to 1e-6 of its absolute sum)
         auto hp = (unsigned long long *)(ctx->ws + ctx->L.counters + sizeof(DevCounters));
-        hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, hp);
+        hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, s, hp, 3);
         const int64_t P = ctx->pb.total_pix;
         struct { const float *p; int64_t n; } maps[] = {{out->rgb, 3 * P}, {out->depth, P}, {out->kmap, P},
-                                                         {out->normal, 3 * P}, {out->T_final, P},
-                                                         {out->sem, (int64_t)g->C_o * P}};
+                                                         {out->normal, 3 * P}, {out->T_final, P}};
         unsigned long long salt = 1;
         for (auto &m : maps) {
             if (m.n > 0 && m.p) hipLaunchKernelGGL(hash_floats, dim3(1024), dim3(256), 0, s, m.p, m.n, salt * 0x9e3779b97f4a7c15ull, hp);
             ++salt;
         }
-        unsigned long long h = 0;
-        if (hipMemcpyAsync(&h, hp, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        if (g->C_o > 0 && out->sem)
+            hipLaunchKernelGGL(sum_floats, dim3(1024), dim3(256), 0, s, out->sem, (int64_t)g->C_o * P, (double *)(hp + 1));
+        unsigned long long hs[3] = {0, 0, 0};
+        if (hipMemcpyAsync(hs, hp, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
             rc = UGS_ERR_HIP;
             break;
         }
+        const unsigned long long h = hs[0];
+        double ssum, sabs;
+        memcpy(&ssum, &hs[1], 8);
+        memcpy(&sabs, &hs[2], 8);
         if (!have_ref) {
             ref_hash = h;
+            ref_sum = ssum;
+            ref_abs = sabs;
             have_ref = true;
-        } else if (h != ref_hash) {
+        } else if (h != ref_hash || fabs(ssum - ref_sum) > 1e-6 * ref_abs + 1e-30) {
             mismatch = true;
         }
         if (tmin < best) {

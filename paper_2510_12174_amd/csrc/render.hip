@@ -664,19 +664,225 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_mfma_kernel(
     }
 }
 
+// ------------------------------------------------------------------------
+// Forward with the semantic blend on the matrix cores (C_o padded to 16 or 32).
+// The walk is the plain kernel's, without the per-fragment channel loop: each
+// lane writes its FP32 weight w_i (0 when the entry does not contribute) to a
+// per-wavefront 16 x 68 LDS buffer, and after every 16 entries the wavefront
+// adds O~[p][c] += sum_f w_f[p] o_f[c] with bf16 MFMAs (16x16x16) on hi/lo
+// splits of both operands (three products, FP32 accumulation, as in the
+// backward).  The accumulators O~ stay in the MFMA output layout until the
+// end of the tile.  Colour, depth, gradient factor, T_final and n_contrib are
+// computed exactly as in the plain kernel; the semantic map differs from it
+// by rounding only (the matrix-core sums group the list entries per tile).
+typedef short bs4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split_bf16_bits(float x, short &hi, short &lo)
+{
+    const __bf16 h = (__bf16)x;
+    const __bf16 l = (__bf16)(x - (float)h);
+    hi = __builtin_bit_cast(short, h);
+    lo = __builtin_bit_cast(short, l);
+}
+
+__device__ __forceinline__ mf4 mfma3k16(const bs4 &ah, const bs4 &al, const bs4 &bh, const bs4 &bl, mf4 c)
+{
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+    return c;
+}
+
+__host__ __device__ constexpr int fwd_semT_stride(int batch) { return batch + 4; }
+
+__host__ __device__ constexpr size_t fwd_mfma_lds(int batch, int CO, int NW)
+{
+    return (size_t)batch * 64 + (size_t)2 * CO * fwd_semT_stride(batch) * 2 + (size_t)NW * kGrp * kWbStride * 4;
+}
+
+template <int TW, int TH, int CO>
+__global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
+    const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
+    const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
+    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles, int centre_depth)
+{
+    static_assert(CO == 16 || CO == 32, "MFMA forward: C_o padded to 16 or 32");
+    constexpr int NT = TW * TH;
+    constexpr int NCB = CO / 16;
+    extern __shared__ float4 smem[];
+    float4 *srec = smem;
+    const int RS = fwd_semT_stride(batch);
+    short *semh = (short *)(smem + 4 * batch);  // [CO][RS]: bf16 hi of o_f[c], transposed
+    short *seml = semh + CO * RS;
+    const int wave = (int)(threadIdx.x >> 6);
+    float *wb = (float *)(seml + CO * RS) + wave * (kGrp * kWbStride);
+    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+    if (tile >= ntiles) return;
+    const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    const uint2 range = ranges[tile];
+    const float fx = (float)ti.px, fy = (float)ti.py;
+    const int64_t recbase = (int64_t)ti.v * N;
+    const int lane = __lane_id();
+    const int l16 = lane & 15, h16 = lane >> 4;
+
+    double T = 1.0, D = 0.0;
+    float cr = 0.f, cg = 0.f, cb = 0.f, K = 0.f;
+    mf4 acc[4][NCB];
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+        for (int q = 0; q < NCB; ++q) acc[pb][q] = mf4{0.f, 0.f, 0.f, 0.f};
+    uint32_t last = 0, n_eval = 0, n_con = 0;
+    bool done = !ti.inside;
+    const float kd = centre_depth ? 0.f : 1.f;
+
+    for (uint32_t start = range.x; start < range.y; start += (uint32_t)batch) {
+        if (__syncthreads_count(done) == NT) break;
+        const int n = (int)min((uint32_t)batch, range.y - start);
+        for (int q = threadIdx.x; q < n * 4; q += NT) {
+            const uint32_t id = vals[start + (q >> 2)];
+            srec[q] = rec[(recbase + id) * 4 + (q & 3)];
+        }
+        // features, split and transposed: column f of row c (zero beyond C_o and past n)
+        const int ng16 = (n + kGrp - 1) / kGrp * kGrp;
+        for (int q = threadIdx.x; q < ng16 * CO; q += NT) {
+            const int e = q / CO, c = q - e * CO;
+            float x = 0.f;
+            if (e < n && c < C_o) x = sem[(int64_t)vals[start + e] * C_o + c];
+            short h, l;
+            split_bf16_bits(x, h, l);
+            semh[c * RS + e] = h;
+            seml[c * RS + e] = l;
+        }
+        __syncthreads();
+        if (__all(done)) continue;  // the block may still walk this batch
+        for (int j0 = 0; j0 < n; j0 += kGrp) {
+            for (int jj = 0; jj < kGrp; ++jj) {
+                const int j = j0 + jj;
+                float wf = 0.f;
+                if (j < n && !done) {
+                    const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
+                    const float dx = fx - r0.x, dy = fy - r0.y;
+                    const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
+                    const float power = -0.5f * (t1 * t1 + t2 * t2);
+                    const float alpha = fminf(kAlphaMax, r1.y * __expf(power));
+                    ++n_eval;
+                    if (alpha >= kAlphaMin) {
+                        const double tT = T * (1.0 - (double)alpha);
+                        if (tT < kTStop) {
+                            done = true;
+                        } else {
+                            const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
+                            const float B = kd * (r2.x * dx + r2.y * dy);
+                            const float Cq = kd * (r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy);
+                            const float d = r1.w * (1.f + B) * rcp_nr(1.f + 2.f * B + Cq);
+                            const double w = (double)alpha * T;
+                            wf = (float)w;
+                            cr += wf * r3.y;
+                            cg += wf * r3.z;
+                            cb += wf * r3.w;
+                            K += wf * r1.z;
+                            D += w * (double)d;
+                            T = tT;
+                            last = start + (uint32_t)j + 1;
+                            ++n_con;
+                        }
+                    }
+                }
+                wb[jj * kWbStride + lane] = wf;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // O~[p][c] += sum_f w[f][p] o[f][c] over the 16 entries
+            bs4 bh[NCB], bl[NCB];
+#pragma unroll
+            for (int q = 0; q < NCB; ++q) {
+                const int c = 16 * q + l16;
+                bh[q] = *(const bs4 *)(semh + c * RS + j0 + 4 * h16);
+                bl[q] = *(const bs4 *)(seml + c * RS + j0 + 4 * h16);
+            }
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) {
+                bs4 ah, al;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    short h, l;
+                    split_bf16_bits(wb[(4 * h16 + e) * kWbStride + 16 * pb + l16], h, l);
+                    ah[e] = h;
+                    al[e] = l;
+                }
+#pragma unroll
+                for (int q = 0; q < NCB; ++q) acc[pb][q] = mfma3k16(ah, al, bh[q], bl[q], acc[pb][q]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (__all(done)) break;
+        }
+    }
+    if (ti.inside) {
+        const int64_t p = ti.pix, HW = ti.HW, off = ti.off;
+        out.rgb[3 * off + p] = cr;
+        out.rgb[3 * off + HW + p] = cg;
+        out.rgb[3 * off + 2 * HW + p] = cb;
+        out.depth[off + p] = (float)D;
+        out.kmap[off + p] = K;
+        out.T_final[off + p] = (float)T;
+        out.n_contrib[off + p] = last ? last - range.x : 0u;
+    }
+    // O~ from the MFMA layout: acc[pb][q][r] is pixel 16 pb + 4 h16 + r, channel 16 q + l16
+    {
+        const int W = cams[ti.v].W, H = cams[ti.v].H;
+        const int qx0 = ti.px - (lane & 7), qy0 = ti.py - (lane >> 3);
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pp = 16 * pb + 4 * h16 + r;
+                const int x = qx0 + (pp & 7), y = qy0 + (pp >> 3);
+                if (x < W && y < H) {
+#pragma unroll
+                    for (int q = 0; q < NCB; ++q) {
+                        const int c = 16 * q + l16;
+                        if (c < C_o)
+                            out.sem[(int64_t)C_o * ti.off + (int64_t)c * ti.HW + (int64_t)y * W + x] = acc[pb][q][r];
+                    }
+                }
+            }
+    }
+    if (count) {
+        unsigned long long e = n_eval, c = n_con;
+        for (int o = 32; o > 0; o >>= 1) {
+            e += __shfl_xor(e, o, 64);
+            c += __shfl_xor(c, o, 64);
+        }
+        if (__lane_id() == 0) {
+            atomicAdd(&cnt->n_eval, e);
+            atomicAdd(&cnt->n_contrib, c);
+        }
+    }
+}
+
 template <int TW, int TH, int CO>
 hipError_t fwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
                         const ugs_outputs &out, int batch, bool counters, int final_buf, hipStream_t s)
 {
-    size_t lds = (size_t)batch * (64 + 4 * CO);
     auto cams = (const DevCam *)(ws + L.cams);
     auto ranges = (const uint2 *)(ws + L.ranges);
     auto vals = (const uint32_t *)(ws + (final_buf ? L.vals1 : L.vals0));
     auto rec = (const float4 *)(ws + L.rec);
     auto cnt = (DevCounters *)(ws + L.counters);
-    hipLaunchKernelGGL((render_fwd_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s, cams,
-                       pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out, batch, cnt, (int)counters,
-                       (uint32_t)pb.total_tiles, pb.depth_mode);
+    if constexpr (CO == 16 || CO == 32) {
+        // whole MFMA groups per batch, at most 64 KB of LDS per workgroup
+        constexpr int NW = TW * TH / 64;
+        int b = (batch + kGrp - 1) / kGrp * kGrp;
+        while (b > kGrp && fwd_mfma_lds(b, CO, NW) > 64 * 1024) b -= kGrp;
+        hipLaunchKernelGGL((render_fwd_mfma_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH),
+                           fwd_mfma_lds(b, CO, NW), s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out, b,
+                           cnt, (int)counters, (uint32_t)pb.total_tiles, pb.depth_mode);
+    } else {
+        size_t lds = (size_t)batch * (64 + 4 * CO);
+        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s,
+                           cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out, batch, cnt, (int)counters,
+                           (uint32_t)pb.total_tiles, pb.depth_mode);
+    }
     return hipGetLastError();
 }
 

@@ -196,13 +196,16 @@ def test_end_to_end_normal_gradients_w1(O):
 @pytest.mark.parametrize("tile", [(8, 8), (32, 8)])
 def test_tile_shapes_bit_identical(O, tile):
     """The alpha-region rectangle makes every tile shape produce the same forward
-    outputs bit for bit."""
+    outputs bit for bit (the semantic map to rounding)."""
     g, cams, opts = Hn.small_workload("w4s")
     a, _, _ = Hn.gpu_run(g, cams, opts, tile=(16, 16))
     b, _, _ = Hn.gpu_run(g, cams, opts, tile=tile)
     for x, y in zip(a, b):
-        for k in ("rgb", "depth", "kmap", "normal", "sem", "T_final"):
+        for k in ("rgb", "depth", "kmap", "normal", "T_final"):
             assert np.array_equal(x[k], y[k]), k
+        # semantic sums run on the matrix cores in per-tile groups of list
+        # entries: equal to rounding
+        assert np.abs(x["sem"].astype(np.float64) - y["sem"]).max() <= 1e-5
 
 
 def test_batched_equals_per_view(O):
