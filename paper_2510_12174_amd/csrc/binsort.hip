@@ -269,59 +269,58 @@ __global__ void __launch_bounds__(256) radix_scan_digit(uint32_t *__restrict__ h
     if (threadIdx.x == 0) digit_tot[blockIdx.x] = tot;
 }
 
-// Stable scatter by one wavefront: walks its chunk in order, 64 keys at a time
-// (loaded kSortUnroll groups ahead).
-// A key's rank is the number of lanes below it with the same digit (eight
-// ballots) plus the digit's running count in LDS, which the lowest lane of each
-// digit group advances afterwards; a single wavefront needs no barriers.
+// Stable scatter of one block's chunk, in tiles of kScatTile keys.  Each of
+// the four wavefronts ranks its quarter of the tile 64 keys at a time (a key's
+// rank among equal digits below it in the wavefront comes from eight ballots,
+// plus the wavefront's running per-digit count in LDS); the per-digit counts
+// of the four wavefronts and of the tile are then scanned, every key is placed
+// at its digit-sorted position in an LDS copy of the tile, and the tile is
+// written out in that order, so each digit's run of keys leaves as consecutive
+// addresses instead of as scattered single words.
+constexpr int kScatThreads = 256;
+constexpr int kScatRounds = 16;                          // 64-key rounds per wavefront and tile
+constexpr int kScatTile = kScatThreads * kScatRounds;    // keys per tile
+constexpr int kScatQuarter = kScatTile / 4;              // keys per wavefront and tile
+
 template <typename K>
-__global__ void __launch_bounds__(kSortThreads) radix_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
+__global__ void __launch_bounds__(kScatThreads) radix_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                               K *__restrict__ kout, uint32_t *__restrict__ vout,
                                                               const uint32_t *__restrict__ n_dev, int shift,
                                                               const uint32_t *__restrict__ hist,
                                                               const uint32_t *__restrict__ digit_tot)
 {
-    __shared__ uint32_t base[256], dex[256];
-    const int t = threadIdx.x;
-    // digit bases: exclusive scan of the digit totals (4 per lane) + this block's offset
+    __shared__ uint32_t gbase[256], loff[256], tot[256], lds4[4];
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ K skey[kScatTile];
+    __shared__ uint32_t sval[kScatTile];
+    const int t = threadIdx.x, lane = __lane_id(), wave = t >> 6;
     {
-        uint32_t d4[4], s = 0;
-        for (int k = 0; k < 4; ++k) {
-            d4[k] = digit_tot[4 * t + k];
-            s += d4[k];
-        }
-        uint32_t inc = s;
-        for (int o = 1; o < 64; o <<= 1) {
-            uint32_t y = __shfl_up(inc, o, 64);
-            if (t >= o) inc += y;
-        }
-        uint32_t ex = inc - s;
-        for (int k = 0; k < 4; ++k) {
-            dex[4 * t + k] = ex;
-            ex += d4[k];
-        }
+        // global start of each digit's run for this block
+        uint32_t total;
+        const uint32_t ex = block_excl_scan256(digit_tot[t], lds4, total);
+        gbase[t] = ex + hist[(size_t)t * kSortBlocks + blockIdx.x];
     }
-    __syncthreads();
-    for (int d = t; d < 256; d += kSortThreads) base[d] = dex[d] + hist[(size_t)d * kSortBlocks + blockIdx.x];
-    __syncthreads();
     const uint32_t P = *n_dev;
     const uint32_t per = ((P + kSortBlocks - 1) / kSortBlocks + 63) & ~63u;
     const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = min((uint64_t)P, b0 + per);
     const uint64_t lt = __lanemask_lt();
-    for (uint64_t tb = b0; tb < b1; tb += kSortThreads * kSortUnroll) {
-        K key[kSortUnroll];
-        uint32_t val[kSortUnroll];
+    for (uint64_t ts = b0; ts < b1; ts += kScatTile) {
+        const uint32_t nt = (uint32_t)min((uint64_t)kScatTile, b1 - ts);
+        for (int d = lane; d < 256; d += 64) wcnt[wave][d] = 0;
+        K key[kScatRounds];
+        uint32_t val[kScatRounds], pw[kScatRounds];
 #pragma unroll
-        for (int u = 0; u < kSortUnroll; ++u) {
-            const uint64_t i = tb + u * kSortThreads + t;
-            key[u] = i < b1 ? kin[i] : K(0);
-            val[u] = i < b1 ? vin[i] : 0u;
+        for (int i = 0; i < kScatRounds; ++i) {
+            const uint32_t li = (uint32_t)(wave * kScatQuarter + i * 64 + lane);
+            key[i] = li < nt ? kin[ts + li] : K(0);
+            val[i] = li < nt ? vin[ts + li] : 0u;
         }
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int u = 0; u < kSortUnroll; ++u) {
-            const uint64_t i = tb + u * kSortThreads + t;
-            const bool valid = i < b1;
-            const uint32_t d = digit_of(key[u], shift);
+        for (int i = 0; i < kScatRounds; ++i) {
+            const uint32_t li = (uint32_t)(wave * kScatQuarter + i * 64 + lane);
+            const bool valid = li < nt;
+            const uint32_t d = digit_of(key[i], shift);
             uint64_t peers = __ballot(valid);
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
@@ -329,16 +328,46 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(const K *__restric
                 peers &= ((d >> b) & 1u) ? m : ~m;
             }
             const uint32_t rank = __popcll(peers & lt);
-            uint32_t pos = 0;
-            if (valid) pos = base[d] + rank;
+            pw[i] = valid ? wcnt[wave][d] + rank : 0u;
             __builtin_amdgcn_wave_barrier();
-            if (valid && rank == 0) base[d] += __popcll(peers);
+            if (valid && rank == 0) wcnt[wave][d] += __popcll(peers);
             __builtin_amdgcn_wave_barrier();
-            if (valid) {
-                kout[pos] = key[u];
-                vout[pos] = val[u];
+        }
+        __syncthreads();
+        {
+            // per digit: offsets of the four wavefronts' keys, tile total, local start
+            const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+            wcnt[0][t] = 0;
+            wcnt[1][t] = c0;
+            wcnt[2][t] = c0 + c1;
+            wcnt[3][t] = c0 + c1 + c2;
+            const uint32_t td = c0 + c1 + c2 + c3;
+            tot[t] = td;
+            uint32_t total;
+            loff[t] = block_excl_scan256(td, lds4, total);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kScatRounds; ++i) {
+            const uint32_t li = (uint32_t)(wave * kScatQuarter + i * 64 + lane);
+            if (li < nt) {
+                const uint32_t d = digit_of(key[i], shift);
+                const uint32_t lp = loff[d] + wcnt[wave][d] + pw[i];
+                skey[lp] = key[i];
+                sval[lp] = val[i];
             }
         }
+        __syncthreads();
+        for (uint32_t i = (uint32_t)t; i < nt; i += kScatThreads) {
+            const K k = skey[i];
+            const uint32_t d = digit_of(k, shift);
+            const uint32_t g = gbase[d] + (i - loff[d]);
+            kout[g] = k;
+            vout[g] = sval[i];
+        }
+        __syncthreads();
+        gbase[t] += tot[t];
+        __syncthreads();
     }
 }
 
@@ -379,7 +408,7 @@ int radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t *n_dev, 
         hipLaunchKernelGGL(radix_hist<K>, dim3(kSortBlocks), dim3(kSortThreads), 0, s, (const K *)k[cur], n_dev, shift,
                            hist);
         hipLaunchKernelGGL(radix_scan_digit, dim3(256), dim3(256), 0, s, hist, dtot);
-        hipLaunchKernelGGL(radix_scatter<K>, dim3(kSortBlocks), dim3(kSortThreads), 0, s, (const K *)k[cur],
+        hipLaunchKernelGGL(radix_scatter<K>, dim3(kSortBlocks), dim3(kScatThreads), 0, s, (const K *)k[cur],
                            (const uint32_t *)v[cur], k[cur ^ 1], v[cur ^ 1], n_dev, shift, (const uint32_t *)hist,
                            (const uint32_t *)dtot);
         cur ^= 1;
