@@ -727,6 +727,7 @@ int ugs_autotune(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, i
         int b = auto_batch(o, g->C_o);
         cands.push_back({t[0], t[1], b});
         if (b / 2 >= 16) cands.push_back({t[0], t[1], b / 2});
+        if (b / 4 >= 16) cands.push_back({t[0], t[1], b / 4});
     }
     hipEvent_t e0, e1;
     HIPCHK(ctx, hipEventCreate(&e0));
