@@ -151,60 +151,156 @@ __global__ void __launch_bounds__(256) compact_visible(int64_t N, int64_t VN, co
 }
 
 // Tile counts in depth order (grid-stride up to the device count R).
-__global__ void __launch_bounds__(256) gather_counts(const uint32_t *__restrict__ didx,
-                                                     const uint32_t *__restrict__ touched,
-                                                     const uint32_t *__restrict__ R, uint32_t *__restrict__ out)
+
+// One depth-sorted record as the binning walks see it: rectangle, view
+// geometry and the culling data of its FP32 projection record.
+struct WalkRec {
+    uint32_t idx, gid, rx, ry, w, area, tb, tw;
+    int W, H;
+    CullGeom c;
+};
+
+__device__ __forceinline__ WalkRec walk_load(const DevCam *cams, int64_t N, uint32_t idx, const uint2 *rect,
+                                             const float4 *rec)
 {
-    const uint32_t n = *R;
-    for (uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (uint64_t)gridDim.x * 256)
-        out[r] = touched[didx[r]];
+    WalkRec k;
+    k.idx = idx;
+    const int v = (int)(idx / (uint64_t)N);
+    k.gid = (uint32_t)(idx - (uint64_t)v * N);
+    const DevCam &cam = cams[v];
+    const uint2 rc = rect[idx];
+    k.rx = rc.x & 0xffff;
+    k.ry = rc.x >> 16;
+    k.w = (rc.y & 0xffff) - k.rx;
+    k.area = k.w * ((rc.y >> 16) - k.ry);
+    k.tb = cam.tile_base;
+    k.tw = (uint32_t)cam.tiles_x;
+    k.W = cam.W;
+    k.H = cam.H;
+    k.c = cull_geom(rec[(int64_t)idx * 4], rec[(int64_t)idx * 4 + 1]);
+    return k;
 }
 
-// Pair emission, one wavefront per run of 64 depth-sorted records: the lanes
-// first load one record each, then write every record's pairs together (lane q
-// writes pairs q, q + 64, ...), so the stores are coalesced whatever the
-// footprint sizes.
-__global__ void __launch_bounds__(256) emit_pairs(const DevCam *__restrict__ cams, int64_t N,
-                                                  const uint32_t *__restrict__ didx,
-                                                  const uint32_t *__restrict__ tsorted,
-                                                  const uint32_t *__restrict__ poff, const uint2 *__restrict__ rect,
-                                                  int64_t cap, const DevCounters *__restrict__ cnt,
-                                                  uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+__device__ __forceinline__ WalkRec walk_bcast(const WalkRec &a, int k)
 {
-    if (cnt->overflow) return;
+    WalkRec b;
+    b.idx = __shfl(a.idx, k, 64);
+    b.gid = __shfl(a.gid, k, 64);
+    b.rx = __shfl(a.rx, k, 64);
+    b.ry = __shfl(a.ry, k, 64);
+    b.w = __shfl(a.w, k, 64);
+    b.area = __shfl(a.area, k, 64);
+    b.tb = __shfl(a.tb, k, 64);
+    b.tw = __shfl(a.tw, k, 64);
+    b.W = __shfl(a.W, k, 64);
+    b.H = __shfl(a.H, k, 64);
+    b.c.mx = __shfl(a.c.mx, k, 64);
+    b.c.my = __shfl(a.c.my, k, 64);
+    b.c.l11 = __shfl(a.c.l11, k, 64);
+    b.c.l21 = __shfl(a.c.l21, k, 64);
+    b.c.l22 = __shfl(a.c.l22, k, 64);
+    b.c.thr = __shfl(a.c.thr, k, 64);
+    b.c.kb = __shfl(a.c.kb, k, 64);
+    b.c.kl = __shfl(a.c.kl, k, 64);
+    return b;
+}
+
+// Tile q (row-major in the rectangle) of record k, and whether its alpha
+// ellipse reaches it.
+__device__ __forceinline__ bool walk_hit(const WalkRec &k, uint32_t q, int tile_w, int tile_h, uint32_t &tile)
+{
+    const uint32_t ty = q / k.w, tx = q - ty * k.w;
+    tile = k.tb + (k.ry + ty) * k.tw + k.rx + tx;
+    if (k.area > (uint32_t)kCullMaxTiles) return true;
+    int bx0, bx1, by0, by1;
+    tile_box((int)(k.rx + tx), (int)(k.ry + ty), tile_w, tile_h, k.W, k.H, bx0, bx1, by0, by1);
+    return cull_hits(k.c, bx0, bx1, by0, by1);
+}
+
+// Culled tile counts of the depth-sorted records, one wavefront per run of 64
+// records walking each rectangle together (lane q tests tiles q, q + 64, ...).
+// Writes the count in depth order and back to the record.
+__global__ void __launch_bounds__(256) count_culled(const DevCam *__restrict__ cams, int64_t N,
+                                                    const uint32_t *__restrict__ didx, const uint2 *__restrict__ rect,
+                                                    const float4 *__restrict__ rec, int tile_w, int tile_h,
+                                                    const DevCounters *__restrict__ cnt,
+                                                    uint32_t *__restrict__ tsorted, uint32_t *__restrict__ touched)
+{
     const uint32_t R = cnt->R;
     const int lane = __lane_id();
     const uint64_t wave0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * 256) >> 6;
     for (uint64_t base = wave0 * 64; base < R; base += nwaves * 64) {
         const uint64_t r = base + lane;
-        uint32_t nt = 0, off = 0, gid = 0, tb = 0, tw = 1, rx = 0, ry = 0, w = 1;
+        WalkRec mine;
+        mine.area = 0;
+        if (r < R) mine = walk_load(cams, N, didx[r], rect, rec);
+        uint32_t my_count = 0;
+        const int m = (int)min((uint64_t)64, (uint64_t)R - base);
+        for (int k = 0; k < m; ++k) {
+            const WalkRec kr = walk_bcast(mine, k);
+            uint32_t count = 0;
+            for (uint32_t q0 = 0; q0 < kr.area; q0 += 64) {
+                const uint32_t q = q0 + (uint32_t)lane;
+                uint32_t tile;
+                const bool hit = q < kr.area && walk_hit(kr, q, tile_w, tile_h, tile);
+                count += (uint32_t)__popcll(__ballot(hit));
+            }
+            if (lane == k) my_count = count;
+        }
+        if (r < R) {
+            tsorted[r] = my_count;
+            touched[mine.idx] = my_count;
+        }
+    }
+}
+
+// Pair emission, the same walk: the kept tiles of every record are written
+// compacted by ballot, so the stores are coalesced whatever the footprint
+// sizes.  Writes never pass the record's counted slots.
+__global__ void __launch_bounds__(256) emit_pairs(const DevCam *__restrict__ cams, int64_t N,
+                                                  const uint32_t *__restrict__ didx,
+                                                  const uint32_t *__restrict__ tsorted,
+                                                  const uint32_t *__restrict__ poff, const uint2 *__restrict__ rect,
+                                                  const float4 *__restrict__ rec, int tile_w, int tile_h,
+                                                  int64_t cap, const DevCounters *__restrict__ cnt,
+                                                  uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    if (cnt->overflow) return;
+    const uint32_t R = cnt->R;
+    const int lane = __lane_id();
+    const uint64_t lt = __lanemask_lt();
+    const uint64_t wave0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * 256) >> 6;
+    for (uint64_t base = wave0 * 64; base < R; base += nwaves * 64) {
+        const uint64_t r = base + lane;
+        WalkRec mine;
+        mine.area = 0;
+        uint32_t nt = 0, off = 0;
         if (r < R) {
             nt = tsorted[r];
             off = poff[r];
-            const uint32_t idx = didx[r];
-            const int v = (int)(idx / (uint64_t)N);
-            gid = (uint32_t)(idx - (uint64_t)v * N);
-            const DevCam &cam = cams[v];
-            const uint2 rc = rect[idx];
-            rx = rc.x & 0xffff;
-            ry = rc.x >> 16;
-            w = (rc.y & 0xffff) - rx;
-            tb = cam.tile_base;
-            tw = (uint32_t)cam.tiles_x;
             if ((uint64_t)off + nt > (uint64_t)cap) nt = 0;
+            if (nt) mine = walk_load(cams, N, didx[r], rect, rec);
         }
         const int m = (int)min((uint64_t)64, (uint64_t)R - base);
         for (int k = 0; k < m; ++k) {
             const uint32_t knt = __shfl(nt, k, 64);
             if (knt == 0) continue;
-            const uint32_t koff = __shfl(off, k, 64), kgid = __shfl(gid, k, 64), ktb = __shfl(tb, k, 64);
-            const uint32_t ktw = __shfl(tw, k, 64), krx = __shfl(rx, k, 64), kry = __shfl(ry, k, 64);
-            const uint32_t kw = __shfl(w, k, 64);
-            for (uint32_t q = lane; q < knt; q += 64) {
-                const uint32_t ty = q / kw, tx = q - ty * kw;
-                keys[koff + q] = ktb + (kry + ty) * ktw + krx + tx;
-                vals[koff + q] = kgid;
+            const uint32_t koff = __shfl(off, k, 64);
+            const WalkRec kr = walk_bcast(mine, k);
+            uint32_t done = 0;
+            for (uint32_t q0 = 0; q0 < kr.area && done < knt; q0 += 64) {
+                const uint32_t q = q0 + (uint32_t)lane;
+                uint32_t tile = 0;
+                const bool hit = q < kr.area && walk_hit(kr, q, tile_w, tile_h, tile);
+                const uint64_t mask = __ballot(hit);
+                const uint32_t slot = done + (uint32_t)__popcll(mask & lt);
+                if (hit && slot < knt) {
+                    keys[koff + slot] = tile;
+                    vals[koff + slot] = kr.gid;
+                }
+                done += (uint32_t)__popcll(mask);
             }
         }
     }
@@ -459,13 +555,13 @@ hipError_t launch_binsort(const Problem &pb, const WsLayout &L, char *ws, hipStr
     const int dcur = radix_sort<unsigned long long>(dk0, di0, dk1, di1, &cnt->R, L.depth_bits, hist, dtot, s);
     uint32_t *didx = dcur ? di1 : di0;
     // 3. tile counts in depth order, pair offsets, emission
-    hipLaunchKernelGGL(gather_counts, dim3(gs_blocks), dim3(256), 0, s, (const uint32_t *)didx,
-                       (const uint32_t *)touched, (const uint32_t *)&cnt->R, tsorted);
+    hipLaunchKernelGGL(count_culled, dim3(gs_blocks), dim3(256), 0, s, cams, L.N, (const uint32_t *)didx, rect, rec,
+                       pb.tile_w, pb.tile_h, (const DevCounters *)cnt, tsorted, touched);
     scan(ScanIn{tsorted, VN, &cnt->R, 0}, L.nb_scan, part, poff, L.pair_cap, &cnt->P, &cnt->overflow, &cnt->P_eff,
          nullptr, s);
     hipLaunchKernelGGL(emit_pairs, dim3(gs_blocks), dim3(256), 0, s, cams, L.N, (const uint32_t *)didx,
-                       (const uint32_t *)tsorted, (const uint32_t *)poff, rect, L.pair_cap,
-                       (const DevCounters *)cnt, k0, v0);
+                       (const uint32_t *)tsorted, (const uint32_t *)poff, rect, rec, pb.tile_w, pb.tile_h,
+                       L.pair_cap, (const DevCounters *)cnt, k0, v0);
     // 4. stable sort of the pairs by tile
     const int cur = radix_sort<uint32_t>(k0, v0, k1, v1, &cnt->P_eff, L.tile_bits, hist, dtot, s);
     // 5. ranges

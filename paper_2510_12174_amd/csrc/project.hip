@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(kProjThreads) project_fwd_kernel(ugs_gaussians
             if (u0 <= u1 && v0 <= v1 && isfinite(S.m2x) && isfinite(S.m2y)) {
                 const int tx0 = (int)u0 / tile_w, tx1 = (int)u1 / tile_w + 1;
                 const int ty0 = (int)v0 / tile_h, ty1 = (int)v1 / tile_h + 1;
-                nt = (uint32_t)((tx1 - tx0) * (ty1 - ty0));
+                const int area = (tx1 - tx0) * (ty1 - ty0);
                 rc = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
                 D Y[NC];
                 sh_basis<DEG>(S.dir[0], S.dir[1], S.dir[2], Y);
@@ -288,11 +288,16 @@ __global__ void __launch_bounds__(kProjThreads) project_fwd_kernel(ugs_gaussians
                 const D l11 = sqrt(S.cov11 / det), l21 = -S.cov01 / (det * l11), l22 = D(1) / sqrt(S.cov11);
                 const D iA = S.iA, fx = D(cam.fx), fy = D(cam.fy);
                 float4 *r = rec + idx * 4;
-                r[0] = make_float4((float)S.m2x, (float)S.m2y, (float)l11, (float)l21);
-                r[1] = make_float4((float)l22, (float)G.o, (float)G.k, (float)S.z);
+                const float4 q0 = make_float4((float)S.m2x, (float)S.m2y, (float)l11, (float)l21);
+                const float4 q1 = make_float4((float)l22, (float)G.o, (float)G.k, (float)S.z);
+                r[0] = q0;
+                r[1] = q1;
                 r[2] = make_float4((float)(S.Qp0x * iA / fx), (float)(S.Qp0y * iA / fy), (float)(S.Q00 * iA / (fx * fx)),
                                    (float)(S.Q01 * iA / (fx * fy)));
                 r[3] = make_float4((float)(S.Q11 * iA / (fy * fy)), col[0], col[1], col[2]);
+                // every tile of the rectangle, for now: the binning pass culls
+                // the tiles that the alpha ellipse misses
+                nt = (uint32_t)area;
                 if (zero_grad) {
                     float4 zf = make_float4(0.f, 0.f, 0.f, 0.f);
                     float4 *gr = grec + idx * 4;

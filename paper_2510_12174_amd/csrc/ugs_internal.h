@@ -124,6 +124,78 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t tiles)
     return ((k / kXcdChunk) * kXcds + xcd) * kXcdChunk + k % kXcdChunk;
 }
 
+// Tile culling by the alpha >= 1/255 ellipse.  A (view, Gaussian) record
+// covers tile [x0, x1] x [y0, y1] (pixel centres, clipped to the image) when
+// the minimum over the box of q(d) = (l11 dx + l21 dy)^2 + (l22 dy)^2 (d the
+// offset from mean2d; power = -q/2) is at most 2 ln(255 o), inflated by 1e-3
+// relative and absolute so that no pixel whose FP32 alpha reaches 1/255 is
+// ever culled.  Evaluated from the FP32 record with non-contracting IEEE
+// operations only, by one routine shared by the counting and the emission
+// pass, so the two take bit-identical decisions.  Rectangles of more than
+// kCullMaxTiles tiles are not tested (every tile kept).
+constexpr int kCullMaxTiles = 1024;
+
+struct CullGeom {
+    float mx, my, l11, l21, l22;
+    float thr;  // inflated 2 ln(255 o)
+    float kb;   // l11 l21 / (l21^2 + l22^2): stationary dy = -kb dx on a vertical edge
+    float kl;   // l21 / l11: stationary dx = -kl dy on a horizontal edge
+};
+
+__device__ __forceinline__ CullGeom cull_geom(float4 r0, float4 r1)
+{
+    CullGeom c;
+    c.mx = r0.x;
+    c.my = r0.y;
+    c.l11 = r0.z;
+    c.l21 = r0.w;
+    c.l22 = r1.x;
+    const float thr = __fmul_rn(2.0f, logf(__fmul_rn(255.0f, r1.y)));
+    c.thr = __fadd_rn(__fmul_rn(thr, 1.001f), 1e-3f);
+    c.kb = __fdiv_rn(__fmul_rn(c.l11, c.l21), __fadd_rn(__fmul_rn(c.l21, c.l21), __fmul_rn(c.l22, c.l22)));
+    c.kl = __fdiv_rn(c.l21, c.l11);
+    return c;
+}
+
+__device__ __forceinline__ float cull_q(const CullGeom &c, float dx, float dy)
+{
+    // (l11 dx + l21 dy)^2 + (l22 dy)^2, the factored form the renderer uses (an
+    // expanded quadratic would cancel badly for thin splats)
+    const float t1 = __fadd_rn(__fmul_rn(c.l11, dx), __fmul_rn(c.l21, dy));
+    const float t2 = __fmul_rn(c.l22, dy);
+    return __fadd_rn(__fmul_rn(t1, t1), __fmul_rn(t2, t2));
+}
+
+__device__ __forceinline__ bool cull_hits(const CullGeom &c, int x0, int x1, int y0, int y1)
+{
+    const float fx0 = (float)x0, fx1 = (float)x1, fy0 = (float)y0, fy1 = (float)y1;
+    if (c.mx >= fx0 && c.mx <= fx1 && c.my >= fy0 && c.my <= fy1) return true;
+    const float ex0 = __fsub_rn(fx0, c.mx), ex1 = __fsub_rn(fx1, c.mx);
+    const float ey0 = __fsub_rn(fy0, c.my), ey1 = __fsub_rn(fy1, c.my);
+    float qmin = INFINITY;
+    for (int k = 0; k < 2; ++k) {
+        const float dx = k ? ex1 : ex0;
+        const float dy = fminf(fmaxf(-__fmul_rn(c.kb, dx), ey0), ey1);
+        qmin = fminf(qmin, cull_q(c, dx, dy));
+    }
+    for (int k = 0; k < 2; ++k) {
+        const float dy = k ? ey1 : ey0;
+        const float dx = fminf(fmaxf(-__fmul_rn(c.kl, dy), ex0), ex1);
+        qmin = fminf(qmin, cull_q(c, dx, dy));
+    }
+    return qmin <= c.thr;
+}
+
+// Pixel box of tile (tx, ty), clipped to a W x H image.
+__device__ __forceinline__ void tile_box(int tx, int ty, int tw, int th, int W, int H, int &x0, int &x1, int &y0,
+                                         int &y1)
+{
+    x0 = tx * tw;
+    y0 = ty * th;
+    x1 = min(x0 + tw, W) - 1;
+    y1 = min(y0 + th, H) - 1;
+}
+
 __device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + __expf(-x)); }
 
 }  // namespace ugs
