@@ -132,6 +132,7 @@ def main():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", default=None, help="force a tile shape, e.g. 16x16")
+    ap.add_argument("--batch", type=int, default=0, help="force the LDS batch (with --tile)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -170,7 +171,7 @@ def main():
     rast = U.Rasterizer(prune_Tk=float(opts["prune_Tk"]))
     if args.tile:
         tw, th = (int(x) for x in args.tile.split("x"))
-        rast.set_options(tile_w=tw, tile_h=th)
+        rast.set_options(tile_w=tw, tile_h=th, batch=args.batch)
     tuned = None
     if not args.no_autotune and not args.tile:
         log("[bench] autotuning tile shape and batch")
