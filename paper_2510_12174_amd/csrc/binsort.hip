@@ -157,6 +157,7 @@ __global__ void __launch_bounds__(256) compact_visible(int64_t N, int64_t VN, co
 struct WalkRec {
     uint32_t idx, gid, rx, ry, w, area, tb, tw;
     int W, H;
+    float rw;  // 1 / w
     CullGeom c;
 };
 
@@ -173,6 +174,7 @@ __device__ __forceinline__ WalkRec walk_load(const DevCam *cams, int64_t N, uint
     k.ry = rc.x >> 16;
     k.w = (rc.y & 0xffff) - k.rx;
     k.area = k.w * ((rc.y >> 16) - k.ry);
+    k.rw = __frcp_rn((float)max(k.w, 1u));
     k.tb = cam.tile_base;
     k.tw = (uint32_t)cam.tiles_x;
     k.W = cam.W;
@@ -194,6 +196,7 @@ __device__ __forceinline__ WalkRec walk_bcast(const WalkRec &a, int k)
     b.tw = __shfl(a.tw, k, 64);
     b.W = __shfl(a.W, k, 64);
     b.H = __shfl(a.H, k, 64);
+    b.rw = __shfl(a.rw, k, 64);
     b.c.mx = __shfl(a.c.mx, k, 64);
     b.c.my = __shfl(a.c.my, k, 64);
     b.c.l11 = __shfl(a.c.l11, k, 64);
@@ -209,9 +212,15 @@ __device__ __forceinline__ WalkRec walk_bcast(const WalkRec &a, int k)
 // ellipse reaches it.
 __device__ __forceinline__ bool walk_hit(const WalkRec &k, uint32_t q, int tile_w, int tile_h, uint32_t &tile)
 {
-    const uint32_t ty = q / k.w, tx = q - ty * k.w;
+    if (k.area > (uint32_t)kCullMaxTiles) {
+        const uint32_t ty = q / k.w, tx = q - ty * k.w;
+        tile = k.tb + (k.ry + ty) * k.tw + k.rx + tx;
+        return true;
+    }
+    // q < 1024: (q + 1/2) / w lies at least 1/(2w) from an integer, far more
+    // than the rounding of the product with the rounded reciprocal
+    const uint32_t ty = (uint32_t)__fmul_rn((float)q + 0.5f, k.rw), tx = q - ty * k.w;
     tile = k.tb + (k.ry + ty) * k.tw + k.rx + tx;
-    if (k.area > (uint32_t)kCullMaxTiles) return true;
     int bx0, bx1, by0, by1;
     tile_box((int)(k.rx + tx), (int)(k.ry + ty), tile_w, tile_h, k.W, k.H, bx0, bx1, by0, by1);
     return cull_hits(k.c, bx0, bx1, by0, by1);

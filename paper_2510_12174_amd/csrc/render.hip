@@ -478,7 +478,10 @@ __device__ __forceinline__ mf4 mfma3(const bf8 &ah, const bf8 &al, const bf8 &bh
 }
 
 template <int TW, int TH, int CO>
-__global__ void __launch_bounds__(TW *TH) render_bwd_mfma_kernel(
+// Four wavefronts per SIMD (at most 128 registers per lane): the kernel is bound
+// by VALU issue and dependency latency, and a fourth wavefront hides enough of
+// the latter to pay for the tighter register budget (no spills).
+__global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))) render_bwd_mfma_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
     const float *__restrict__ T_final, const uint32_t *__restrict__ n_contrib, const float *__restrict__ up_rgb,
