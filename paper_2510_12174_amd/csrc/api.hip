@@ -202,7 +202,7 @@ WsLayout make_layout(const Problem &pb, int64_t pair_cap)
     L.pair_cap = pair_cap;
     L.nb_scan = (int)((L.VN + kScanBlock - 1) / kScanBlock);
     if (L.nb_scan < 1) L.nb_scan = 1;
-    L.depth_bits = 32 + bit_length((uint64_t)(pb.V > 0 ? pb.V - 1 : 0));
+    L.depth_bits = 32;
     L.tile_bits = bit_length((uint64_t)(pb.total_tiles > 0 ? pb.total_tiles - 1 : 0));
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -220,8 +220,8 @@ WsLayout make_layout(const Problem &pb, int64_t pair_cap)
     L.voff = take(VN * 4);
     L.poff = take(VN * 4);
     L.tsorted = take(VN * 4);
-    L.dkey0 = take(VN * 8);
-    L.dkey1 = take(VN * 8);
+    L.dkey0 = take(VN * 4);
+    L.dkey1 = take(VN * 4);
     L.didx0 = take(VN * 4);
     L.didx1 = take(VN * 4);
     L.scan_part = take((size_t)L.nb_scan * 4);

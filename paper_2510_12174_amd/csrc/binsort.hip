@@ -1,11 +1,13 @@
 // Stages S2-S4: tile binning, (tile, depth) ordering and per-tile ranges.
 //
 // Order of work:
-//   1. compact the visible (view, Gaussian) records (tiles touched > 0);
-//   2. sort them by (view, camera depth) -- a stable LSD radix sort over the
-//      depth bits and the view bits of a 64-bit key, on ~R records only;
-//   3. scan their tile counts in that order and emit one (tile, index) pair per
-//      covered tile: pairs come out in (view, depth, index) order;
+//   1. compact the visible (view, Gaussian) records (rectangle not empty);
+//   2. sort them by camera depth -- a stable LSD radix sort of the 32 depth
+//      bits, on ~R records only (views need no key bits: tile ids keep them
+//      apart and every later pass is stable);
+//   3. count, in that order, the rectangle tiles that each record's alpha
+//      ellipse reaches, scan the counts and emit one (tile, index) pair per
+//      kept tile: pairs come out in (depth, index) order;
 //   4. stable LSD radix sort of the pairs by global tile id (32-bit keys, only
 //      the bits in use: two 8-bit passes up to 65,536 tiles);
 //   5. per-tile [start, end) ranges.
@@ -139,32 +141,35 @@ __global__ void __launch_bounds__(kScanThreads) scan_down(ScanIn si, const uint3
 __global__ void __launch_bounds__(256) compact_visible(int64_t N, int64_t VN, const uint32_t *__restrict__ touched,
                                                        const uint32_t *__restrict__ voff,
                                                        const float4 *__restrict__ rec,
-                                                       unsigned long long *__restrict__ dkey,
-                                                       uint32_t *__restrict__ didx)
+                                                       uint32_t *__restrict__ dkey, uint32_t *__restrict__ didx)
 {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= VN || touched[idx] == 0) return;
     const uint32_t r = voff[idx];
-    const uint64_t view = (uint64_t)(idx / N);
-    dkey[r] = (view << 32) | __float_as_uint(rec[idx * 4 + 1].w);
+    // the camera depth is > z_near > 0, so its float bits order as integers;
+    // the view needs no key bits (tile ids keep views apart and the tile sort
+    // is stable)
+    dkey[r] = __float_as_uint(rec[idx * 4 + 1].w);
     didx[r] = (uint32_t)idx;
 }
 
 // Tile counts in depth order (grid-stride up to the device count R).
 
-// One depth-sorted record as the binning walks see it: rectangle, view
-// geometry and the culling data of its FP32 projection record.
-struct WalkRec {
+// One depth-sorted record as the binning walk sees it: rectangle, view
+// geometry and the culling data of its FP32 projection record (96 B, so that
+// a wavefront can stage its 64 records in LDS).
+struct __align__(16) WalkRec {
     uint32_t idx, gid, rx, ry, w, area, tb, tw;
     int W, H;
-    float rw;  // 1 / w
+    float rw;        // 1 / w
+    uint32_t start;  // first position of the record in the wavefront's tile run
     CullGeom c;
+    uint32_t nt, off, pad0, pad1;  // emission: counted slots and first pair
 };
 
-__device__ __forceinline__ WalkRec walk_load(const DevCam *cams, int64_t N, uint32_t idx, const uint2 *rect,
-                                             const float4 *rec)
+__device__ __forceinline__ void walk_load(WalkRec &k, const DevCam *cams, int64_t N, uint32_t idx,
+                                          const uint2 *rect, const float4 *rec)
 {
-    WalkRec k;
     k.idx = idx;
     const int v = (int)(idx / (uint64_t)N);
     k.gid = (uint32_t)(idx - (uint64_t)v * N);
@@ -180,32 +185,6 @@ __device__ __forceinline__ WalkRec walk_load(const DevCam *cams, int64_t N, uint
     k.W = cam.W;
     k.H = cam.H;
     k.c = cull_geom(rec[(int64_t)idx * 4], rec[(int64_t)idx * 4 + 1]);
-    return k;
-}
-
-__device__ __forceinline__ WalkRec walk_bcast(const WalkRec &a, int k)
-{
-    WalkRec b;
-    b.idx = __shfl(a.idx, k, 64);
-    b.gid = __shfl(a.gid, k, 64);
-    b.rx = __shfl(a.rx, k, 64);
-    b.ry = __shfl(a.ry, k, 64);
-    b.w = __shfl(a.w, k, 64);
-    b.area = __shfl(a.area, k, 64);
-    b.tb = __shfl(a.tb, k, 64);
-    b.tw = __shfl(a.tw, k, 64);
-    b.W = __shfl(a.W, k, 64);
-    b.H = __shfl(a.H, k, 64);
-    b.rw = __shfl(a.rw, k, 64);
-    b.c.mx = __shfl(a.c.mx, k, 64);
-    b.c.my = __shfl(a.c.my, k, 64);
-    b.c.l11 = __shfl(a.c.l11, k, 64);
-    b.c.l21 = __shfl(a.c.l21, k, 64);
-    b.c.l22 = __shfl(a.c.l22, k, 64);
-    b.c.thr = __shfl(a.c.thr, k, 64);
-    b.c.kb = __shfl(a.c.kb, k, 64);
-    b.c.kl = __shfl(a.c.kl, k, 64);
-    return b;
 }
 
 // Tile q (row-major in the rectangle) of record k, and whether its alpha
@@ -226,92 +205,96 @@ __device__ __forceinline__ bool walk_hit(const WalkRec &k, uint32_t q, int tile_
     return cull_hits(k.c, bx0, bx1, by0, by1);
 }
 
-// Culled tile counts of the depth-sorted records, one wavefront per run of 64
-// records walking each rectangle together (lane q tests tiles q, q + 64, ...).
-// Writes the count in depth order and back to the record.
-__global__ void __launch_bounds__(256) count_culled(const DevCam *__restrict__ cams, int64_t N,
-                                                    const uint32_t *__restrict__ didx, const uint2 *__restrict__ rect,
-                                                    const float4 *__restrict__ rec, int tile_w, int tile_h,
-                                                    const DevCounters *__restrict__ cnt,
-                                                    uint32_t *__restrict__ tsorted, uint32_t *__restrict__ touched)
-{
-    const uint32_t R = cnt->R;
-    const int lane = __lane_id();
-    const uint64_t wave0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * 256) >> 6;
-    for (uint64_t base = wave0 * 64; base < R; base += nwaves * 64) {
-        const uint64_t r = base + lane;
-        WalkRec mine;
-        mine.area = 0;
-        if (r < R) mine = walk_load(cams, N, didx[r], rect, rec);
-        uint32_t my_count = 0;
-        const int m = (int)min((uint64_t)64, (uint64_t)R - base);
-        for (int k = 0; k < m; ++k) {
-            const WalkRec kr = walk_bcast(mine, k);
-            uint32_t count = 0;
-            for (uint32_t q0 = 0; q0 < kr.area; q0 += 64) {
-                const uint32_t q = q0 + (uint32_t)lane;
-                uint32_t tile;
-                const bool hit = q < kr.area && walk_hit(kr, q, tile_w, tile_h, tile);
-                count += (uint32_t)__popcll(__ballot(hit));
-            }
-            if (lane == k) my_count = count;
-        }
-        if (r < R) {
-            tsorted[r] = my_count;
-            touched[mine.idx] = my_count;
-        }
-    }
-}
-
-// Pair emission, the same walk: the kept tiles of every record are written
-// compacted by ballot, so the stores are coalesced whatever the footprint
-// sizes.  Writes never pass the record's counted slots.
-__global__ void __launch_bounds__(256) emit_pairs(const DevCam *__restrict__ cams, int64_t N,
-                                                  const uint32_t *__restrict__ didx,
-                                                  const uint32_t *__restrict__ tsorted,
-                                                  const uint32_t *__restrict__ poff, const uint2 *__restrict__ rect,
+// The binning walk over the depth-sorted records, one wavefront per run of 64:
+// the records' rectangles are laid end to end (an inclusive scan of their
+// areas), and the wavefront walks that run 64 tiles at a time with every lane
+// busy -- each lane finds its record by binary search over the scan, reads it
+// from LDS and tests its tile against the alpha ellipse.  Per-record counts of
+// kept tiles live in LDS.  COUNT: writes the counts (in depth order and back to
+// the records).  EMIT: writes each kept tile's (tile, index) pair at the
+// record's offset plus the number of kept tiles before it, never past the
+// counted slots.  Both modes take bit-identical decisions (same routine, same
+// FP32 record).
+template <bool EMIT>
+__global__ void __launch_bounds__(256) walk_pairs(const DevCam *__restrict__ cams, int64_t N,
+                                                  const uint32_t *__restrict__ didx, const uint2 *__restrict__ rect,
                                                   const float4 *__restrict__ rec, int tile_w, int tile_h,
-                                                  int64_t cap, const DevCounters *__restrict__ cnt,
-                                                  uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+                                                  const DevCounters *__restrict__ cnt, uint32_t *__restrict__ tsorted,
+                                                  uint32_t *__restrict__ touched, const uint32_t *__restrict__ poff,
+                                                  int64_t cap, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
 {
-    if (cnt->overflow) return;
+    __shared__ WalkRec srec[4][64];
+    __shared__ uint32_t scnt[4][64];
+    if (EMIT && cnt->overflow) return;
     const uint32_t R = cnt->R;
-    const int lane = __lane_id();
+    const int lane = __lane_id(), wave = (int)(threadIdx.x >> 6);
     const uint64_t lt = __lanemask_lt();
     const uint64_t wave0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * 256) >> 6;
+    WalkRec *wr = srec[wave];
+    uint32_t *wc = scnt[wave];
     for (uint64_t base = wave0 * 64; base < R; base += nwaves * 64) {
         const uint64_t r = base + lane;
         WalkRec mine;
         mine.area = 0;
-        uint32_t nt = 0, off = 0;
+        mine.nt = 0;
+        mine.off = 0;
         if (r < R) {
-            nt = tsorted[r];
-            off = poff[r];
-            if ((uint64_t)off + nt > (uint64_t)cap) nt = 0;
-            if (nt) mine = walk_load(cams, N, didx[r], rect, rec);
-        }
-        const int m = (int)min((uint64_t)64, (uint64_t)R - base);
-        for (int k = 0; k < m; ++k) {
-            const uint32_t knt = __shfl(nt, k, 64);
-            if (knt == 0) continue;
-            const uint32_t koff = __shfl(off, k, 64);
-            const WalkRec kr = walk_bcast(mine, k);
-            uint32_t done = 0;
-            for (uint32_t q0 = 0; q0 < kr.area && done < knt; q0 += 64) {
-                const uint32_t q = q0 + (uint32_t)lane;
-                uint32_t tile = 0;
-                const bool hit = q < kr.area && walk_hit(kr, q, tile_w, tile_h, tile);
-                const uint64_t mask = __ballot(hit);
-                const uint32_t slot = done + (uint32_t)__popcll(mask & lt);
-                if (hit && slot < knt) {
-                    keys[koff + slot] = tile;
-                    vals[koff + slot] = kr.gid;
-                }
-                done += (uint32_t)__popcll(mask);
+            walk_load(mine, cams, N, didx[r], rect, rec);
+            if (EMIT) {
+                mine.nt = tsorted[r];
+                mine.off = poff[r];
+                if ((uint64_t)mine.off + mine.nt > (uint64_t)cap) mine.nt = 0;
+                if (mine.nt == 0) mine.area = 0;
             }
         }
+        const uint32_t incl = wave_incl_scan(mine.area);
+        mine.start = incl - mine.area;
+        const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+        __builtin_amdgcn_wave_barrier();
+        wr[lane] = mine;
+        wc[lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t t0 = 0; t0 < total; t0 += 64) {
+            const uint32_t t = t0 + (uint32_t)lane;
+            const bool valid = t < total;
+            // record of position t: the first k with incl[k] > t
+            int lo = 0, hi = 63;
+#pragma unroll
+            for (int it = 0; it < 6; ++it) {
+                const int mid = (lo + hi) >> 1;
+                const uint32_t v = (uint32_t)__shfl((int)incl, mid, 64);
+                if (v > t) hi = mid;
+                else lo = mid + 1;
+            }
+            const int k = valid ? lo : 63;
+            const WalkRec kr = wr[k];
+            uint32_t tile = 0;
+            const bool hit = valid && walk_hit(kr, t - kr.start, tile_w, tile_h, tile);
+            const uint64_t hm = __ballot(hit);
+            // lanes [a, b) of this chunk belong to record k
+            const int a = (int)max((int64_t)kr.start - (int64_t)t0, (int64_t)0);
+            const int64_t bend = (int64_t)kr.start + kr.area - (int64_t)t0;
+            const uint64_t from_a = ~((1ull << a) - 1ull);
+            const uint64_t upto_b = bend >= 64 ? ~0ull : ((1ull << bend) - 1ull);
+            const uint32_t before = wc[k];
+            if (EMIT && hit) {
+                const uint32_t slot = before + (uint32_t)__popcll(hm & lt & from_a);
+                if (slot < kr.nt) {
+                    keys[kr.off + slot] = tile;
+                    vals[kr.off + slot] = kr.gid;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (valid && lane == a) wc[k] = before + (uint32_t)__popcll(hm & from_a & upto_b);
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (!EMIT && r < R) {
+            const uint32_t c = wc[lane];
+            tsorted[r] = c;
+            touched[mine.idx] = c;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -543,7 +526,7 @@ hipError_t launch_binsort(const Problem &pb, const WsLayout &L, char *ws, hipStr
     auto cnt = (DevCounters *)(ws + L.counters);
     auto rect = (const uint2 *)(ws + L.rect);
     auto rec = (const float4 *)(ws + L.rec);
-    auto dk0 = (unsigned long long *)(ws + L.dkey0), dk1 = (unsigned long long *)(ws + L.dkey1);
+    auto dk0 = (uint32_t *)(ws + L.dkey0), dk1 = (uint32_t *)(ws + L.dkey1);
     auto di0 = (uint32_t *)(ws + L.didx0), di1 = (uint32_t *)(ws + L.didx1);
     auto k0 = (uint32_t *)(ws + L.keys0), k1 = (uint32_t *)(ws + L.keys1);
     auto v0 = (uint32_t *)(ws + L.vals0), v1 = (uint32_t *)(ws + L.vals1);
@@ -560,17 +543,18 @@ hipError_t launch_binsort(const Problem &pb, const WsLayout &L, char *ws, hipStr
     if (VN > 0)
         hipLaunchKernelGGL(compact_visible, dim3(vn_blocks), dim3(256), 0, s, L.N, VN, (const uint32_t *)touched,
                            (const uint32_t *)voff, rec, dk0, di0);
-    // 2. sort by (view, depth)
-    const int dcur = radix_sort<unsigned long long>(dk0, di0, dk1, di1, &cnt->R, L.depth_bits, hist, dtot, s);
+    // 2. sort by depth
+    const int dcur = radix_sort<uint32_t>(dk0, di0, dk1, di1, &cnt->R, L.depth_bits, hist, dtot, s);
     uint32_t *didx = dcur ? di1 : di0;
     // 3. tile counts in depth order, pair offsets, emission
-    hipLaunchKernelGGL(count_culled, dim3(gs_blocks), dim3(256), 0, s, cams, L.N, (const uint32_t *)didx, rect, rec,
-                       pb.tile_w, pb.tile_h, (const DevCounters *)cnt, tsorted, touched);
+    hipLaunchKernelGGL(walk_pairs<false>, dim3(gs_blocks), dim3(256), 0, s, cams, L.N, (const uint32_t *)didx, rect,
+                       rec, pb.tile_w, pb.tile_h, (const DevCounters *)cnt, tsorted, touched, (const uint32_t *)poff,
+                       (int64_t)0, k0, v0);
     scan(ScanIn{tsorted, VN, &cnt->R, 0}, L.nb_scan, part, poff, L.pair_cap, &cnt->P, &cnt->overflow, &cnt->P_eff,
          nullptr, s);
-    hipLaunchKernelGGL(emit_pairs, dim3(gs_blocks), dim3(256), 0, s, cams, L.N, (const uint32_t *)didx,
-                       (const uint32_t *)tsorted, (const uint32_t *)poff, rect, rec, pb.tile_w, pb.tile_h,
-                       L.pair_cap, (const DevCounters *)cnt, k0, v0);
+    hipLaunchKernelGGL(walk_pairs<true>, dim3(gs_blocks), dim3(256), 0, s, cams, L.N, (const uint32_t *)didx, rect,
+                       rec, pb.tile_w, pb.tile_h, (const DevCounters *)cnt, tsorted, touched, (const uint32_t *)poff,
+                       L.pair_cap, k0, v0);
     // 4. stable sort of the pairs by tile
     const int cur = radix_sort<uint32_t>(k0, v0, k1, v1, &cnt->P_eff, L.tile_bits, hist, dtot, s);
     // 5. ranges
