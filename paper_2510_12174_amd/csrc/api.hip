@@ -223,6 +223,7 @@ WsLayout make_layout(const Problem &pb, int64_t pair_cap)
     L.dkey0 = take(VN * 4);
     L.dkey1 = take(VN * 4);
     L.didx0 = take(VN * 4);
+    L.vlist = take(VN * 4);
     L.didx1 = take(VN * 4);
     L.scan_part = take((size_t)L.nb_scan * 4);
     L.keys0 = take(P * 4);
@@ -241,10 +242,15 @@ WsLayout make_layout(const Problem &pb, int64_t pair_cap)
 int auto_batch(const ugs_options &o, int C_o)
 {
     if (o.batch > 0) return o.batch;
-    int nt = o.tile_w * o.tile_h;
-    int per = 64 + 4 * channel_pad(C_o);
+    // largest power of two up to the tile's pixel count whose LDS staging fits
+    // 32 KB per workgroup; the matrix-core kernels (16 or 32 padded channels)
+    // also hold a 16 x 68 FP32 buffer per wavefront and 212 B per entry
+    const int nt = o.tile_w * o.tile_h, cp = channel_pad(C_o);
+    const bool mfma = cp == 16 || cp == 32;
+    const size_t per = mfma ? 212 : (size_t)(64 + 4 * cp);
+    const size_t fixed = mfma ? (size_t)(nt / 64) * 16 * 68 * 4 : 0;
     int b = nt;
-    while (b > 16 && (size_t)b * per > 32 * 1024) b /= 2;
+    while (b > 16 && fixed + (size_t)b * per > 32 * 1024) b /= 2;
     return b;
 }
 

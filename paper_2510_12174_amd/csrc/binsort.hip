@@ -141,7 +141,8 @@ __global__ void __launch_bounds__(kScanThreads) scan_down(ScanIn si, const uint3
 __global__ void __launch_bounds__(256) compact_visible(int64_t N, int64_t VN, const uint32_t *__restrict__ touched,
                                                        const uint32_t *__restrict__ voff,
                                                        const float4 *__restrict__ rec,
-                                                       uint32_t *__restrict__ dkey, uint32_t *__restrict__ didx)
+                                                       uint32_t *__restrict__ dkey, uint32_t *__restrict__ didx,
+                                                       uint32_t *__restrict__ vlist)
 {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= VN || touched[idx] == 0) return;
@@ -151,6 +152,7 @@ __global__ void __launch_bounds__(256) compact_visible(int64_t N, int64_t VN, co
     // is stable)
     dkey[r] = __float_as_uint(rec[idx * 4 + 1].w);
     didx[r] = (uint32_t)idx;
+    vlist[r] = (uint32_t)idx;
 }
 
 // Tile counts in depth order (grid-stride up to the device count R).
@@ -542,7 +544,7 @@ hipError_t launch_binsort(const Problem &pb, const WsLayout &L, char *ws, hipStr
     scan(ScanIn{touched, VN, nullptr, 1}, L.nb_scan, part, voff, -1, &cnt->R, nullptr, nullptr, cnt, s);
     if (VN > 0)
         hipLaunchKernelGGL(compact_visible, dim3(vn_blocks), dim3(256), 0, s, L.N, VN, (const uint32_t *)touched,
-                           (const uint32_t *)voff, rec, dk0, di0);
+                           (const uint32_t *)voff, rec, dk0, di0, (uint32_t *)(ws + L.vlist));
     // 2. sort by depth
     const int dcur = radix_sort<uint32_t>(dk0, di0, dk1, di1, &cnt->R, L.depth_bits, hist, dtot, s);
     uint32_t *didx = dcur ? di1 : di0;

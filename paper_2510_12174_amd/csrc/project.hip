@@ -310,40 +310,46 @@ __global__ void __launch_bounds__(kProjThreads) project_fwd_kernel(ugs_gaussians
     }
 }
 
-// Backward of the per-view record into the Gaussian parameters, summed over views.
+// Backward of the per-view records into the Gaussian parameters, in two
+// passes.  The first runs the whole chain rule once per visible (view,
+// Gaussian) record -- one thread per record of the index-ordered visible list,
+// so no lane idles on views where its Gaussian is not visible and neighbouring
+// lanes read neighbouring parameters -- and writes the
+// record's contributions to the parameter gradients back into its gradient
+// record: mean 0-2, quaternion 3-6, log-scale 7-9, opacity logit 10, mask logit
+// 11 and the clamped colour gradient 12-14 (the SH coefficients' share is
+// Y(dir) times it).  The chain is linear in the record gradients, so applying
+// it per view and summing equals summing first.  The second pass sums the
+// contributions of each Gaussian's visible views and forms the SH gradients.
 template <int DEG>
-__global__ void __launch_bounds__(kProjThreads) project_bwd_kernel(ugs_gaussians g, const DevCam *__restrict__ cams,
-                                                                   int V, const uint32_t *__restrict__ touched,
-                                                                   const float4 *__restrict__ grec,
-                                                                   ugs_gaussian_grads dg)
+__global__ void __launch_bounds__(kProjThreads) project_bwd_rec_kernel(ugs_gaussians g, const DevCam *__restrict__ cams,
+                                                                       const uint32_t *__restrict__ didx,
+                                                                       const DevCounters *__restrict__ cnt,
+                                                                       const uint32_t *__restrict__ touched,
+                                                                       float4 *__restrict__ grec)
 {
     const int64_t N = g.N;
-    const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
-    if (i >= N) return;
     constexpr int NC = (DEG + 1) * (DEG + 1);
     using D = double;  // the chain rule runs in FP64: its terms scale like 1/s^2 and cancel
-    GaussState<D> G;
-    load_gauss(g, i, G);
-    D dmu[3] = {D(0), D(0), D(0)}, dRg[9], ds[3] = {D(0), D(0), D(0)}, dSig[6], dis2[3] = {D(0), D(0), D(0)};
-    for (int k = 0; k < 9; ++k) dRg[k] = D(0);
-    for (int k = 0; k < 6; ++k) dSig[k] = D(0);
-    D dop = D(0), dk = D(0);
-    float sh[NC][3], dsh[NC][3];  // coefficients and their gradients stay FP32
-    bool loaded = false;
-    for (int v = 0; v < V; ++v) {
-        const int64_t idx = (int64_t)v * N + i;
+    const uint32_t Rn = cnt->R;
+    for (uint64_t rr = (uint64_t)blockIdx.x * kProjThreads + threadIdx.x; rr < Rn;
+         rr += (uint64_t)gridDim.x * kProjThreads) {
+        const uint32_t idx = didx[rr];
         if (touched[idx] == 0) continue;
+        const int v = (int)(idx / (uint64_t)N);
+        const int64_t i = (int64_t)idx - (int64_t)v * N;
+        GaussState<D> G;
+        load_gauss(g, i, G);
+        D dmu[3] = {D(0), D(0), D(0)}, dRg[9], ds[3] = {D(0), D(0), D(0)}, dSig[6], dis2[3] = {D(0), D(0), D(0)};
+        for (int k = 0; k < 9; ++k) dRg[k] = D(0);
+        for (int k = 0; k < 6; ++k) dSig[k] = D(0);
+        D dop = D(0), dk = D(0);
+        float sh[NC][3], dcs[3] = {0.f, 0.f, 0.f};
+        for (int c = 0; c < NC; ++c)
+            for (int ch = 0; ch < 3; ++ch) sh[c][ch] = g.sh[((int64_t)c * 3 + ch) * N + i];
         const DevCam &cam = cams[v];
-        if (!loaded) {
-            for (int c = 0; c < NC; ++c)
-                for (int ch = 0; ch < 3; ++ch) {
-                    sh[c][ch] = g.sh[((int64_t)c * 3 + ch) * N + i];
-                    dsh[c][ch] = 0.f;
-                }
-            loaded = true;
-        }
-        const float4 *gr = grec + idx * 4;
-        float4 g0 = gr[0], g1 = gr[1], g2 = gr[2], g3 = gr[3];
+        const float4 *gin = grec + (int64_t)idx * 4;
+        float4 g0 = gin[0], g1 = gin[1], g2 = gin[2], g3 = gin[3];
         ViewState<D> S;
         project_view(G, cam, S);
         D R[9];
@@ -363,10 +369,10 @@ __global__ void __launch_bounds__(kProjThreads) project_bwd_kernel(ugs_gaussians
                 D raw = D(0.5);
                 for (int c = 0; c < NC; ++c) raw += Y[c] * sh[c][ch];
                 D dc = raw > D(0) ? dcol[ch] : D(0);
+                dcs[ch] = (float)dc;
                 if (dc == D(0)) continue;
                 D w[NC];
                 for (int c = 0; c < NC; ++c) {
-                    dsh[c][ch] += dc * Y[c];
                     w[c] = dc * sh[c][ch];
                 }
                 D gx, gy, gz;
@@ -483,40 +489,86 @@ __global__ void __launch_bounds__(kProjThreads) project_bwd_kernel(ugs_gaussians
         }
         // mc = R mu + t
         for (int e = 0; e < 3; ++e) dmu[e] += R[e] * dmc[0] + R[3 + e] * dmc[1] + R[6 + e] * dmc[2];
+        {
+        // Sig = Rg S^2 Rg^T: with Mg = Rg S, dMg = 2 dSig Mg (full symmetric dSig)
+        {
+            D dS3[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
+            for (int r = 0; r < 3; ++r)
+                for (int q = 0; q < 3; ++q) {
+                    D acc = D(0);
+                    for (int k = 0; k < 3; ++k) acc += dS3[3 * r + k] * G.Rg[3 * k + q];
+                    D dMg = D(2) * acc * G.s[q];
+                    dRg[3 * r + q] += dMg * G.s[q];
+                    ds[q] += G.Rg[3 * r + q] * dMg;
+                }
+        }
+        for (int k = 0; k < 3; ++k) ds[k] += dis2[k] * (-D(2)) * G.is2[k] / G.s[k];
+        // rotation matrix -> unit quaternion -> quaternion
+        D w = G.qh[0], x = G.qh[1], y = G.qh[2], z = G.qh[3];
+        const D *d = dRg;
+        D gw = D(2) * (-z * d[1] + y * d[2] + z * d[3] - x * d[5] - y * d[6] + x * d[7]);
+        D gx = D(2) * (y * d[1] + z * d[2] + y * d[3] - D(2) * x * d[4] - w * d[5] + z * d[6] + w * d[7] - D(2) * x * d[8]);
+        D gy = D(2) * (-D(2) * y * d[0] + x * d[1] + w * d[2] + x * d[3] + z * d[5] - w * d[6] + z * d[7] - D(2) * y * d[8]);
+        D gz = D(2) * (-D(2) * z * d[0] - w * d[1] + x * d[2] + w * d[3] - D(2) * z * d[4] + y * d[5] + x * d[6] + y * d[7]);
+        D pq = gw * w + gx * x + gy * y + gz * z;
+        D iq = D(1) / G.qn;
+        float4 *gr = grec + (int64_t)idx * 4;
+        gr[0] = make_float4((float)dmu[0], (float)dmu[1], (float)dmu[2], (float)((gw - w * pq) * iq));
+        gr[1] = make_float4((float)((gx - x * pq) * iq), (float)((gy - y * pq) * iq), (float)((gz - z * pq) * iq),
+                            (float)(ds[0] * G.s[0]));
+        gr[2] = make_float4((float)(ds[1] * G.s[1]), (float)(ds[2] * G.s[2]), (float)(dop * G.o * (D(1) - G.o)),
+                            (float)(dk * G.k * (D(1) - G.k)));
+        gr[3] = make_float4(dcs[0], dcs[1], dcs[2], 0.f);
+        }
     }
-    if (!loaded) return;
-    // Sig = Rg S^2 Rg^T: with Mg = Rg S, dMg = 2 dSig Mg (full symmetric dSig)
-    {
-        D dS3[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
-        for (int r = 0; r < 3; ++r)
-            for (int q = 0; q < 3; ++q) {
-                D acc = D(0);
-                for (int k = 0; k < 3; ++k) acc += dS3[3 * r + k] * G.Rg[3 * k + q];
-                D dMg = D(2) * acc * G.s[q];
-                dRg[3 * r + q] += dMg * G.s[q];
-                ds[q] += G.Rg[3 * r + q] * dMg;
-            }
+}
+
+// Second pass: per Gaussian, the sum over its visible views of the record
+// contributions, and the SH gradients Y(dir_v) times the clamped colour
+// gradient of each view (Y in FP64, as in the projection).
+template <int DEG>
+__global__ void __launch_bounds__(kProjThreads) project_bwd_sum_kernel(ugs_gaussians g, const DevCam *__restrict__ cams,
+                                                                       int V, const uint32_t *__restrict__ touched,
+                                                                       const float4 *__restrict__ grec,
+                                                                       ugs_gaussian_grads dg)
+{
+    const int64_t N = g.N;
+    const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
+    if (i >= N) return;
+    constexpr int NC = (DEG + 1) * (DEG + 1);
+    using D = double;
+    D acc[12];
+    for (int k = 0; k < 12; ++k) acc[k] = D(0);
+    float dsh[NC][3];
+    for (int c = 0; c < NC; ++c)
+        for (int ch = 0; ch < 3; ++ch) dsh[c][ch] = 0.f;
+    const D mu[3] = {D(g.mean[i]), D(g.mean[N + i]), D(g.mean[2 * N + i])};
+    bool any = false;
+    for (int v = 0; v < V; ++v) {
+        const int64_t idx = (int64_t)v * N + i;
+        if (touched[idx] == 0) continue;
+        any = true;
+        const float4 *gr = grec + idx * 4;
+        const float4 a = gr[0], b = gr[1], c2 = gr[2], d3 = gr[3];
+        const float f[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c2.x, c2.y, c2.z, c2.w};
+        for (int k = 0; k < 12; ++k) acc[k] += D(f[k]);
+        const DevCam &cam = cams[v];
+        const D v0 = mu[0] - D(cam.C[0]), v1 = mu[1] - D(cam.C[1]), v2 = mu[2] - D(cam.C[2]);
+        const D id = D(1) / m_sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+        D Y[NC];
+        sh_basis<DEG>(v0 * id, v1 * id, v2 * id, Y);
+        const D dc[3] = {D(d3.x), D(d3.y), D(d3.z)};
+        for (int ch = 0; ch < 3; ++ch) {
+            if (dc[ch] == D(0)) continue;
+            for (int c = 0; c < NC; ++c) dsh[c][ch] += dc[ch] * Y[c];
+        }
     }
-    for (int k = 0; k < 3; ++k) ds[k] += dis2[k] * (-D(2)) * G.is2[k] / G.s[k];
-    // rotation matrix -> unit quaternion -> quaternion
-    D w = G.qh[0], x = G.qh[1], y = G.qh[2], z = G.qh[3];
-    const D *d = dRg;
-    D gw = D(2) * (-z * d[1] + y * d[2] + z * d[3] - x * d[5] - y * d[6] + x * d[7]);
-    D gx = D(2) * (y * d[1] + z * d[2] + y * d[3] - D(2) * x * d[4] - w * d[5] + z * d[6] + w * d[7] - D(2) * x * d[8]);
-    D gy = D(2) * (-D(2) * y * d[0] + x * d[1] + w * d[2] + x * d[3] + z * d[5] - w * d[6] + z * d[7] - D(2) * y * d[8]);
-    D gz = D(2) * (-D(2) * z * d[0] - w * d[1] + x * d[2] + w * d[3] - D(2) * z * d[4] + y * d[5] + x * d[6] + y * d[7]);
-    D pq = gw * w + gx * x + gy * y + gz * z;
-    D iq = D(1) / G.qn;
-    dg.quat[i] += (gw - w * pq) * iq;
-    dg.quat[N + i] += (gx - x * pq) * iq;
-    dg.quat[2 * N + i] += (gy - y * pq) * iq;
-    dg.quat[3 * N + i] += (gz - z * pq) * iq;
-    for (int e = 0; e < 3; ++e) {
-        dg.mean[e * N + i] += dmu[e];
-        dg.log_scale[e * N + i] += ds[e] * G.s[e];
-    }
-    dg.opacity_logit[i] += dop * G.o * (D(1) - G.o);
-    dg.mask_logit[i] += dk * G.k * (D(1) - G.k);
+    if (!any) return;
+    for (int e = 0; e < 3; ++e) dg.mean[e * N + i] += acc[e];
+    for (int e = 0; e < 4; ++e) dg.quat[e * N + i] += acc[3 + e];
+    for (int e = 0; e < 3; ++e) dg.log_scale[e * N + i] += acc[7 + e];
+    dg.opacity_logit[i] += acc[10];
+    dg.mask_logit[i] += acc[11];
     for (int c = 0; c < NC; ++c)
         for (int ch = 0; ch < 3; ++ch) dg.sh[((int64_t)c * 3 + ch) * N + i] += dsh[c][ch];
 }
@@ -546,15 +598,31 @@ hipError_t launch_project_bwd(const ugs_gaussians &g, const Problem &pb, const W
                               const ugs_gaussian_grads &dg, hipStream_t s)
 {
     if (g.N == 0) return hipSuccess;
-    dim3 grid((unsigned)((g.N + kProjThreads - 1) / kProjThreads));
     auto cams = (const DevCam *)(ws + L.cams);
     auto touched = (const uint32_t *)(ws + L.touched);
-    auto grec = (const float4 *)(ws + L.grec);
+    auto grec = (float4 *)(ws + L.grec);
+    auto cnt = (const DevCounters *)(ws + L.counters);
+    auto didx = (const uint32_t *)(ws + L.vlist);  // visible records in index order: coalesced parameter loads
+    const int64_t VN = L.VN;
+    const unsigned rec_blocks = (unsigned)std::min<int64_t>(std::max<int64_t>((VN + kProjThreads - 1) / kProjThreads, 1), 8192);
+    dim3 grid((unsigned)((g.N + kProjThreads - 1) / kProjThreads));
     switch (g.sh_deg) {
-    case 0: hipLaunchKernelGGL(project_bwd_kernel<0>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, touched, grec, dg); break;
-    case 1: hipLaunchKernelGGL(project_bwd_kernel<1>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, touched, grec, dg); break;
-    case 2: hipLaunchKernelGGL(project_bwd_kernel<2>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, touched, grec, dg); break;
-    default: hipLaunchKernelGGL(project_bwd_kernel<3>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, touched, grec, dg); break;
+    case 0:
+        hipLaunchKernelGGL(project_bwd_rec_kernel<0>, dim3(rec_blocks), dim3(kProjThreads), 0, s, g, cams, didx, cnt, touched, grec);
+        hipLaunchKernelGGL(project_bwd_sum_kernel<0>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, touched, (const float4 *)grec, dg);
+        break;
+    case 1:
+        hipLaunchKernelGGL(project_bwd_rec_kernel<1>, dim3(rec_blocks), dim3(kProjThreads), 0, s, g, cams, didx, cnt, touched, grec);
+        hipLaunchKernelGGL(project_bwd_sum_kernel<1>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, touched, (const float4 *)grec, dg);
+        break;
+    case 2:
+        hipLaunchKernelGGL(project_bwd_rec_kernel<2>, dim3(rec_blocks), dim3(kProjThreads), 0, s, g, cams, didx, cnt, touched, grec);
+        hipLaunchKernelGGL(project_bwd_sum_kernel<2>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, touched, (const float4 *)grec, dg);
+        break;
+    default:
+        hipLaunchKernelGGL(project_bwd_rec_kernel<3>, dim3(rec_blocks), dim3(kProjThreads), 0, s, g, cams, didx, cnt, touched, grec);
+        hipLaunchKernelGGL(project_bwd_sum_kernel<3>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, touched, (const float4 *)grec, dg);
+        break;
     }
     return hipGetLastError();
 }

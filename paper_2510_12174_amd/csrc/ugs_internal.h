@@ -57,7 +57,7 @@ struct DevCounters {
 };
 
 struct WsLayout {
-    size_t cams, rec, rect, touched, voff, poff, tsorted, dkey0, dkey1, didx0, didx1, scan_part, keys0, keys1, vals0,
+    size_t cams, rec, rect, touched, voff, poff, tsorted, dkey0, dkey1, didx0, didx1, vlist, scan_part, keys0, keys1, vals0,
         vals1, hist, digit_tot, ranges, grec, gd, nadj, counters, total;
     int64_t N, VN, total_tiles, total_pix, pair_cap;
     int V, nb_scan, depth_bits, tile_bits;
@@ -92,6 +92,10 @@ hipError_t launch_normal_fwd(const Problem &pb, const WsLayout &L, char *ws, con
 hipError_t launch_normal_bwd(const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out,
                              const ugs_upstream &up, const ugs_options &opt, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+// Which record-index buffer (0: didx0, 1: didx1) holds the depth-sorted visible
+// records after launch_binsort (the depth sort flips buffers once per 8 bits).
+// L.vlist holds the same records in index order.
+inline int depth_sort_buffer(const WsLayout &L) { return ((L.depth_bits + 7) / 8) & 1; }
 int channel_pad(int C_o);
 
 // index of the view owning a global tile (V small: linear scan over tile_base)
