@@ -142,6 +142,7 @@ def main():
     ap.add_argument("--workload", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-forward-only", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", default=None, help="force a tile shape, e.g. 16x16")
     ap.add_argument("--batch", type=int, default=0, help="force the LDS batch (with --tile)")
@@ -265,6 +266,27 @@ def main():
         t_pv = (time.perf_counter() - t0) / args.steps
         log(f"[bench] per-view {t_pv * 1e3:.3f} ms/step")
 
+    # forward-only form (viewer / inference): one captured graph per frame set,
+    # no upstream, no gradients, no T_final / n_contrib stores
+    fwd_only = None
+    if not args.no_forward_only:
+        fo = U.Rasterizer(prune_Tk=float(opts["prune_Tk"]), tile_w=rast.opts.tile_w, tile_h=rast.opts.tile_h,
+                          batch=rast.opts.batch)
+        out_fo = U.alloc_outputs(cams, C_o, state=False)
+        fo.capture_step(g, cams, out_fo, None, None)
+        for _ in range(args.warmup):
+            fo.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fo.replay()
+        torch.cuda.synchronize()
+        t_fo = (time.perf_counter() - t0) / args.steps
+        fwd_only = dict(value=round(Px / t_fo / 1e6, 2), unit="MP/s", ms_per_step=round(t_fo * 1e3, 3),
+                        views_per_s=round(len(cams) / t_fo, 1))
+        log(f"[bench] forward-only {t_fo * 1e3:.3f} ms per {len(cams)} views ({fwd_only['value']} MP/s)")
+        del fo, out_fo
+
     # quick parity spot check of the timed batched outputs (view 0, sampled pixels)
     parity = None
     try:
@@ -313,6 +335,7 @@ def main():
                            autotuned=tuned is not None),
                per_view=None if t_pv is None else dict(value=round(Px / t_pv / 1e6, 2), unit="MP/s",
                                                         ms_per_step=round(t_pv * 1e3, 3)),
+               forward_only=fwd_only,
                step_hbm=dict(alg_bytes=int(b_alg), frac=round(b_alg / t_batched / PEAK_HBM, 4)),
                counts=dict(pairs=P, records=V_rec, evaluated=F_eval, contributing=F_contrib),
                stage_ms={k: round(v, 4) for k, v in stage_ms.items()},

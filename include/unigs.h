@@ -84,7 +84,9 @@ typedef struct {
  * stencil leaves the image or is degenerate), sem [C_o] (Eq. semantic_render),
  * T_final [1] (transmittance after the last contributor, saved for the backward
  * as in Alg. forward_render), n_contrib [1] uint32 (one past the position, in the
- * pixel's tile list, of its last contributor). */
+ * pixel's tile list, of its last contributor).  T_final and n_contrib may be
+ * NULL for forward-only use (viewer/inference): they are then not stored, and
+ * the backward, which needs them, rejects such outputs. */
 typedef struct {
     float *rgb, *depth, *kmap, *normal, *sem, *T_final;
     uint32_t *n_contrib;
@@ -172,6 +174,9 @@ int ugs_render_bwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_out
 
 /* Batched training step: captures project -> bin_sort -> render_fwd ->
  * render_bwd for all V views into one HIP graph (no host synchronisation inside;
+ * with dout and dg both NULL, a forward-only step: project -> bin_sort ->
+ * render_fwd (normals included), for viewing or inference, where T_final and
+ * n_contrib may be NULL too;
  * the pair count stays on the device and is bounded by the workspace capacity).
  * ugs_step_replay launches it; a replay whose pair count overflowed returns
  * UGS_ERR_CAPACITY at the NEXT replay (outputs of the overflowing replay are

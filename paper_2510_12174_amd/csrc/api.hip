@@ -131,12 +131,19 @@ int check_grads(const ugs_gaussian_grads *d, int C_o)
     return UGS_OK;
 }
 
-int check_outputs(const ugs_outputs *o, int C_o)
+// The forward needs the image planes; T_final and n_contrib are optional for
+// it (forward-only use) and required by the backward.
+int check_outputs(const ugs_outputs *o, int C_o, bool need_state)
 {
     if (!o) return UGS_ERR_INVALID_ARG;
-    const void *ps[] = {o->rgb, o->depth, o->kmap, o->normal, o->T_final, o->n_contrib};
+    const void *ps[] = {o->rgb, o->depth, o->kmap, o->normal};
     for (auto p : ps)
         if (!p || !aligned(p, 4)) return UGS_ERR_INVALID_ARG;
+    const void *st[] = {o->T_final, o->n_contrib};
+    for (auto p : st) {
+        if (need_state && !p) return UGS_ERR_INVALID_ARG;
+        if (p && !aligned(p, 4)) return UGS_ERR_INVALID_ARG;
+    }
     if (C_o > 0 && (!o->sem || !aligned(o->sem, 4))) return UGS_ERR_INVALID_ARG;
     return UGS_OK;
 }
@@ -330,7 +337,7 @@ int upload_cams(ugs_ctx *ctx, const std::vector<DevCam> &dcs, hipStream_t s)
 }
 
 int do_project(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, int V, void *ws, size_t ws_bytes,
-               hipStream_t s)
+               hipStream_t s, bool zero_grec = true)
 {
     int rc;
     if ((rc = check_gaussians(g)) || (rc = check_cams(cams, V))) return rc;
@@ -353,7 +360,7 @@ int do_project(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, int
     ctx->sorted = false;
     if ((rc = upload_cams(ctx, dcs, s))) return rc;
     StageTimer tm(ctx, 1, s);
-    HIPCHK(ctx, launch_project_fwd(*g, ctx->pb, ctx->L, ctx->ws, true, s));
+    HIPCHK(ctx, launch_project_fwd(*g, ctx->pb, ctx->L, ctx->ws, zero_grec, s));
     return UGS_OK;
 }
 
@@ -388,7 +395,7 @@ int check_fwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs 
 {
     int rc;
     if (!ctx->sorted || ws != ctx->ws) return UGS_ERR_STATE;
-    if ((rc = check_gaussians(g)) || (rc = check_outputs(out, g->C_o))) return rc;
+    if ((rc = check_gaussians(g)) || (rc = check_outputs(out, g->C_o, false))) return rc;
     if (g->N != ctx->pb.N || g->C_o != ctx->pb.C_o || g->sh_deg != ctx->pb.sh_deg) return UGS_ERR_INVALID_ARG;
     return UGS_OK;
 }
@@ -398,6 +405,7 @@ int check_bwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs 
 {
     int rc;
     if ((rc = check_fwd(ctx, g, ws, out))) return rc;
+    if ((rc = check_outputs(out, g->C_o, true))) return rc;
     if ((rc = check_grads(dg, g->C_o))) return rc;
     return up ? UGS_OK : UGS_ERR_INVALID_ARG;
 }
@@ -421,9 +429,11 @@ int zero_grads(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_gaussian_grads *d
 int step_stage(ugs_ctx *ctx, const StepArgs &a, int st, hipStream_t s)
 {
     int rc;
+    // a step without gradients (forward only) has no backward stages
+    if (!a.dg && (st == 0 || (st >= 5 && st <= 7))) return UGS_OK;
     switch (st) {
     case 0: return zero_grads(ctx, a.g, a.dg, s);
-    case 1: return do_project(ctx, a.g, a.cams, a.V, a.ws, a.ws_bytes, s);
+    case 1: return do_project(ctx, a.g, a.cams, a.V, a.ws, a.ws_bytes, s, a.dg != nullptr);
     case 2: return do_bin_sort(ctx, a.ws, s, nullptr);
     case 3: {
         if ((rc = check_fwd(ctx, a.g, a.ws, a.out))) return rc;
@@ -658,10 +668,13 @@ int ugs_step_capture(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cam
 {
     if (!ctx) return UGS_ERR_INVALID_ARG;
     int rc;
-    if ((rc = check_gaussians(g)) || (rc = check_cams(cams, V)) || (rc = check_outputs(out, g->C_o)) ||
-        (rc = check_grads(dg, g->C_o)))
+    // dout and dg both NULL: a forward-only step (project, bin_sort, render_fwd, normals)
+    const bool fwd_only = !dout && !dg;
+    if ((rc = check_gaussians(g)) || (rc = check_cams(cams, V)) || (rc = check_outputs(out, g->C_o, !fwd_only)) ||
+        (!fwd_only && (rc = check_grads(dg, g->C_o))))
         return rc;
-    if (!dout || !ws) return UGS_ERR_INVALID_ARG;
+    if ((!fwd_only && !dout) || !ws) return UGS_ERR_INVALID_ARG;
+    if (fwd_only && ctx->timed_stage >= 5) return UGS_ERR_INVALID_ARG;
     release_graph(ctx);
     hipStream_t s = (hipStream_t)stream;
     if (!ctx->host_flag) {

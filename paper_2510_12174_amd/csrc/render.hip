@@ -287,8 +287,8 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
         out.rgb[3 * off + 2 * HW + p] = cb;
         out.depth[off + p] = (float)D;
         out.kmap[off + p] = K;
-        out.T_final[off + p] = (float)T;
-        out.n_contrib[off + p] = last ? last - range.x : 0u;
+        if (out.T_final) out.T_final[off + p] = (float)T;  // optional in forward-only use
+        if (out.n_contrib) out.n_contrib[off + p] = last ? last - range.x : 0u;
         if constexpr (CO > 0) {
 #pragma unroll
             for (int c = 0; c < CO; ++c)
@@ -827,8 +827,8 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
         out.rgb[3 * off + 2 * HW + p] = cb;
         out.depth[off + p] = (float)D;
         out.kmap[off + p] = K;
-        out.T_final[off + p] = (float)T;
-        out.n_contrib[off + p] = last ? last - range.x : 0u;
+        if (out.T_final) out.T_final[off + p] = (float)T;  // optional in forward-only use
+        if (out.n_contrib) out.n_contrib[off + p] = last ? last - range.x : 0u;
     }
     // O~ from the MFMA layout: acc[pb][q][r] is pixel 16 pb + 4 h16 + r, channel 16 q + l16
     {

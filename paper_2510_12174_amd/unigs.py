@@ -232,12 +232,16 @@ def pixel_offsets(cams):
     return off
 
 
-def alloc_outputs(cams, C_o, device="cuda"):
+def alloc_outputs(cams, C_o, device="cuda", state=True):
+    """Output planes for all views; state=False leaves out T_final and
+    n_contrib (forward-only use: the backward needs them)."""
     import torch
     P = pixel_offsets(cams)[-1]
     f = lambda n: torch.empty(n, dtype=torch.float32, device=device)
-    return dict(rgb=f(3 * P), depth=f(P), kmap=f(P), normal=f(3 * P), sem=f(max(C_o, 0) * P), T_final=f(P),
-                n_contrib=torch.empty(P, dtype=torch.int32, device=device))
+    o = dict(rgb=f(3 * P), depth=f(P), kmap=f(P), normal=f(3 * P), sem=f(max(C_o, 0) * P))
+    if state:
+        o.update(T_final=f(P), n_contrib=torch.empty(P, dtype=torch.int32, device=device))
+    return o
 
 
 def split_views(flat, cams, channels):
@@ -373,10 +377,13 @@ class Rasterizer:
     # batched step ------------------------------------------------------
     def capture_step(self, g, cams, out, up, grads, margin=1.25):
         """Sizes the workspace from an eager pass (pair count x margin) and
-        captures the whole fwd+bwd step for all views into one HIP graph."""
+        captures the whole fwd+bwd step for all views into one HIP graph; with
+        up and grads both None, the forward-only step."""
         P = self.project_and_sort(g, cams)
         self.ensure_workspace(g, cams, max(int(P * margin) + 4096, self.pair_cap))
-        self._keep = [make_gaussians(g), make_cameras(cams), make_outputs(out), make_upstream(up), make_grads(grads)]
+        fwd_only = up is None and grads is None
+        self._keep = [make_gaussians(g), make_cameras(cams), make_outputs(out),
+                      None if fwd_only else make_upstream(up), None if fwd_only else make_grads(grads)]
         gs, cs, os_, us, ds = self._keep
         # capture needs a non-default stream; the graph is launched later on
         # whatever stream is current
@@ -386,7 +393,8 @@ class Rasterizer:
         side.wait_stream(cur)
         with torch.cuda.stream(side):
             rc = lib().ugs_step_capture(self.ctx, C.byref(gs), cs, len(cams), self.ws_ptr, self.ws_bytes,
-                                        C.byref(os_), C.byref(us), C.byref(ds), C.c_void_p(side.cuda_stream))
+                                        C.byref(os_), C.byref(us) if us is not None else None,
+                                        C.byref(ds) if ds is not None else None, C.c_void_p(side.cuda_stream))
         cur.wait_stream(side)
         _chk(rc, "ugs_step_capture", self.ctx)
 

@@ -279,6 +279,38 @@ def test_graph_replay_matches_eager(O):
             assert np.max(np.abs(a - b) / (1e-4 * np.abs(b) + 1e-4 * scale)) <= 1.0, (rep, k)
 
 
+def test_forward_only_step(O):
+    """The forward-only captured step (viewer/inference: no upstream, no
+    gradients, no T_final / n_contrib stores) gives the training step's forward
+    outputs bit for bit on every replay, and the backward refuses outputs
+    without the saved state."""
+    import torch
+    from paper_2510_12174_amd import unigs as U
+    g, cams, opts = Hn.small_workload("w4s")
+    eager_out, _, _ = Hn.gpu_run(g, cams, opts)
+    gd = U.to_device(g)
+    rast = U.Rasterizer(prune_Tk=float(opts.get("prune_Tk", 0.0)))
+    out = U.alloc_outputs(cams, g["C_o"], state=False)
+    assert "T_final" not in out
+    rast.capture_step(gd, cams, out, None, None)
+    for rep in range(3):
+        rast.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()
+        P = U.pixel_offsets(cams)[-1]
+        full = dict(out, T_final=torch.zeros(P, device="cuda"), n_contrib=torch.zeros(P, dtype=torch.int32, device="cuda"))
+        outs = Hn.unstack(full, cams, g["C_o"])
+        for x, y in zip(outs, eager_out):
+            for k in ("rgb", "depth", "kmap", "normal", "sem"):
+                assert np.array_equal(x[k], y[k]), (rep, k)
+    # the backward needs T_final and n_contrib
+    r2 = U.Rasterizer(prune_Tk=float(opts.get("prune_Tk", 0.0)))
+    o2 = r2.forward(gd, cams, U.alloc_outputs(cams, g["C_o"], state=False))
+    ups = Hn.scenes.upstream(cams, g["C_o"], seed=9)
+    with pytest.raises(U.UgsError):
+        r2.backward(gd, o2, Hn.stack_upstream(ups, g["C_o"]))
+
+
 def test_autograd_function_matches_oracle(O):
     import torch
     from paper_2510_12174_amd import unigs as U
