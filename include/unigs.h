@@ -236,6 +236,28 @@ const char *ugs_last_hip_error(const ugs_ctx *ctx);
 int ugs_enable_counters(ugs_ctx *ctx, int on);
 int ugs_read_counters(ugs_ctx *ctx, void *ws, void *stream, int64_t *evaluated, int64_t *contributing);
 
+/* Scratch bytes (device memory) that ugs_prune needs for N Gaussians. */
+int ugs_prune_scratch_size(int64_t N, size_t *bytes);
+
+/* Differentiable pruning (section 3.3, "Pruning"): keeps the Gaussians whose
+ * gradient factor k = sigmoid(mask_logit) satisfies |k - 1| <= T_k -- the test
+ * of the projection's pruning skip, evaluated in FP64 -- and compacts, in index
+ * order, every parameter array of `g` into `out`, and each of the `n_state`
+ * state sets state_in[s] (per-Gaussian arrays laid out like the parameters,
+ * e.g. optimiser moments; NULL fields are skipped; their N, sh_deg and C_o are
+ * taken from `g`) into state_out[s].  Output arrays are caller-owned device
+ * memory with room for g->N Gaussians; their structure-of-arrays rows are
+ * packed at the kept count (row r of `mean` starts at r * n_kept), `sem` rows
+ * stay [n_kept][C_o].  With reset_k != 0 the kept mask logits in `out` become
+ * ln 9 (k = 0.9), the paper's reset after pruning.  `scratch` (device,
+ * 256-byte aligned, ugs_prune_scratch_size bytes) is overwritten; inputs and
+ * outputs must not overlap.  Synchronises `stream`; returns the kept count in
+ * *n_kept.  Errors: UGS_ERR_INVALID_ARG (NULL or misaligned pointers, T_k < 0,
+ * scratch too small), UGS_ERR_HIP. */
+int ugs_prune(const ugs_gaussians *g, const ugs_gaussian_grads *out, int n_state, const ugs_gaussians *state_in,
+              const ugs_gaussian_grads *state_out, float T_k, int reset_k, void *scratch, size_t scratch_bytes,
+              int64_t *n_kept, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -342,3 +342,36 @@ def bin_sort(rect, depth_f32, tiles_x, tile_base, N, cull=None):
     keys, gid, dbits, tile, amb = keys[sel], gid[sel], dbits[sel], tile[sel], amb[sel]
     order = np.lexsort((gid, dbits, tile))
     return keys[order], gid[order], kept_counts, amb[order], amb_counts
+
+
+# ------------------------------------------------------------------ pruning
+def prune(g, T_k, reset=True, states=()):
+    """Differentiable pruning (section 3.3, "Pruning"): keep the Gaussians with
+    |k - 1| <= T_k, k = sigmoid(mask_logit) (FP64, T_k rounded to FP32 as the
+    option is), compacted in index order; with reset, the kept mask logits
+    become float32(ln 9), i.e. k = 0.9.  `states` are dicts of arrays laid out
+    like the parameters.  Returns (pruned dict, pruned states, keep mask,
+    ambiguity mask: decisions within 1e-12 relative of the threshold)."""
+    N = int(g["N"])
+    m = np.asarray(g["mask_logit"], np.float64).reshape(N)
+    dev = np.abs(1.0 / (1.0 + np.exp(-m)) - 1.0)
+    T = float(np.float32(T_k))
+    keep = dev <= T
+    amb = np.abs(dev - T) <= 1e-12 * max(T, 1e-300)
+
+    def compact(d):
+        out = {}
+        for k in ("mean", "quat", "log_scale", "opacity_logit", "mask_logit", "sh", "sem"):
+            a = d.get(k)
+            if a is None:
+                out[k] = None
+                continue
+            a = np.asarray(a)
+            out[k] = np.ascontiguousarray(a[keep] if k == "sem" else a[..., keep])
+        return out
+
+    res = compact(g)
+    res.update(N=int(keep.sum()), sh_deg=int(g["sh_deg"]), C_o=int(g["C_o"]))
+    if reset:
+        res["mask_logit"] = np.full(res["N"], np.float32(np.log(9.0)), np.float32)
+    return res, [compact(st) for st in states], keep, amb

@@ -517,6 +517,15 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_scan_flags(const uint32_t *flags, int64_t n, uint32_t *part, uint32_t *out, uint32_t *total,
+                             hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int nb = (int)((n + kScanBlock - 1) / kScanBlock);
+    scan(ScanIn{flags, n, nullptr, 1}, nb, part, out, -1, total, nullptr, nullptr, nullptr, s);
+    return hipGetLastError();
+}
+
 hipError_t launch_binsort(const Problem &pb, const WsLayout &L, char *ws, hipStream_t s, int *final_buf)
 {
     auto cams = (const DevCam *)(ws + L.cams);

@@ -92,6 +92,10 @@ hipError_t launch_normal_fwd(const Problem &pb, const WsLayout &L, char *ws, con
 hipError_t launch_normal_bwd(const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out,
                              const ugs_upstream &up, const ugs_options &opt, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+// Exclusive scan of (flags[i] > 0) over n elements into out, total to *total;
+// part holds ceil(n / kScanBlock) partials.
+hipError_t launch_scan_flags(const uint32_t *flags, int64_t n, uint32_t *part, uint32_t *out, uint32_t *total,
+                             hipStream_t s);
 // Which record-index buffer (0: didx0, 1: didx1) holds the depth-sorted visible
 // records after launch_binsort (the depth sort flips buffers once per 8 bits).
 // L.vlist holds the same records in index order.

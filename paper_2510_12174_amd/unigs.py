@@ -32,7 +32,8 @@ UGS_MAX_VIEWS = 64
 EXPORTS = ["ugs_default_options", "ugs_create", "ugs_destroy", "ugs_set_options", "ugs_workspace_size",
            "ugs_project", "ugs_bin_sort", "ugs_check_overflow", "ugs_render_fwd", "ugs_render_bwd",
            "ugs_step_capture", "ugs_step_replay", "ugs_autotune", "ugs_pair_count", "ugs_status_string",
-           "ugs_last_hip_error", "ugs_enable_counters", "ugs_read_counters", "ugs_debug_buffer", "ugs_time_stage"]
+           "ugs_last_hip_error", "ugs_enable_counters", "ugs_read_counters", "ugs_debug_buffer", "ugs_time_stage",
+           "ugs_prune_scratch_size", "ugs_prune"]
 
 
 class UgsError(RuntimeError):
@@ -111,6 +112,10 @@ def lib():
         L.ugs_read_counters.argtypes = [P, P, P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.ugs_debug_buffer.argtypes = [P, P, C.c_int, P, C.POINTER(C.c_void_p), C.POINTER(C.c_int64)]
         L.ugs_time_stage.argtypes = [P, C.c_int, P, P]
+        L.ugs_prune_scratch_size.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
+        L.ugs_prune.argtypes = [C.POINTER(ugs_gaussians), C.POINTER(ugs_gaussian_grads), C.c_int,
+                                C.POINTER(ugs_gaussians), C.POINTER(ugs_gaussian_grads), C.c_float, C.c_int, P,
+                                C.c_size_t, C.POINTER(C.c_int64), P]
         _lib = L
     return _lib
 
@@ -223,6 +228,49 @@ def to_device(g, device="cuda"):
 def zeros_like_params(g):
     import torch
     return {k: torch.zeros_like(g[k]) for k in PARAM_KEYS}
+
+
+def prune(g, T_k, reset_k=True, states=()):
+    """Differentiable pruning (ugs_prune): returns (pruned parameter dict,
+    list of pruned state dicts, kept count).  `states` are dicts with the
+    parameter keys (None for absent arrays), laid out like the parameters."""
+    import torch
+    N = int(g["N"])
+    out = {k: torch.empty_like(g[k]) for k in PARAM_KEYS}
+    outs_state = [{k: (torch.empty_like(st[k]) if st.get(k) is not None else None) for k in PARAM_KEYS}
+                  for st in states]
+    nb = C.c_size_t()
+    _chk(lib().ugs_prune_scratch_size(N, C.byref(nb)), "ugs_prune_scratch_size")
+    scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=g["mean"].device)
+    gs = make_gaussians(g)
+    os_ = make_grads(out)
+    n_state = len(states)
+    sin = (ugs_gaussians * max(n_state, 1))()
+    sout = (ugs_gaussian_grads * max(n_state, 1))()
+    for k_, (st, so) in enumerate(zip(states, outs_state)):
+        sin[k_].N, sin[k_].sh_deg, sin[k_].C_o = N, int(g["sh_deg"]), int(g["C_o"])
+        for key in PARAM_KEYS:
+            setattr(sin[k_], key, st[key].data_ptr() if st.get(key) is not None else None)
+            setattr(sout[k_], key, so[key].data_ptr() if so.get(key) is not None else None)
+    nk = C.c_int64()
+    _chk(lib().ugs_prune(C.byref(gs), C.byref(os_), n_state, sin, sout, float(T_k), int(bool(reset_k)),
+                         C.c_void_p(scratch.data_ptr()), int(nb.value), C.byref(nk), _stream()), "ugs_prune")
+    n = int(nk.value)
+
+    def view(key, t):
+        if t is None:
+            return None
+        if key == "sem":  # [N][C_o], row-major per Gaussian
+            return t[:n]
+        shape = tuple(g[key].shape[:-1])  # structure of arrays: rows packed at stride n
+        rows = int(np.prod(shape)) if shape else 1
+        return t.view(-1)[:rows * n].view(*shape, n)
+
+    res = dict(N=n, sh_deg=int(g["sh_deg"]), C_o=int(g["C_o"]))
+    for key in PARAM_KEYS:
+        res[key] = view(key, out[key])
+    res_states = [{key: view(key, so[key]) for key in PARAM_KEYS} for so in outs_state]
+    return res, res_states, n
 
 
 def pixel_offsets(cams):

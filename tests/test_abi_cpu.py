@@ -117,3 +117,30 @@ def test_calls_rejected_before_launch(U):
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.ugs_status_string(code)
     L.ugs_destroy(ctx)
+
+
+def test_prune_rejections(U):
+    """ugs_prune validates before touching the device."""
+    L = U.lib()
+    nb = C.c_size_t()
+    assert L.ugs_prune_scratch_size(1000, C.byref(nb)) == U.UGS_OK and nb.value >= 8000
+    assert L.ugs_prune_scratch_size(-1, C.byref(nb)) == U.UGS_ERR_INVALID_ARG
+    g = U.ugs_gaussians()
+    g.N, g.sh_deg, g.C_o = 10, 0, 0
+    g.mask_logit = 256
+    out = U.ugs_gaussian_grads()
+    n = C.c_int64()
+    # NULL parameter set, NULL count, negative threshold, missing scratch
+    assert L.ugs_prune(None, C.byref(out), 0, None, None, 0.2, 1, C.c_void_p(256), 4096, C.byref(n), None) \
+        == U.UGS_ERR_INVALID_ARG
+    assert L.ugs_prune(C.byref(g), C.byref(out), 0, None, None, 0.2, 1, C.c_void_p(256), 4096, None, None) \
+        == U.UGS_ERR_INVALID_ARG
+    assert L.ugs_prune(C.byref(g), C.byref(out), 0, None, None, -0.1, 1, C.c_void_p(256), 4096, C.byref(n), None) \
+        == U.UGS_ERR_INVALID_ARG
+    assert L.ugs_prune(C.byref(g), C.byref(out), 0, None, None, 0.2, 1, None, 4096, C.byref(n), None) \
+        == U.UGS_ERR_INVALID_ARG
+    # scratch too small, state sets announced but missing
+    assert L.ugs_prune(C.byref(g), C.byref(out), 0, None, None, 0.2, 1, C.c_void_p(256), 8, C.byref(n), None) \
+        == U.UGS_ERR_INVALID_ARG
+    assert L.ugs_prune(C.byref(g), C.byref(out), 2, None, None, 0.2, 1, C.c_void_p(256), 4096, C.byref(n), None) \
+        == U.UGS_ERR_INVALID_ARG

@@ -491,3 +491,34 @@ def test_bin_sort_cull_is_conservative(oracle_mod):
                 elif (alpha < 0.5 / 255).all() and (tile, i) not in kept:
                     dropped += 1
     assert dropped > 50
+
+
+def test_prune_reference(oracle_mod):
+    """Pruning (section 3.3): the kept set is exactly {|sigmoid(m) - 1| <= T_k}
+    by a plain loop, index order is kept, T_k >= 1 keeps everything, T_k = 0
+    keeps only k == 1, and the reset logit ln 9 gives k = 0.9."""
+    import math
+    O = oracle_mod
+    g, cams, opts = scenes.tiny_scene(n=200, seed=13, sh_deg=2, C_o=5)
+    g = dict(g)
+    rng = np.random.default_rng(13)
+    m = rng.normal(1.5, 1.5, g["N"]).astype(np.float32)
+    m[:5] = 40.0  # k == 1 in FP64
+    g["mask_logit"] = m
+    st = {k: (np.asarray(g[k]) * 2 + 1).astype(np.float32) for k in ("mean", "quat", "sh", "sem")}
+    for T in (0.0, 0.2, 0.5, 1.0):
+        res, (rst,), keep, amb = O.prune(g, T, reset=True, states=[st])
+        want = [i for i in range(g["N"]) if abs(1.0 / (1.0 + math.exp(-float(m[i]))) - 1.0) <= float(np.float32(T))]
+        assert list(np.nonzero(keep)[0]) == want
+        assert res["N"] == len(want)
+        assert np.array_equal(res["mean"], np.asarray(g["mean"])[:, want])
+        assert np.array_equal(res["sh"], np.asarray(g["sh"])[..., want])
+        assert np.array_equal(res["sem"], np.asarray(g["sem"])[want])
+        assert np.array_equal(rst["quat"], st["quat"][:, want])
+        assert rst["log_scale"] is None
+        assert np.all(res["mask_logit"] == np.float32(np.log(9.0)))
+        if T >= 1.0:
+            assert res["N"] == g["N"]
+        if T == 0.0:
+            assert res["N"] == 5
+    assert abs(1.0 / (1.0 + math.exp(-math.log(9.0))) - 0.9) < 1e-15
