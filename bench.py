@@ -143,6 +143,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-forward-only", action="store_true")
+    ap.add_argument("--no-prune", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", default=None, help="force a tile shape, e.g. 16x16")
     ap.add_argument("--batch", type=int, default=0, help="force the LDS batch (with --tile)")
@@ -287,6 +288,29 @@ def main():
         log(f"[bench] forward-only {t_fo * 1e3:.3f} ms per {len(cams)} views ({fwd_only['value']} MP/s)")
         del fo, out_fo
 
+    # differentiable pruning (section 3.3): compaction of the parameters and two
+    # optimiser-moment sets at T_k = 0.2; HBM-bound (every array read once, the
+    # kept part written once)
+    prune_res = None
+    if not args.no_prune:
+        moments = [{k: torch.zeros_like(g[k]) for k in U.PARAM_KEYS} for _ in range(2)]
+        for _ in range(2):
+            U.prune(g, 0.2, reset_k=True, states=moments)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, _, n_kept = U.prune(g, 0.2, reset_k=True, states=moments)
+        torch.cuda.synchronize()
+        t_pr = (time.perf_counter() - t0) / reps
+        floats = sum(int(g[k].numel()) for k in U.PARAM_KEYS) // N  # per Gaussian
+        b_pr = 3 * 4 * floats * (N + n_kept) + 4 * N
+        prune_res = dict(ms=round(t_pr * 1e3, 3), kept=int(n_kept), gaussians=N, state_sets=2,
+                         achieved_gbps=round(b_pr / t_pr / 1e9, 1), peak_gbps=PEAK_HBM / 1e9,
+                         frac=round(b_pr / t_pr / PEAK_HBM, 4), note="includes the host read-back of the count")
+        log(f"[bench] prune {prune_res}")
+        del moments
+
     # quick parity spot check of the timed batched outputs (view 0, sampled pixels)
     parity = None
     try:
@@ -335,7 +359,7 @@ def main():
                            autotuned=tuned is not None),
                per_view=None if t_pv is None else dict(value=round(Px / t_pv / 1e6, 2), unit="MP/s",
                                                         ms_per_step=round(t_pv * 1e3, 3)),
-               forward_only=fwd_only,
+               forward_only=fwd_only, prune=prune_res,
                step_hbm=dict(alg_bytes=int(b_alg), frac=round(b_alg / t_batched / PEAK_HBM, 4)),
                counts=dict(pairs=P, records=V_rec, evaluated=F_eval, contributing=F_contrib),
                stage_ms={k: round(v, 4) for k, v in stage_ms.items()},

@@ -23,32 +23,82 @@ __global__ void __launch_bounds__(kPruneThreads) prune_flags(const float *__rest
     flags[i] = fabs(k - 1.0) > T_k ? 0u : 1u;
 }
 
-// Copies row r (stride N in, stride M out) of a structure-of-arrays field.
-__device__ __forceinline__ void copy_rows(const float *in, float *out, int rows, int64_t N, int64_t M, int64_t i,
-                                          int64_t j)
-{
-    if (!in || !out) return;
-    for (int r = 0; r < rows; ++r) out[r * M + j] = in[r * N + i];
-}
+// One structure-of-arrays row per grid row: src points at the input row
+// (length N), dst at the output field, whose row `rl` starts at rl * M with M
+// the kept count (known on the device only).
+constexpr int kMaxRows = 64;
+struct RowTable {
+    const float *src[kMaxRows];
+    float *dst[kMaxRows];
+    int rl[kMaxRows];
+    int reset[kMaxRows];  // write reset_logit instead of copying (mask logits)
+};
 
-__global__ void __launch_bounds__(kPruneThreads) prune_scatter(ugs_gaussians in, ugs_gaussian_grads out, int nsh,
-                                                               const uint32_t *__restrict__ flags,
-                                                               const uint32_t *__restrict__ pos,
-                                                               const uint32_t *__restrict__ total, int reset,
-                                                               float reset_logit)
+// One thread per (Gaussian, row): every element is one coalesced load and one
+// coalesced store, so the copy runs at memory speed instead of walking a
+// Gaussian's rows one after the other.
+__global__ void __launch_bounds__(kPruneThreads) prune_rows(RowTable t, int64_t N, const uint32_t *__restrict__ flags,
+                                                            const uint32_t *__restrict__ pos,
+                                                            const uint32_t *__restrict__ total, float reset_logit)
 {
-    const int64_t N = in.N;
     const int64_t i = (int64_t)blockIdx.x * kPruneThreads + threadIdx.x;
+    const int r = blockIdx.y;
     if (i >= N || !flags[i]) return;
     const int64_t j = pos[i], M = *total;
-    copy_rows(in.mean, out.mean, 3, N, M, i, j);
-    copy_rows(in.quat, out.quat, 4, N, M, i, j);
-    copy_rows(in.log_scale, out.log_scale, 3, N, M, i, j);
-    copy_rows(in.opacity_logit, out.opacity_logit, 1, N, M, i, j);
-    if (out.mask_logit) out.mask_logit[j] = reset ? reset_logit : (in.mask_logit ? in.mask_logit[i] : 0.f);
-    copy_rows(in.sh, out.sh, nsh, N, M, i, j);
-    if (in.sem && out.sem)
-        for (int c = 0; c < in.C_o; ++c) out.sem[j * in.C_o + c] = in.sem[i * in.C_o + c];
+    t.dst[r][t.rl[r] * M + j] = t.reset[r] ? reset_logit : t.src[r][i];
+}
+
+// Row-major [N][C] arrays (semantic logits): one thread per element.
+__global__ void __launch_bounds__(kPruneThreads) prune_rowmajor(const float *__restrict__ src, float *__restrict__ dst,
+                                                                int64_t N, int C, const uint32_t *__restrict__ flags,
+                                                                const uint32_t *__restrict__ pos)
+{
+    const int64_t e = (int64_t)blockIdx.x * kPruneThreads + threadIdx.x;
+    if (e >= N * C) return;
+    const int64_t i = e / C;
+    if (!flags[i]) return;
+    dst[(int64_t)pos[i] * C + (e - i * C)] = src[e];
+}
+
+// Fills the row table of one parameter set; returns the row count.
+int row_table(const ugs_gaussians &in, const ugs_gaussian_grads &out, int nsh, int reset, RowTable &t)
+{
+    int n = 0;
+    auto add = [&](const float *src, float *dst, int rows, int rs) {
+        if (!src || !dst) return;
+        for (int r = 0; r < rows; ++r) {
+            t.src[n] = src + (int64_t)r * in.N;
+            t.dst[n] = dst;
+            t.rl[n] = r;
+            t.reset[n] = rs;
+            ++n;
+        }
+    };
+    add(in.mean, out.mean, 3, 0);
+    add(in.quat, out.quat, 4, 0);
+    add(in.log_scale, out.log_scale, 3, 0);
+    add(in.opacity_logit, out.opacity_logit, 1, 0);
+    if (reset && out.mask_logit) add(out.mask_logit, out.mask_logit, 1, 1);  // src unused
+    else add(in.mask_logit, out.mask_logit, 1, 0);
+    add(in.sh, out.sh, nsh, 0);
+    return n;
+}
+
+int compact_set(const ugs_gaussians &in, const ugs_gaussian_grads &out, int nsh, int reset, const uint32_t *flags,
+                const uint32_t *pos, const uint32_t *total, float reset_logit, hipStream_t s)
+{
+    RowTable t;
+    const int n = row_table(in, out, nsh, reset, t);
+    const unsigned bx = (unsigned)((in.N + kPruneThreads - 1) / kPruneThreads);
+    if (n > 0)
+        hipLaunchKernelGGL(prune_rows, dim3(bx, (unsigned)n), dim3(kPruneThreads), 0, s, t, in.N, flags, pos, total,
+                           reset_logit);
+    if (in.sem && out.sem && in.C_o > 0) {
+        const int64_t ne = in.N * in.C_o;
+        hipLaunchKernelGGL(prune_rowmajor, dim3((unsigned)((ne + kPruneThreads - 1) / kPruneThreads)),
+                           dim3(kPruneThreads), 0, s, in.sem, out.sem, in.N, in.C_o, flags, pos);
+    }
+    return hipGetLastError() == hipSuccess ? UGS_OK : UGS_ERR_HIP;
 }
 
 int64_t scan_parts(int64_t N) { return (N + kScanBlock - 1) / kScanBlock; }
@@ -98,17 +148,15 @@ int ugs_prune(const ugs_gaussians *g, const ugs_gaussian_grads *out, int n_state
     if (launch_scan_flags(flags, N, part, pos, total, s) != hipSuccess) return UGS_ERR_HIP;
     // logit(0.9) = ln 9
     const float reset_logit = 2.19722457733621956f;
-    hipLaunchKernelGGL(prune_scatter, dim3(blocks), dim3(kPruneThreads), 0, s, *g, *out, nsh, (const uint32_t *)flags,
-                       (const uint32_t *)pos, (const uint32_t *)total, reset_k ? 1 : 0, reset_logit);
-    for (int k = 0; k < n_state; ++k) {
+    int rc = compact_set(*g, *out, nsh, reset_k ? 1 : 0, flags, pos, total, reset_logit, s);
+    for (int k = 0; k < n_state && rc == UGS_OK; ++k) {
         ugs_gaussians si = state_in[k];
         si.N = N;
         si.sh_deg = g->sh_deg;
         si.C_o = g->C_o;
-        hipLaunchKernelGGL(prune_scatter, dim3(blocks), dim3(kPruneThreads), 0, s, si, state_out[k], nsh,
-                           (const uint32_t *)flags, (const uint32_t *)pos, (const uint32_t *)total, 0, 0.f);
+        rc = compact_set(si, state_out[k], nsh, 0, flags, pos, total, 0.f, s);
     }
-    if (hipGetLastError() != hipSuccess) return UGS_ERR_HIP;
+    if (rc != UGS_OK) return rc;
     uint32_t h = 0;
     if (hipMemcpyAsync(&h, total, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
         return UGS_ERR_HIP;
