@@ -144,6 +144,7 @@ def main():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-forward-only", action="store_true")
     ap.add_argument("--no-prune", action="store_true")
+    ap.add_argument("--no-loss", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", default=None, help="force a tile shape, e.g. 16x16")
     ap.add_argument("--batch", type=int, default=0, help="force the LDS batch (with --tile)")
@@ -311,6 +312,37 @@ def main():
         log(f"[bench] prune {prune_res}")
         del moments
 
+    # training loss of section 3.4 on the batched outputs against synthetic
+    # targets: values and every upstream map, on the device (graph-capturable)
+    loss_res = None
+    if not args.no_loss:
+        gen = torch.Generator(device="cuda").manual_seed(1000 * wl + 7)
+        gt = dict(rgb=(out["rgb"] + 0.05 * torch.randn(out["rgb"].shape, device="cuda", generator=gen)).clamp_(0, 1),
+                  depth=out["depth"] * (1 + 0.05 * torch.randn(out["depth"].shape, device="cuda", generator=gen)),
+                  normal=torch.nn.functional.normalize(
+                      out["normal"].view(-1, 3, 1) + 0.2 * torch.randn(out["normal"].numel() // 3, 3, 1,
+                                                                       device="cuda", generator=gen), dim=1).view(-1),
+                  label=torch.randint(0, max(C_o, 1), (Px,), device="cuda", generator=gen, dtype=torch.int32)
+                  if C_o else None)
+        lossf = U.Loss(cams, C_o)
+        for _ in range(2):
+            lossf(out, gt)
+        torch.cuda.synchronize()
+        reps = 10
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        for _ in range(reps):
+            lv, _ = lossf(out, gt)
+        s1.record()
+        torch.cuda.synchronize()
+        t_l = s0.elapsed_time(s1) / reps * 1e-3
+        b_l = (96 + 8 * C_o) * Px  # every input map read once, every gradient map written once
+        loss_res = dict(ms=round(t_l * 1e3, 3), alg_bytes=int(b_l), achieved_gbps=round(b_l / t_l / 1e9, 1),
+                        peak_gbps=PEAK_HBM / 1e9, frac=round(b_l / t_l / PEAK_HBM, 4),
+                        values=dict(zip(U.LOSS_NAMES, [round(float(x), 6) for x in lv.cpu()])))
+        log(f"[bench] loss {loss_res}")
+        del gt, lossf
+
     # quick parity spot check of the timed batched outputs (view 0, sampled pixels)
     parity = None
     try:
@@ -359,7 +391,7 @@ def main():
                            autotuned=tuned is not None),
                per_view=None if t_pv is None else dict(value=round(Px / t_pv / 1e6, 2), unit="MP/s",
                                                         ms_per_step=round(t_pv * 1e3, 3)),
-               forward_only=fwd_only, prune=prune_res,
+               forward_only=fwd_only, prune=prune_res, loss=loss_res,
                step_hbm=dict(alg_bytes=int(b_alg), frac=round(b_alg / t_batched / PEAK_HBM, 4)),
                counts=dict(pairs=P, records=V_rec, evaluated=F_eval, contributing=F_contrib),
                stage_ms={k: round(v, 4) for k, v in stage_ms.items()},

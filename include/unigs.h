@@ -258,6 +258,55 @@ int ugs_prune(const ugs_gaussians *g, const ugs_gaussian_grads *out, int n_state
               const ugs_gaussian_grads *state_out, float T_k, int reset_k, void *scratch, size_t scratch_bytes,
               int64_t *n_kept, void *stream);
 
+/* ---------------------------------------------------------------- losses
+ * The training loss of section 3.4 ("Loss Function") on the rendered maps,
+ * producing the upstream gradients that ugs_render_bwd consumes, on the device
+ * and without host synchronisation (graph-capturable).  Terms, each a mean
+ * over the P pixels of all views (RGB terms over 3P values):
+ *   L_l1     = mean |C - C_gt|;
+ *   L_ssim   = 1 - mean SSIM(C, C_gt) per channel (11x11 Gaussian window,
+ *              sigma 1.5, C1 = 0.01^2, C2 = 0.03^2, zero padding);
+ *   L_normal = 1 - mean N . N_gt (Eq. csloss; its gradient is the seed
+ *              -N_gt / P of Eq. gradientn);
+ *   L_depth  = mean |D - D_gt| (the paper names it without a definition);
+ *   L_seg    = mean cross-entropy of softmax(O) against the class label
+ *              (a label outside [0, C_o) marks a pixel that adds nothing);
+ *   L_K      = mean |K - 1| (Eq. for L_K).
+ * L_all = l1 L_l1 + sum_x lambda_x w_x L_x with w_x = |L_l1| / |L_x| when
+ * `balance` is set (the equation for L_all; the ratios are held constant in
+ * the gradient; 0 when L_x is 0) and 1 otherwise.  A NULL target drops its
+ * term (its loss and gradient are 0). */
+typedef struct {
+    const float *rgb;      /* [3][H][W] per view, stacked like ugs_outputs */
+    const float *depth;    /* [H][W] per view, or NULL */
+    const float *normal;   /* [3][H][W] per view, or NULL */
+    const int32_t *label;  /* [H][W] class index in [0, C_o) per view, or NULL */
+} ugs_targets;
+
+typedef struct {
+    float lambda[6];  /* weights of l1, ssim, normal, depth, seg, K (1, 0.1 x 5) */
+    int balance;      /* 1: scale terms by |L_l1| / |L_x| */
+} ugs_loss_options;
+
+/* Fills the defaults listed above. */
+void ugs_default_loss_options(ugs_loss_options *opt);
+
+/* Scratch bytes (device) ugs_loss needs for these views. */
+int ugs_loss_scratch_size(const ugs_camera *cams, int V, size_t *bytes);
+
+/* Evaluates the loss of `out` against `gt` and writes dL_all/d(map) into the
+ * caller-owned device maps of `grad` (same layouts as ugs_outputs; rgb, kmap
+ * always written, depth/normal/sem written as zero when their term is absent;
+ * the pointers are written through despite the const of ugs_upstream).
+ * `losses` is device memory for 8 floats: L_l1, L_ssim, L_normal, L_depth,
+ * L_seg, L_K, L_all and the SSIM mean.  `scratch` (256-byte aligned,
+ * ugs_loss_scratch_size bytes) is overwritten.  Asynchronous on `stream`.
+ * Errors: UGS_ERR_INVALID_ARG (NULL rgb maps, NULL or misaligned buffers,
+ * C_o out of range, labels without C_o). */
+int ugs_loss(const ugs_camera *cams, int V, int C_o, const ugs_outputs *out, const ugs_targets *gt,
+             const ugs_loss_options *opt, const ugs_upstream *grad, float *losses, void *scratch,
+             size_t scratch_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -33,7 +33,8 @@ EXPORTS = ["ugs_default_options", "ugs_create", "ugs_destroy", "ugs_set_options"
            "ugs_project", "ugs_bin_sort", "ugs_check_overflow", "ugs_render_fwd", "ugs_render_bwd",
            "ugs_step_capture", "ugs_step_replay", "ugs_autotune", "ugs_pair_count", "ugs_status_string",
            "ugs_last_hip_error", "ugs_enable_counters", "ugs_read_counters", "ugs_debug_buffer", "ugs_time_stage",
-           "ugs_prune_scratch_size", "ugs_prune"]
+           "ugs_prune_scratch_size", "ugs_prune", "ugs_default_loss_options", "ugs_loss_scratch_size",
+           "ugs_loss"]
 
 
 class UgsError(RuntimeError):
@@ -69,6 +70,16 @@ class ugs_options(C.Structure):
                 ("step2", C.c_int), ("lambda_", C.c_float), ("orient_sign", C.c_int), ("prune_Tk", C.c_float),
                 ("depth_mode", C.c_int)]
 
+
+class ugs_targets(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("rgb", "depth", "normal", "label")]
+
+
+class ugs_loss_options(C.Structure):
+    _fields_ = [("lambda_", C.c_float * 6), ("balance", C.c_int)]
+
+
+LOSS_NAMES = ("l1", "ssim", "normal", "depth", "seg", "K", "all", "ssim_mean")
 
 _lib = None
 
@@ -116,6 +127,12 @@ def lib():
         L.ugs_prune.argtypes = [C.POINTER(ugs_gaussians), C.POINTER(ugs_gaussian_grads), C.c_int,
                                 C.POINTER(ugs_gaussians), C.POINTER(ugs_gaussian_grads), C.c_float, C.c_int, P,
                                 C.c_size_t, C.POINTER(C.c_int64), P]
+        L.ugs_default_loss_options.argtypes = [C.POINTER(ugs_loss_options)]
+        L.ugs_default_loss_options.restype = None
+        L.ugs_loss_scratch_size.argtypes = [C.POINTER(ugs_camera), C.c_int, C.POINTER(C.c_size_t)]
+        L.ugs_loss.argtypes = [C.POINTER(ugs_camera), C.c_int, C.c_int, C.POINTER(ugs_outputs),
+                               C.POINTER(ugs_targets), C.POINTER(ugs_loss_options), C.POINTER(ugs_upstream), P, P,
+                               C.c_size_t, P]
         _lib = L
     return _lib
 
@@ -271,6 +288,48 @@ def prune(g, T_k, reset_k=True, states=()):
         res[key] = view(key, out[key])
     res_states = [{key: view(key, so[key]) for key in PARAM_KEYS} for so in outs_state]
     return res, res_states, n
+
+
+def loss_options(lambdas=None, balance=True):
+    o = ugs_loss_options()
+    lib().ugs_default_loss_options(C.byref(o))
+    if lambdas is not None:
+        for k in range(6):
+            o.lambda_[k] = float(lambdas[k])
+    o.balance = int(bool(balance))
+    return o
+
+
+class Loss:
+    """The section-3.4 loss (ugs_loss) for a fixed set of views: owns the
+    scratch buffer, the 8-float loss vector and the gradient maps, which are
+    the upstream of Rasterizer.backward."""
+
+    def __init__(self, cams, C_o, lambdas=None, balance=True, device="cuda"):
+        import torch
+        self.cams_c = make_cameras(cams)
+        self.V, self.C_o = len(cams), int(C_o)
+        nb = C.c_size_t()
+        _chk(lib().ugs_loss_scratch_size(self.cams_c, self.V, C.byref(nb)), "ugs_loss_scratch_size")
+        self.scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        self.nb = int(nb.value)
+        self.losses = torch.zeros(8, dtype=torch.float32, device=device)
+        P = pixel_offsets(cams)[-1]
+        f = lambda n: torch.empty(n, dtype=torch.float32, device=device)
+        self.grad = dict(rgb=f(3 * P), depth=f(P), kmap=f(P), normal=f(3 * P), sem=f(max(self.C_o, 0) * P))
+        self.opts = loss_options(lambdas, balance)
+
+    def __call__(self, out, gt):
+        """out: rasterizer outputs; gt: dict with rgb and optional depth,
+        normal, label (int32).  Returns (losses tensor[8], gradient dict)."""
+        t = ugs_targets()
+        for k in ("rgb", "depth", "normal", "label"):
+            v = gt.get(k)
+            setattr(t, k, v.data_ptr() if v is not None else None)
+        o, u = make_outputs(out), make_upstream(self.grad)
+        _chk(lib().ugs_loss(self.cams_c, self.V, self.C_o, C.byref(o), C.byref(t), C.byref(self.opts), C.byref(u),
+                            _ptr(self.losses), _ptr(self.scratch), self.nb, _stream()), "ugs_loss")
+        return self.losses, self.grad
 
 
 def pixel_offsets(cams):

@@ -144,3 +144,30 @@ def test_prune_rejections(U):
         == U.UGS_ERR_INVALID_ARG
     assert L.ugs_prune(C.byref(g), C.byref(out), 2, None, None, 0.2, 1, C.c_void_p(256), 4096, C.byref(n), None) \
         == U.UGS_ERR_INVALID_ARG
+
+
+def test_loss_rejections(U):
+    """ugs_loss validates before touching the device."""
+    L = U.lib()
+    nb = C.c_size_t()
+    cams = U.make_cameras([dict(W=64, H=48, fx=50, fy=50, cx=32, cy=24, R=np.eye(3), t=np.zeros(3))])
+    assert L.ugs_loss_scratch_size(cams, 1, C.byref(nb)) == U.UGS_OK and nb.value >= 36 * 64 * 48
+    assert L.ugs_loss_scratch_size(cams, 0, C.byref(nb)) == U.UGS_ERR_INVALID_ARG
+    o = U.loss_options()
+    assert abs(o.lambda_[0] - 1.0) < 1e-7 and abs(o.lambda_[5] - 0.1) < 1e-7 and o.balance == 1
+    out, gt, up = U.ugs_outputs(), U.ugs_targets(), U.ugs_upstream()
+    for s in (out, gt, up):
+        for f, _ in s._fields_:
+            setattr(s, f, 256)
+    sc = C.c_void_p(256)
+    ok = lambda **kw: L.ugs_loss(cams, 1, kw.get("C_o", 4), C.byref(out), C.byref(gt), C.byref(o), C.byref(up),
+                                 C.c_void_p(256), kw.get("sc", sc), kw.get("nb", nb.value), None)
+    assert ok(nb=8) == U.UGS_ERR_INVALID_ARG             # scratch too small
+    assert ok(sc=C.c_void_p(260)) == U.UGS_ERR_INVALID_ARG  # misaligned scratch
+    assert ok(C_o=0) == U.UGS_ERR_INVALID_ARG             # labels without channels
+    assert ok(C_o=U.UGS_MAX_CHANNELS + 1) == U.UGS_ERR_INVALID_ARG
+    gt.rgb = None
+    assert ok() == U.UGS_ERR_INVALID_ARG
+    gt.rgb = 256
+    out.kmap = 258
+    assert ok() == U.UGS_ERR_INVALID_ARG                  # misaligned map
