@@ -84,7 +84,10 @@ typedef struct {
     double eps_n;
     int depth_mode;  /* 0: ray-ellipsoid midpoint depth (section 3.2); 1: the
                         Gaussian centre's camera depth (the "Center Point" row of
-                        the supplementary's module ablation table) */
+                        the supplementary's module ablation table); 2: the
+                        midpoint where the ray meets the ellipsoid (two real
+                        roots or one, discriminant >= 0) and the centre depth
+                        where it has no valid solution */
 } orc_opt;
 
 /* Per-Gaussian projected state for one view. */
@@ -354,7 +357,7 @@ static void ctx_free(ctx_t *c)
  * the local scaled frame of section 3.2, a = ds.ds, b = 2 vs.ds,
  * t_mid = -b/(2a), d = z-component in the camera frame of C + t_mid dray. */
 typedef struct {
-    double dr[3], v[3], vl[3], dl[3], vs[3], ds[3], a, b, tm, d, dd_dt;
+    double dr[3], v[3], vl[3], dl[3], vs[3], ds[3], a, b, c, disc, hmargin, tm, d, dd_dt;
 } depth_t;
 
 static void depth_literal(const ctx_t *c, const proj_t *P, const double *mu, double u, double v, depth_t *D)
@@ -378,6 +381,13 @@ static void depth_literal(const ctx_t *c, const proj_t *P, const double *mu, dou
     }
     D->a = D->ds[0] * D->ds[0] + D->ds[1] * D->ds[1] + D->ds[2] * D->ds[2];
     D->b = 2.0 * (D->vs[0] * D->ds[0] + D->vs[1] * D->ds[1] + D->vs[2] * D->ds[2]);
+    double vv = D->vs[0] * D->vs[0] + D->vs[1] * D->vs[1] + D->vs[2] * D->vs[2];
+    D->c = vv - 1.0;
+    /* discriminant of a t^2 + b t + c = 0 and its distance from 0 relative to
+     * the size of the terms it is formed from (the rounding scale of an FP32
+     * evaluation) */
+    D->disc = D->b * D->b - 4.0 * D->a * D->c;
+    D->hmargin = fabs(D->disc) / (D->b * D->b + 4.0 * D->a * (vv + 1.0));
     D->tm = -D->b / (2.0 * D->a);
     double X[3];
     for (int k = 0; k < 3; ++k) X[k] = c->C[k] + D->tm * D->dr[k];
@@ -464,6 +474,10 @@ static int pixel_frags(const ctx_t *c, int u, int v, frag_t *F, pixinfo_t *info)
             depth_t D;
             depth_literal(c, P, mu, u, v, &D);
             F[n].d = D.d;
+            if (c->opt->depth_mode == 2) {
+                if (D.hmargin < margin) margin = D.hmargin;
+                if (D.disc < 0.0) F[n].d = P->z; /* no valid solution: centre depth */
+            }
         }
         T = tT;
         ++n;
@@ -755,14 +769,18 @@ static void pixel_backward(const ctx_t *c, int u, int v, const frag_t *F, int n,
         for (int ch = 0; ch < Co; ++ch) atomic_add(&dsem[id * Co + ch], w * gO[ch]);
         /* depth: supplementary S1.2 chain */
         double dd = w * gD;
-        if (dd != 0.0 && c->opt->depth_mode == 1) {
+        depth_t D;
+        int centre = c->opt->depth_mode == 1;
+        if (dd != 0.0 && !centre) {
+            double mu[3];
+            gauss_mean(g, id, mu);
+            depth_literal(c, P, mu, u, v, &D);
+            centre = c->opt->depth_mode == 2 && D.disc < 0.0;
+        }
+        if (dd != 0.0 && centre) {
             /* d = mu_c.z = R[2,:] mu + t_z */
             for (int r = 0; r < 3; ++r) atomic_add(&a[A_DMU + r], dd * c->cam->R[6 + r]);
         } else if (dd != 0.0) {
-            double mu[3];
-            gauss_mean(g, id, mu);
-            depth_t D;
-            depth_literal(c, P, mu, u, v, &D);
             double dtm = dd * D.dd_dt;                 /* Eq. (d->tmid) */
             double gvs[3], gds[3], gvl[3], gdl[3];
             for (int k = 0; k < 3; ++k) {              /* Eq. (tmid->vs) */

@@ -369,6 +369,48 @@ def test_centre_depth_mode_gradients_match_fd(oracle_mod, seed):
     assert ok > 0.8 * len(picks)
 
 
+def test_hit_fallback_mode_closed_form(oracle_mod):
+    """depth_mode 2 (midpoint where the quadratic has real roots, centre depth
+    where it has none): for one on-axis Gaussian the ray through normalised
+    image point (x, y) reaches Mahalanobis distance z^2 K / (1 + K s_z^2) at its
+    closest point, K = x^2/s_x^2 + y^2/s_y^2, so it hits the ellipsoid exactly
+    where that is <= 1; the depth is z / (1 + s_z^2 K) there and z elsewhere."""
+    O = oracle_mod
+    cases = json.load(open(os.path.join(GOLDEN, "single_gaussian.json")))["cases"]
+    n_hit = n_miss = 0
+    for case in cases:
+        g, cam = _single(case)
+        out = O.render(g, cam, dict(O.OPTS_DEFAULT, depth_mode=2), path=0)
+        s = np.exp(g["log_scale"].astype(np.float64)[:, 0])
+        z = float(g["mean"][2, 0])
+        f, W, H = case["f"], case["W"], case["H"]
+        u, v = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
+        xh, yh = (u - W / 2) / f, (v - H / 2) / f
+        K = xh ** 2 / s[0] ** 2 + yh ** 2 / s[1] ** 2
+        m = z * z * K / (1 + K * s[2] ** 2)
+        d = np.where(m <= 1, z / (1.0 + s[2] ** 2 * K), z)
+        alpha = 1 - out["T_final"]
+        ok = np.abs(m - 1) > 1e-9
+        assert np.abs(out["depth"] - alpha * d)[ok].max() < 1e-12
+        n_hit += int(((m < 1) & (alpha > 0)).sum())
+        n_miss += int(((m > 1) & (alpha > 0)).sum())
+    assert n_hit > 20 and n_miss > 20
+
+
+@pytest.mark.parametrize("seed", [5, 8])
+def test_hit_fallback_mode_gradients_match_fd(oracle_mod, seed):
+    """Adjoint of depth_mode 2 (midpoint chain on hits, centre chain on misses)
+    against central differences of every parameter of a tiny scene."""
+    O = oracle_mod
+    g, cams, opts = scenes.tiny_scene(n=5, seed=seed, sh_deg=1, C_o=3)
+    opts = dict(opts, depth_mode=2)
+    ups = scenes.upstream(cams, g["C_o"], seed=seed)
+    picks = [(k, j) for k in ("mean", "quat", "log_scale", "opacity_logit", "mask_logit", "sh", "sem")
+             for j in range(np.asarray(g[k]).size)]
+    ok = _fd_check(O, g, cams, opts, ups, picks)
+    assert ok > 0.8 * len(picks)
+
+
 def test_gradients_match_fd_workload1(oracle_mod):
     """Same check on the 2,000-Gaussian 128x128 workload, 70 sampled parameters
     stratified over every parameter kind."""
