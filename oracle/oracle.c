@@ -383,16 +383,29 @@ static void depth_literal(const ctx_t *c, const proj_t *P, const double *mu, dou
     D->b = 2.0 * (D->vs[0] * D->ds[0] + D->vs[1] * D->ds[1] + D->vs[2] * D->ds[2]);
     double vv = D->vs[0] * D->vs[0] + D->vs[1] * D->vs[1] + D->vs[2] * D->vs[2];
     D->c = vv - 1.0;
-    /* discriminant of a t^2 + b t + c = 0 and its distance from 0 relative to
-     * the size of the terms it is formed from (the rounding scale of an FP32
-     * evaluation) */
-    D->disc = D->b * D->b - 4.0 * D->a * D->c;
-    D->hmargin = fabs(D->disc) / (D->b * D->b + 4.0 * D->a * (vv + 1.0));
+    D->disc = D->b * D->b - 4.0 * D->a * D->c; /* >= 0: the ray meets the ellipsoid */
     D->tm = -D->b / (2.0 * D->a);
     double X[3];
     for (int k = 0; k < 3; ++k) X[k] = c->C[k] + D->tm * D->dr[k];
     D->d = R[6] * X[0] + R[7] * X[1] + R[8] * X[2] + cam->t[2];
     D->dd_dt = R[6] * D->dr[0] + R[7] * D->dr[1] + R[8] * D->dr[2];
+    /* Decision margin of the hit test.  disc >= 0 exactly when the smallest
+     * squared Mahalanobis distance along the ray, m = |vs|^2 - (vs.ds)^2 / a, is
+     * at most 1; the margin is m's relative distance from 1, divided by the
+     * cancellation factor of m when it is formed from the pixel's offset delta
+     * from the centre's ray p0 (m is proportional to |p0|^2 |delta|^2 -
+     * (p0.delta)^2 in the scaled frame). */
+    double m = vv - (D->b * D->b) / (4.0 * D->a);
+    double p0s[3], dls[3], pp = 0, dd2 = 0, pd = 0;
+    for (int k = 0; k < 3; ++k) {
+        p0s[k] = -D->vs[k] / P->z;              /* mu_c / z0 in the scaled frame */
+        dls[k] = D->ds[k] / D->dd_dt - p0s[k];  /* ray point at camera depth 1, minus p0 */
+        pp += p0s[k] * p0s[k];
+        dd2 += dls[k] * dls[k];
+        pd += p0s[k] * dls[k];
+    }
+    double lag = pp * dd2 - pd * pd, kappa = lag > 0 ? (pp * dd2 + pd * pd) / lag : 1.0;
+    D->hmargin = fabs(m - 1.0) / ((1.0 + m) * kappa);
 }
 
 static void gauss_mean(const orc_gs *g, int64_t i, double *mu)
