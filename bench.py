@@ -145,6 +145,7 @@ def main():
     ap.add_argument("--no-forward-only", action="store_true")
     ap.add_argument("--no-prune", action="store_true")
     ap.add_argument("--no-loss", action="store_true")
+    ap.add_argument("--no-depth-modes", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", default=None, help="force a tile shape, e.g. 16x16")
     ap.add_argument("--batch", type=int, default=0, help="force the LDS batch (with --tile)")
@@ -289,6 +290,28 @@ def main():
         log(f"[bench] forward-only {t_fo * 1e3:.3f} ms per {len(cams)} views ({fwd_only['value']} MP/s)")
         del fo, out_fo
 
+    # depth variants (the module ablation's ray-casting vs centre-point depth):
+    # the same batched step with depth_mode 1 (centre) and 2 (midpoint where the
+    # ray meets the ellipsoid, centre elsewhere)
+    depth_modes = None
+    if not args.no_depth_modes:
+        depth_modes = {"midpoint": round(t_batched * 1e3, 3)}
+        for name, mode in (("centre", 1), ("hit_else_centre", 2)):
+            dm = U.Rasterizer(prune_Tk=float(opts["prune_Tk"]), tile_w=rast.opts.tile_w, tile_h=rast.opts.tile_h,
+                              batch=rast.opts.batch, depth_mode=mode)
+            dm.capture_step(g, cams, out, up, grads)
+            for _ in range(args.warmup):
+                dm.replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                dm.replay()
+            torch.cuda.synchronize()
+            depth_modes[name] = round((time.perf_counter() - t0) / args.steps * 1e3, 3)
+            del dm
+        depth_modes["unit"] = "ms per batched step"
+        log(f"[bench] depth modes {depth_modes}")
+
     # differentiable pruning (section 3.3): compaction of the parameters and two
     # optimiser-moment sets at T_k = 0.2; HBM-bound (every array read once, the
     # kept part written once)
@@ -391,7 +414,7 @@ def main():
                            autotuned=tuned is not None),
                per_view=None if t_pv is None else dict(value=round(Px / t_pv / 1e6, 2), unit="MP/s",
                                                         ms_per_step=round(t_pv * 1e3, 3)),
-               forward_only=fwd_only, prune=prune_res, loss=loss_res,
+               forward_only=fwd_only, prune=prune_res, loss=loss_res, depth_modes=depth_modes,
                step_hbm=dict(alg_bytes=int(b_alg), frac=round(b_alg / t_batched / PEAK_HBM, 4)),
                counts=dict(pairs=P, records=V_rec, evaluated=F_eval, contributing=F_contrib),
                stage_ms={k: round(v, 4) for k, v in stage_ms.items()},

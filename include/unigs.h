@@ -112,7 +112,11 @@ typedef struct {
                               ray-ellipsoid intersections (section 3.2, Eq. midpoint);
                             1: the camera depth of the Gaussian's centre, the
                               "Center Point" row of the supplementary's module
-                              ablation table.  Gradients follow the chosen form. */
+                              ablation table;
+                            2: the midpoint where the pixel ray meets the
+                              ellipsoid (the quadratic of section 3.2 has a real
+                              root) and the centre depth where it has no valid
+                              solution.  Gradients follow the chosen form. */
 } ugs_options;
 
 typedef struct ugs_ctx ugs_ctx;

@@ -86,7 +86,7 @@ int check_options(const ugs_options *o)
     if (!(o->lambda >= 0.f && o->lambda <= 1.f)) return UGS_ERR_INVALID_ARG;
     if (o->orient_sign != 1 && o->orient_sign != -1) return UGS_ERR_INVALID_ARG;
     if (!(o->prune_Tk >= 0.f)) return UGS_ERR_INVALID_ARG;
-    if (o->depth_mode != 0 && o->depth_mode != 1) return UGS_ERR_INVALID_ARG;
+    if (o->depth_mode < 0 || o->depth_mode > 2) return UGS_ERR_INVALID_ARG;
     return UGS_OK;
 }
 
@@ -221,6 +221,7 @@ WsLayout make_layout(const Problem &pb, int64_t pair_cap)
     L.counters = take(sizeof(DevCounters) + 64);
     L.cams = take(sizeof(DevCam) * pb.V);
     L.rec = take(VN * 64);
+    L.hrec = take(VN * 4);
     L.grec = take(VN * 64);
     L.rect = take(VN * 8);
     L.touched = take(VN * 4);
@@ -251,10 +252,10 @@ int auto_batch(const ugs_options &o, int C_o)
     if (o.batch > 0) return o.batch;
     // largest power of two up to the tile's pixel count whose LDS staging fits
     // 32 KB per workgroup; the matrix-core kernels (16 or 32 padded channels)
-    // also hold a 16 x 68 FP32 buffer per wavefront and 212 B per entry
+    // also hold a 16 x 68 FP32 buffer per wavefront and 216 B per entry
     const int nt = o.tile_w * o.tile_h, cp = channel_pad(C_o);
     const bool mfma = cp == 16 || cp == 32;
-    const size_t per = mfma ? 212 : (size_t)(64 + 4 * cp);
+    const size_t per = mfma ? 216 : (size_t)(68 + 4 * cp);
     const size_t fixed = mfma ? (size_t)(nt / 64) * 16 * 68 * 4 : 0;
     int b = nt;
     while (b > 16 && fixed + (size_t)b * per > 32 * 1024) b /= 2;

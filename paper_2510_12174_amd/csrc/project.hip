@@ -238,7 +238,8 @@ __global__ void __launch_bounds__(kProjThreads) project_fwd_kernel(ugs_gaussians
                                                                    int V, int tile_w, int tile_h, float prune_Tk,
                                                                    float4 *__restrict__ rec, uint2 *__restrict__ rect,
                                                                    uint32_t *__restrict__ touched,
-                                                                   float4 *__restrict__ grec, int zero_grad)
+                                                                   float4 *__restrict__ grec, int zero_grad,
+                                                                   float *__restrict__ hrec)
 {
     const int64_t N = g.N;
     const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
@@ -295,6 +296,9 @@ __global__ void __launch_bounds__(kProjThreads) project_fwd_kernel(ugs_gaussians
                 r[2] = make_float4((float)(S.Qp0x * iA / fx), (float)(S.Qp0y * iA / fy), (float)(S.Q00 * iA / (fx * fx)),
                                    (float)(S.Q01 * iA / (fx * fy)));
                 r[3] = make_float4((float)(S.Q11 * iA / (fy * fy)), col[0], col[1], col[2]);
+                // hit constant of depth_mode 2: the Mahalanobis distance of the
+                // camera centre, z0^2 p0^T Q p0
+                if (hrec) hrec[idx] = (float)(S.z * S.z * S.A);
                 // every tile of the rectangle, for now: the binning pass culls
                 // the tiles that the alpha ellipse misses
                 nt = (uint32_t)area;
@@ -585,11 +589,12 @@ hipError_t launch_project_fwd(const ugs_gaussians &g, const Problem &pb, const W
     auto rect = (uint2 *)(ws + L.rect);
     auto touched = (uint32_t *)(ws + L.touched);
     auto grec = (float4 *)(ws + L.grec);
+    auto hrec = pb.depth_mode == 2 ? (float *)(ws + L.hrec) : nullptr;
     switch (g.sh_deg) {
-    case 0: hipLaunchKernelGGL(project_fwd_kernel<0>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad); break;
-    case 1: hipLaunchKernelGGL(project_fwd_kernel<1>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad); break;
-    case 2: hipLaunchKernelGGL(project_fwd_kernel<2>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad); break;
-    default: hipLaunchKernelGGL(project_fwd_kernel<3>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad); break;
+    case 0: hipLaunchKernelGGL(project_fwd_kernel<0>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad, hrec); break;
+    case 1: hipLaunchKernelGGL(project_fwd_kernel<1>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad, hrec); break;
+    case 2: hipLaunchKernelGGL(project_fwd_kernel<2>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad, hrec); break;
+    default: hipLaunchKernelGGL(project_fwd_kernel<3>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad, hrec); break;
     }
     return hipGetLastError();
 }

@@ -188,6 +188,40 @@ __device__ __forceinline__ TileInfo tile_info(const DevCam *cams, int V, uint32_
     return ti;
 }
 
+// Whether the pixel ray meets the Gaussian's ellipsoid, i.e. the quadratic of
+// section 3.2 has a real root (depth_mode 2).  In the per-record quadric form
+// the smallest Mahalanobis distance along the ray is h (Cq - B^2) / (1 + 2B + Cq)
+// with h = z0^2 p0^T Q p0, so the ray hits where h (Cq - B^2) <= 1 + 2B + Cq.
+// Non-contracting operations: the forward and backward kernels take the same
+// decision bit for bit.
+__device__ __forceinline__ bool ray_hits(float h, float4 r2, float4 r3, float dx, float dy)
+{
+    const float B = __fadd_rn(__fmul_rn(r2.x, dx), __fmul_rn(r2.y, dy));
+    const float Cq = __fadd_rn(__fadd_rn(__fmul_rn(__fmul_rn(r2.z, dx), dx), __fmul_rn(__fmul_rn(__fmul_rn(2.f, r2.w), dx), dy)),
+                               __fmul_rn(__fmul_rn(r3.x, dy), dy));
+    return __fmul_rn(h, __fsub_rn(Cq, __fmul_rn(B, B))) <= __fadd_rn(__fadd_rn(1.f, __fmul_rn(2.f, B)), Cq);
+}
+
+// Depth-form factor of one fragment: kd (1 midpoint, 0 centre), or, with the
+// staged hit constants of depth_mode 2, 1 where the ray hits and 0 where not.
+template <bool HIT>
+__device__ __forceinline__ float frag_kd(float kd, const float *shh, int j, float4 r2, float4 r3, float dx, float dy)
+{
+    if constexpr (HIT)
+        return ray_hits(shh[j], r2, r3, dx, dy) ? 1.f : 0.f;
+    else
+        return kd;
+}
+
+// Stages the hit constants of `n` list entries (depth_mode 2 only).
+template <int NT, bool HIT>
+__device__ __forceinline__ void stage_hits(float *shh, const uint32_t *vals, uint32_t start, int n,
+                                           const float *hrec, int64_t recbase)
+{
+    if constexpr (HIT)
+        for (int q = threadIdx.x; q < n; q += NT) shh[q] = hrec[recbase + vals[start + q]];
+}
+
 // Stage `n` list entries [start, start+n) into LDS: 4 float4 of record and CO
 // semantic floats (zero beyond C_o) each.
 template <int NT, int CO>
@@ -207,16 +241,17 @@ __device__ __forceinline__ void stage_batch(float4 *srec, float *ssem, const uin
     }
 }
 
-template <int TW, int TH, int CO>
+template <int TW, int TH, int CO, bool HIT>
 __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
-    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles, int centre_depth)
+    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles, int depth_mode, const float *__restrict__ hrec)
 {
     constexpr int NT = TW * TH;
     extern __shared__ float4 smem[];
     float4 *srec = smem;
     float *ssem = (float *)(smem + 4 * batch);
+    float *shh = HIT ? ssem + (size_t)batch * CO : nullptr;
     const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
@@ -231,12 +266,13 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
     for (int c = 0; c < (CO > 0 ? CO : 1); ++c) acc[c] = 0.f;
     uint32_t last = 0, n_eval = 0, n_con = 0;
     bool done = !ti.inside;
-    const float kd = centre_depth ? 0.f : 1.f;
+    const float kd = depth_mode == 1 ? 0.f : 1.f;
 
     for (uint32_t start = range.x; start < range.y; start += (uint32_t)batch) {
         if (__syncthreads_count(done) == NT) break;
         const int n = (int)min((uint32_t)batch, range.y - start);
         stage_batch<NT, CO>(srec, ssem, vals, start, n, rec, recbase, sem, C_o);
+        stage_hits<NT, HIT>(shh, vals, start, n, hrec, recbase);
         __syncthreads();
         if (!done) {
             for (int j = 0; j < n; ++j) {
@@ -253,8 +289,9 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
                     break;
                 }
                 const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
-                const float B = kd * (r2.x * dx + r2.y * dy);
-                const float Cq = kd * (r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy);
+                const float kdj = frag_kd<HIT>(kd, shh, j, r2, r3, dx, dy);
+                const float B = kdj * (r2.x * dx + r2.y * dy);
+                const float Cq = kdj * (r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy);
                 const float d = r1.w * (1.f + B) * rcp_nr(1.f + 2.f * B + Cq);
                 const double w = (double)alpha * T;
                 const float wf = (float)w;
@@ -335,13 +372,13 @@ __device__ __forceinline__ void emit_groups(const float (&v)[16], float w, const
     if constexpr (REM > G) emit_groups<OFF + G, REM - G, CO, CA>(v, w, gO, lane, grec_i, dsem_i, C_o);
 }
 
-template <int TW, int TH, int CO>
+template <int TW, int TH, int CO, bool HIT>
 __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
     const float *__restrict__ T_final, const uint32_t *__restrict__ n_contrib, const float *__restrict__ up_rgb,
     const float *__restrict__ gD_img, const float *__restrict__ up_kmap, const float *__restrict__ up_sem,
-    float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, int centre_depth)
+    float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, int depth_mode, const float *__restrict__ hrec)
 {
     constexpr int NT = TW * TH;
     constexpr int CA = CO > 0 ? CO : 1;
@@ -349,6 +386,7 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     __shared__ uint32_t s_max;
     float4 *srec = smem;
     float *ssem = (float *)(smem + 4 * batch);
+    float *shh = HIT ? ssem + (size_t)batch * CO : nullptr;
     const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
@@ -391,13 +429,14 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, o, 64));
     wave_last = __builtin_amdgcn_readfirstlane(wave_last);
     float A = 0.f;
-    const float kd = centre_depth ? 0.f : 1.f;
+    const float kd = depth_mode == 1 ? 0.f : 1.f;
 
     for (uint32_t end = end_all; end > range.x;) {
         const uint32_t start = end - range.x > (uint32_t)batch ? end - (uint32_t)batch : range.x;
         const int n = (int)(end - start);
         __syncthreads();
         stage_batch<NT, CO>(srec, ssem, vals, start, n, rec, recbase, sem, C_o);
+        stage_hits<NT, HIT>(shh, vals, start, n, hrec, recbase);
         __syncthreads();
         for (int j = n - 1; j >= 0; --j) {
             const uint32_t entry = start + (uint32_t)j;
@@ -421,8 +460,9 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
                 }
             }
             float v[16];
-            const float w = frag_adjoint(contrib, r0, r1, srec[4 * j + 2], srec[4 * j + 3], dx, dy, t1, t2, G, oG,
-                                         alpha, s_sem, gR, gG, gB, gDp, gK, kd, T, A, v);
+            const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
+            const float w = frag_adjoint(contrib, r0, r1, r2, r3, dx, dy, t1, t2, G, oG, alpha, s_sem, gR, gG, gB,
+                                         gDp, gK, frag_kd<HIT>(kd, shh, j, r2, r3, dx, dy), T, A, v);
             // per-fragment values: slots 0..15 are the gradient record (slot 6 the
             // gradient factor), slots 16..16+C_o the semantic logits
             const uint32_t id = vals[entry];
@@ -460,7 +500,7 @@ constexpr int kSemRow = 72;    // bf16 per staged feature row: 32 hi, 32 lo, 8 p
 
 __host__ __device__ constexpr size_t bwd_mfma_lds(int batch, int NW)
 {
-    return (size_t)batch * (64 + 2 * kSemRow + 4) + (size_t)NW * kGrp * kWbStride * 4;
+    return (size_t)batch * (64 + 2 * kSemRow + 4 + 4) + (size_t)NW * kGrp * kWbStride * 4;
 }
 
 __device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo)
@@ -477,7 +517,7 @@ __device__ __forceinline__ mf4 mfma3(const bf8 &ah, const bf8 &al, const bf8 &bh
     return c;
 }
 
-template <int TW, int TH, int CO>
+template <int TW, int TH, int CO, bool HIT>
 // Four wavefronts per SIMD (at most 128 registers per lane): the kernel is bound
 // by VALU issue and dependency latency, and a fourth wavefront hides enough of
 // the latter to pay for the tighter register budget (no spills).
@@ -486,7 +526,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
     const float *__restrict__ T_final, const uint32_t *__restrict__ n_contrib, const float *__restrict__ up_rgb,
     const float *__restrict__ gD_img, const float *__restrict__ up_kmap, const float *__restrict__ up_sem,
-    float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, int centre_depth)
+    float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, int depth_mode, const float *__restrict__ hrec)
 {
     static_assert(CO == 16 || CO == 32, "MFMA backward: C_o padded to 16 or 32");
     constexpr int NT = TW * TH;
@@ -498,6 +538,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
     uint32_t *sid = (uint32_t *)(ssem + (size_t)batch * kSemRow);
     const int wave = (int)(threadIdx.x >> 6);
     float *wb = (float *)(sid + batch) + wave * (kGrp * kWbStride);
+    float *shh = HIT ? (float *)(sid + batch) + (TW * TH / 64) * (kGrp * kWbStride) : nullptr;
     const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
@@ -564,7 +605,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
     for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, o, 64));
     wave_last = __builtin_amdgcn_readfirstlane(wave_last);
     float A = 0.f;
-    const float kd = centre_depth ? 0.f : 1.f;
+    const float kd = depth_mode == 1 ? 0.f : 1.f;
 
     for (uint32_t end = end_all; end > range.x;) {
         const uint32_t start = end - range.x > (uint32_t)batch ? end - (uint32_t)batch : range.x;
@@ -584,6 +625,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
             ssem[e * kSemRow + 32 + c] = l;
         }
         for (int q = threadIdx.x; q < n; q += NT) sid[q] = vals[start + q];
+        stage_hits<NT, HIT>(shh, vals, start, n, hrec, recbase);
         __syncthreads();
         const int ngrp = (n + kGrp - 1) / kGrp;
         for (int grp = ngrp - 1; grp >= 0; --grp) {
@@ -618,8 +660,9 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
                     const bool contrib = entry < last && alpha >= kAlphaMin;
                     if (__any(contrib)) {
                         float v[16];
-                        w = frag_adjoint(contrib, r0, r1, srec[4 * j + 2], srec[4 * j + 3], dx, dy, t1, t2, G, oG,
-                                         alpha, s_sem, gR, gG, gB, gDp, gK, kd, T, A, v);
+                        const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
+                        w = frag_adjoint(contrib, r0, r1, r2, r3, dx, dy, t1, t2, G, oG, alpha, s_sem, gR, gG, gB,
+                                         gDp, gK, frag_kd<HIT>(kd, shh, j, r2, r3, dx, dy), T, A, v);
                         const float tot = reduce_scatter<16>(v);
                         if ((lane & 3) == 0)
                             unsafeAtomicAdd(&grec[(recbase + sid[j]) * kRecFloats + (lane >> 2)], tot);
@@ -700,14 +743,14 @@ __host__ __device__ constexpr int fwd_semT_stride(int batch) { return batch + 4;
 
 __host__ __device__ constexpr size_t fwd_mfma_lds(int batch, int CO, int NW)
 {
-    return (size_t)batch * 64 + (size_t)2 * CO * fwd_semT_stride(batch) * 2 + (size_t)NW * kGrp * kWbStride * 4;
+    return (size_t)batch * (64 + 4) + (size_t)2 * CO * fwd_semT_stride(batch) * 2 + (size_t)NW * kGrp * kWbStride * 4;
 }
 
-template <int TW, int TH, int CO>
+template <int TW, int TH, int CO, bool HIT>
 __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
-    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles, int centre_depth)
+    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles, int depth_mode, const float *__restrict__ hrec)
 {
     static_assert(CO == 16 || CO == 32, "MFMA forward: C_o padded to 16 or 32");
     constexpr int NT = TW * TH;
@@ -719,6 +762,7 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
     short *seml = semh + CO * RS;
     const int wave = (int)(threadIdx.x >> 6);
     float *wb = (float *)(seml + CO * RS) + wave * (kGrp * kWbStride);
+    float *shh = HIT ? (float *)(seml + CO * RS) + (NT / 64) * (kGrp * kWbStride) : nullptr;
     const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
@@ -737,7 +781,7 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
         for (int q = 0; q < NCB; ++q) acc[pb][q] = mf4{0.f, 0.f, 0.f, 0.f};
     uint32_t last = 0, n_eval = 0, n_con = 0;
     bool done = !ti.inside;
-    const float kd = centre_depth ? 0.f : 1.f;
+    const float kd = depth_mode == 1 ? 0.f : 1.f;
 
     for (uint32_t start = range.x; start < range.y; start += (uint32_t)batch) {
         if (__syncthreads_count(done) == NT) break;
@@ -757,6 +801,7 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
             semh[c * RS + e] = h;
             seml[c * RS + e] = l;
         }
+        stage_hits<NT, HIT>(shh, vals, start, n, hrec, recbase);
         __syncthreads();
         if (__all(done)) continue;  // the block may still walk this batch
         for (int j0 = 0; j0 < n; j0 += kGrp) {
@@ -776,8 +821,9 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
                             done = true;
                         } else {
                             const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
-                            const float B = kd * (r2.x * dx + r2.y * dy);
-                            const float Cq = kd * (r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy);
+                            const float kdj = frag_kd<HIT>(kd, shh, j, r2, r3, dx, dy);
+                            const float B = kdj * (r2.x * dx + r2.y * dy);
+                            const float Cq = kdj * (r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy);
                             const float d = r1.w * (1.f + B) * rcp_nr(1.f + 2.f * B + Cq);
                             const double w = (double)alpha * T;
                             wf = (float)w;
@@ -872,19 +918,22 @@ hipError_t fwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
     auto vals = (const uint32_t *)(ws + (final_buf ? L.vals1 : L.vals0));
     auto rec = (const float4 *)(ws + L.rec);
     auto cnt = (DevCounters *)(ws + L.counters);
+    auto hrec = (const float *)(ws + L.hrec);
     if constexpr (CO == 16 || CO == 32) {
         // whole MFMA groups per batch, at most 64 KB of LDS per workgroup
         constexpr int NW = TW * TH / 64;
         int b = (batch + kGrp - 1) / kGrp * kGrp;
         while (b > kGrp && fwd_mfma_lds(b, CO, NW) > 64 * 1024) b -= kGrp;
-        hipLaunchKernelGGL((render_fwd_mfma_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH),
-                           fwd_mfma_lds(b, CO, NW), s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out, b,
-                           cnt, (int)counters, (uint32_t)pb.total_tiles, pb.depth_mode);
+        auto k = pb.depth_mode == 2 ? render_fwd_mfma_kernel<TW, TH, CO, true> : render_fwd_mfma_kernel<TW, TH, CO, false>;
+        hipLaunchKernelGGL(k, dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), fwd_mfma_lds(b, CO, NW), s, cams, pb.V,
+                           pb.N, ranges, vals, rec, g.sem, pb.C_o, out, b, cnt, (int)counters,
+                           (uint32_t)pb.total_tiles, pb.depth_mode, hrec);
     } else {
-        size_t lds = (size_t)batch * (64 + 4 * CO);
-        hipLaunchKernelGGL((render_fwd_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s,
+        size_t lds = (size_t)batch * (64 + 4 * CO + 4);
+        auto k = pb.depth_mode == 2 ? render_fwd_kernel<TW, TH, CO, true> : render_fwd_kernel<TW, TH, CO, false>;
+        hipLaunchKernelGGL(k, dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s,
                            cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out, batch, cnt, (int)counters,
-                           (uint32_t)pb.total_tiles, pb.depth_mode);
+                           (uint32_t)pb.total_tiles, pb.depth_mode, hrec);
     }
     return hipGetLastError();
 }
@@ -900,20 +949,22 @@ hipError_t bwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
     auto rec = (const float4 *)(ws + L.rec);
     auto grec = (float *)(ws + L.grec);
     auto gd = (const float *)(ws + L.gd);
+    auto hrec = (const float *)(ws + L.hrec);
     if constexpr (CO == 16 || CO == 32) {
         // whole MFMA groups per batch, at most 64 KB of LDS per workgroup
         constexpr int NW = TW * TH / 64;
         int b = (batch + kGrp - 1) / kGrp * kGrp;
         while (b > kGrp && bwd_mfma_lds(b, NW) > 64 * 1024) b -= kGrp;
-        hipLaunchKernelGGL((render_bwd_mfma_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH),
-                           bwd_mfma_lds(b, NW), s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o,
+        auto k = pb.depth_mode == 2 ? render_bwd_mfma_kernel<TW, TH, CO, true> : render_bwd_mfma_kernel<TW, TH, CO, false>;
+        hipLaunchKernelGGL(k, dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), bwd_mfma_lds(b, NW), s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o,
                            out.T_final, out.n_contrib, up.rgb, gd, up.kmap, up.sem, grec, dg.sem, b,
-                           (uint32_t)pb.total_tiles, pb.depth_mode);
+                           (uint32_t)pb.total_tiles, pb.depth_mode, hrec);
     } else {
-        size_t lds = (size_t)batch * (64 + 4 * CO);
-        hipLaunchKernelGGL((render_bwd_kernel<TW, TH, CO>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s,
+        size_t lds = (size_t)batch * (64 + 4 * CO + 4);
+        auto k = pb.depth_mode == 2 ? render_bwd_kernel<TW, TH, CO, true> : render_bwd_kernel<TW, TH, CO, false>;
+        hipLaunchKernelGGL(k, dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s,
                            cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out.T_final, out.n_contrib, up.rgb, gd,
-                           up.kmap, up.sem, grec, dg.sem, batch, (uint32_t)pb.total_tiles, pb.depth_mode);
+                           up.kmap, up.sem, grec, dg.sem, batch, (uint32_t)pb.total_tiles, pb.depth_mode, hrec);
     }
     return hipGetLastError();
 }

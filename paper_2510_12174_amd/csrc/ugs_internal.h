@@ -57,8 +57,8 @@ struct DevCounters {
 };
 
 struct WsLayout {
-    size_t cams, rec, rect, touched, voff, poff, tsorted, dkey0, dkey1, didx0, didx1, vlist, scan_part, keys0, keys1, vals0,
-        vals1, hist, digit_tot, ranges, grec, gd, nadj, counters, total;
+    size_t cams, rec, hrec, rect, touched, voff, poff, tsorted, dkey0, dkey1, didx0, didx1, vlist, scan_part, keys0, keys1,
+        vals0, vals1, hist, digit_tot, ranges, grec, gd, nadj, counters, total;
     int64_t N, VN, total_tiles, total_pix, pair_cap;
     int V, nb_scan, depth_bits, tile_bits;
 };
@@ -73,7 +73,7 @@ struct Problem {
     int tile_w, tile_h;
     int64_t total_tiles, total_pix;
     float prune_Tk;
-    int depth_mode;  // 0: ray-ellipsoid midpoint, 1: Gaussian centre
+    int depth_mode;  // 0: ray-ellipsoid midpoint, 1: Gaussian centre, 2: midpoint on a hit, else centre
 };
 
 // ---- launchers (each enqueues on `s`; return the launch error) ----

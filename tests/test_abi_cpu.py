@@ -54,11 +54,12 @@ def test_options_validation(U):
     assert L.ugs_set_options(ctx, C.byref(bad)) == U.UGS_ERR_INVALID_ARG
     bad = U.default_options(lambda_=1.5)
     assert L.ugs_set_options(ctx, C.byref(bad)) == U.UGS_ERR_INVALID_ARG
-    bad = U.default_options(depth_mode=2)
+    bad = U.default_options(depth_mode=3)
     assert L.ugs_set_options(ctx, C.byref(bad)) == U.UGS_ERR_INVALID_ARG
     assert o.depth_mode == 0
-    ok = U.default_options(depth_mode=1)
-    assert L.ugs_set_options(ctx, C.byref(ok)) == U.UGS_OK
+    for m in (1, 2):
+        ok = U.default_options(depth_mode=m)
+        assert L.ugs_set_options(ctx, C.byref(ok)) == U.UGS_OK
     for tw, th in ((8, 8), (32, 8), (16, 16)):
         ok = U.default_options(tile_w=tw, tile_h=th)
         assert L.ugs_set_options(ctx, C.byref(ok)) == U.UGS_OK

@@ -175,12 +175,13 @@ def test_backward_parity(O, kind):
         assert e <= 1.0, (k, e)
 
 
-@pytest.mark.parametrize("kind", ["w1", "w3s"])
-def test_centre_depth_mode_parity(O, kind):
-    """Centre-point depth (depth_mode 1): images and gradients against the
+@pytest.mark.parametrize("kind,mode", [("w1", 1), ("w3s", 1), ("w1", 2), ("w3s", 2), ("w4s", 2)])
+def test_depth_mode_parity(O, kind, mode):
+    """Centre-point depth (depth_mode 1) and the midpoint with the centre as the
+    no-solution fallback (depth_mode 2): images and gradients against the
     oracle run in the same mode."""
-    _check_forward(O, kind, extra=dict(depth_mode=1))
-    err, _, _ = _check_backward(O, kind, with_normals=(kind == "w1"), extra=dict(depth_mode=1))
+    _check_forward(O, kind, extra=dict(depth_mode=mode))
+    err, _, _ = _check_backward(O, kind, with_normals=(kind == "w1"), extra=dict(depth_mode=mode))
     for k, e in err.items():
         assert e <= 1.0, (k, e)
 
