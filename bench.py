@@ -287,6 +287,20 @@ def main():
         t_fo = (time.perf_counter() - t0) / args.steps
         fwd_only = dict(value=round(Px / t_fo / 1e6, 2), unit="MP/s", ms_per_step=round(t_fo * 1e3, 3),
                         views_per_s=round(len(cams) / t_fo, 1))
+        # the same step writing binary16 colour, K, normal and semantic maps
+        fh = U.Rasterizer(prune_Tk=float(opts["prune_Tk"]), tile_w=rast.opts.tile_w, tile_h=rast.opts.tile_h,
+                          batch=rast.opts.batch, half_outputs=1)
+        out_h = U.alloc_outputs(cams, C_o, state=False, half=True)
+        fh.capture_step(g, cams, out_h, None, None)
+        for _ in range(args.warmup):
+            fh.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fh.replay()
+        torch.cuda.synchronize()
+        fwd_only["half_outputs_ms_per_step"] = round((time.perf_counter() - t0) / args.steps * 1e3, 3)
+        del fh, out_h
         log(f"[bench] forward-only {t_fo * 1e3:.3f} ms per {len(cams)} views ({fwd_only['value']} MP/s)")
         del fo, out_fo
 
@@ -299,7 +313,8 @@ def main():
         for name, mode in (("centre", 1), ("hit_else_centre", 2)):
             dm = U.Rasterizer(prune_Tk=float(opts["prune_Tk"]), tile_w=rast.opts.tile_w, tile_h=rast.opts.tile_h,
                               batch=rast.opts.batch, depth_mode=mode)
-            dm.capture_step(g, cams, out, up, grads)
+            out_dm = U.alloc_outputs(cams, C_o)
+            dm.capture_step(g, cams, out_dm, up, grads)
             for _ in range(args.warmup):
                 dm.replay()
             torch.cuda.synchronize()
@@ -308,7 +323,7 @@ def main():
                 dm.replay()
             torch.cuda.synchronize()
             depth_modes[name] = round((time.perf_counter() - t0) / args.steps * 1e3, 3)
-            del dm
+            del dm, out_dm
         depth_modes["unit"] = "ms per batched step"
         log(f"[bench] depth modes {depth_modes}")
 

@@ -117,6 +117,12 @@ typedef struct {
                               ellipsoid (the quadratic of section 3.2 has a real
                               root) and the centre depth where it has no valid
                               solution.  Gradients follow the chosen form. */
+    int half_outputs;    /* 1: the rgb, kmap, normal and sem maps of ugs_outputs
+                            are IEEE binary16 (the float pointers are read as
+                            2-byte elements, rounded to nearest even); depth,
+                            T_final and n_contrib keep their types.  For viewing
+                            and inference: ugs_render_bwd and training steps
+                            reject it.  Default 0 (FP32). */
 } ugs_options;
 
 typedef struct ugs_ctx ugs_ctx;

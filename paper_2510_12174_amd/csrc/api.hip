@@ -87,6 +87,7 @@ int check_options(const ugs_options *o)
     if (o->orient_sign != 1 && o->orient_sign != -1) return UGS_ERR_INVALID_ARG;
     if (!(o->prune_Tk >= 0.f)) return UGS_ERR_INVALID_ARG;
     if (o->depth_mode < 0 || o->depth_mode > 2) return UGS_ERR_INVALID_ARG;
+    if (o->half_outputs != 0 && o->half_outputs != 1) return UGS_ERR_INVALID_ARG;
     return UGS_OK;
 }
 
@@ -138,13 +139,14 @@ int check_outputs(const ugs_outputs *o, int C_o, bool need_state)
     if (!o) return UGS_ERR_INVALID_ARG;
     const void *ps[] = {o->rgb, o->depth, o->kmap, o->normal};
     for (auto p : ps)
-        if (!p || !aligned(p, 4)) return UGS_ERR_INVALID_ARG;
+        if (!p || !aligned(p, 2)) return UGS_ERR_INVALID_ARG;
+    if (!aligned(o->depth, 4)) return UGS_ERR_INVALID_ARG;
     const void *st[] = {o->T_final, o->n_contrib};
     for (auto p : st) {
         if (need_state && !p) return UGS_ERR_INVALID_ARG;
         if (p && !aligned(p, 4)) return UGS_ERR_INVALID_ARG;
     }
-    if (C_o > 0 && (!o->sem || !aligned(o->sem, 4))) return UGS_ERR_INVALID_ARG;
+    if (C_o > 0 && (!o->sem || !aligned(o->sem, 2))) return UGS_ERR_INVALID_ARG;
     return UGS_OK;
 }
 
@@ -169,6 +171,7 @@ void make_problem(const ugs_options &o, int64_t N, int C_o, int sh_deg, const ug
     pb.tile_h = o.tile_h;
     pb.prune_Tk = o.prune_Tk;
     pb.depth_mode = o.depth_mode;
+    pb.half_out = o.half_outputs;
     int64_t tiles = 0, pix = 0;
     for (int v = 0; v < V; ++v) {
         const ugs_camera &c = cams[v];
@@ -406,6 +409,7 @@ int check_bwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs 
 {
     int rc;
     if ((rc = check_fwd(ctx, g, ws, out))) return rc;
+    if (ctx->opt.half_outputs) return UGS_ERR_INVALID_ARG;  // half outputs are for forward-only use
     if ((rc = check_outputs(out, g->C_o, true))) return rc;
     if ((rc = check_grads(dg, g->C_o))) return rc;
     return up ? UGS_OK : UGS_ERR_INVALID_ARG;
@@ -565,6 +569,7 @@ void ugs_default_options(ugs_options *o)
     o->orient_sign = 1;
     o->prune_Tk = 0.f;
     o->depth_mode = 0;
+    o->half_outputs = 0;
 }
 
 int ugs_create(ugs_ctx **out, const ugs_options *opt)
@@ -676,6 +681,7 @@ int ugs_step_capture(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cam
         return rc;
     if ((!fwd_only && !dout) || !ws) return UGS_ERR_INVALID_ARG;
     if (fwd_only && ctx->timed_stage >= 5) return UGS_ERR_INVALID_ARG;
+    if (!fwd_only && ctx->opt.half_outputs) return UGS_ERR_INVALID_ARG;  // training steps need FP32 maps
     release_graph(ctx);
     hipStream_t s = (hipStream_t)stream;
     if (!ctx->host_flag) {
@@ -733,7 +739,7 @@ int ugs_autotune(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, i
                  const ugs_outputs *out, const ugs_upstream *dout, const ugs_gaussian_grads *dg, void *stream,
                  ugs_options *chosen, float *ms)
 {
-    if (!ctx || !g || !out || !dout || !dg) return UGS_ERR_INVALID_ARG;
+    if (!ctx || !g || !out || !dout || !dg || ctx->opt.half_outputs) return UGS_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     const ugs_options base = ctx->opt;
     struct Cand { int tw, th, batch; };

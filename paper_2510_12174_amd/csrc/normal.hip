@@ -96,7 +96,7 @@ __device__ __forceinline__ bool pixel_of(const DevCam *cams, int V, uint32_t nti
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW *TH) normal_fwd_kernel(const DevCam *__restrict__ cams, int V, uint32_t ntiles,
                                                            const float *__restrict__ depth, float *__restrict__ normal,
-                                                           int s1, int s2, float lam, int orient)
+                                                           int s1, int s2, float lam, int orient, int half_out)
 {
     int view, u, v;
     if (!pixel_of<TW, TH>(cams, V, ntiles, view, u, v)) return;
@@ -110,10 +110,10 @@ __global__ void __launch_bounds__(TW *TH) normal_fwd_kernel(const DevCam *__rest
         const float *R = cam.R;
         for (int c = 0; c < 3; ++c) N[c] = sg * (R[c] * S.n0[0] + R[3 + c] * S.n0[1] + R[6 + c] * S.n0[2]);
     }
-    float *o = normal + 3 * cam.pix_off;
-    o[p] = N[0];
-    o[HW + p] = N[1];
-    o[2 * HW + p] = N[2];
+    const int64_t o = 3 * cam.pix_off;
+    put_out(normal, o + p, N[0], half_out);
+    put_out(normal, o + HW + p, N[1], half_out);
+    put_out(normal, o + 2 * HW + p, N[2], half_out);
 }
 
 // Pass 1: adjoints of (vx1, vy1, vx2, vy2) in the camera frame, planar [12][pixels].
@@ -208,7 +208,7 @@ hipError_t nfwd(const Problem &pb, const WsLayout &L, char *ws, const ugs_output
 {
     hipLaunchKernelGGL((normal_fwd_kernel<TW, TH>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), 0, s,
                        (const DevCam *)(ws + L.cams), pb.V, (uint32_t)pb.total_tiles, out.depth, out.normal, o.step1, o.step2, o.lambda,
-                       o.orient_sign);
+                       o.orient_sign, pb.half_out);
     return hipGetLastError();
 }
 

@@ -245,7 +245,8 @@ template <int TW, int TH, int CO, bool HIT>
 __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
-    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles, int depth_mode, const float *__restrict__ hrec)
+    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles, int depth_mode, const float *__restrict__ hrec,
+    int half_out)
 {
     constexpr int NT = TW * TH;
     extern __shared__ float4 smem[];
@@ -319,17 +320,17 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
     }
     if (ti.inside) {
         const int64_t p = ti.pix, HW = ti.HW, off = ti.off;
-        out.rgb[3 * off + p] = cr;
-        out.rgb[3 * off + HW + p] = cg;
-        out.rgb[3 * off + 2 * HW + p] = cb;
+        put_out(out.rgb, 3 * off + p, cr, half_out);
+        put_out(out.rgb, 3 * off + HW + p, cg, half_out);
+        put_out(out.rgb, 3 * off + 2 * HW + p, cb, half_out);
         out.depth[off + p] = (float)D;
-        out.kmap[off + p] = K;
+        put_out(out.kmap, off + p, K, half_out);
         if (out.T_final) out.T_final[off + p] = (float)T;  // optional in forward-only use
         if (out.n_contrib) out.n_contrib[off + p] = last ? last - range.x : 0u;
         if constexpr (CO > 0) {
 #pragma unroll
             for (int c = 0; c < CO; ++c)
-                if (c < C_o) out.sem[(int64_t)C_o * off + c * HW + p] = acc[c];
+                if (c < C_o) put_out(out.sem, (int64_t)C_o * off + c * HW + p, acc[c], half_out);
         }
     }
     if (count) {
@@ -750,7 +751,8 @@ template <int TW, int TH, int CO, bool HIT>
 __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
-    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles, int depth_mode, const float *__restrict__ hrec)
+    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles, int depth_mode, const float *__restrict__ hrec,
+    int half_out)
 {
     static_assert(CO == 16 || CO == 32, "MFMA forward: C_o padded to 16 or 32");
     constexpr int NT = TW * TH;
@@ -868,11 +870,11 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
     }
     if (ti.inside) {
         const int64_t p = ti.pix, HW = ti.HW, off = ti.off;
-        out.rgb[3 * off + p] = cr;
-        out.rgb[3 * off + HW + p] = cg;
-        out.rgb[3 * off + 2 * HW + p] = cb;
+        put_out(out.rgb, 3 * off + p, cr, half_out);
+        put_out(out.rgb, 3 * off + HW + p, cg, half_out);
+        put_out(out.rgb, 3 * off + 2 * HW + p, cb, half_out);
         out.depth[off + p] = (float)D;
-        out.kmap[off + p] = K;
+        put_out(out.kmap, off + p, K, half_out);
         if (out.T_final) out.T_final[off + p] = (float)T;  // optional in forward-only use
         if (out.n_contrib) out.n_contrib[off + p] = last ? last - range.x : 0u;
     }
@@ -891,7 +893,8 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
                     for (int q = 0; q < NCB; ++q) {
                         const int c = 16 * q + l16;
                         if (c < C_o)
-                            out.sem[(int64_t)C_o * ti.off + (int64_t)c * ti.HW + (int64_t)y * W + x] = acc[pb][q][r];
+                            put_out(out.sem, (int64_t)C_o * ti.off + (int64_t)c * ti.HW + (int64_t)y * W + x,
+                                    acc[pb][q][r], half_out);
                     }
                 }
             }
@@ -927,13 +930,13 @@ hipError_t fwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
         auto k = pb.depth_mode == 2 ? render_fwd_mfma_kernel<TW, TH, CO, true> : render_fwd_mfma_kernel<TW, TH, CO, false>;
         hipLaunchKernelGGL(k, dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), fwd_mfma_lds(b, CO, NW), s, cams, pb.V,
                            pb.N, ranges, vals, rec, g.sem, pb.C_o, out, b, cnt, (int)counters,
-                           (uint32_t)pb.total_tiles, pb.depth_mode, hrec);
+                           (uint32_t)pb.total_tiles, pb.depth_mode, hrec, pb.half_out);
     } else {
         size_t lds = (size_t)batch * (64 + 4 * CO + 4);
         auto k = pb.depth_mode == 2 ? render_fwd_kernel<TW, TH, CO, true> : render_fwd_kernel<TW, TH, CO, false>;
         hipLaunchKernelGGL(k, dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s,
                            cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out, batch, cnt, (int)counters,
-                           (uint32_t)pb.total_tiles, pb.depth_mode, hrec);
+                           (uint32_t)pb.total_tiles, pb.depth_mode, hrec, pb.half_out);
     }
     return hipGetLastError();
 }

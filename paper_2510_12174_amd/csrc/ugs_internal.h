@@ -74,7 +74,17 @@ struct Problem {
     int64_t total_tiles, total_pix;
     float prune_Tk;
     int depth_mode;  // 0: ray-ellipsoid midpoint, 1: Gaussian centre, 2: midpoint on a hit, else centre
+    int half_out;    // rgb, kmap, normal and sem outputs in binary16
 };
+
+// Stores an output value as FP32 or, for half outputs, binary16 (nearest even).
+__device__ __forceinline__ void put_out(float *p, int64_t i, float v, int half)
+{
+    if (half)
+        reinterpret_cast<_Float16 *>(p)[i] = (_Float16)v;
+    else
+        p[i] = v;
+}
 
 // ---- launchers (each enqueues on `s`; return the launch error) ----
 hipError_t launch_project_fwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,

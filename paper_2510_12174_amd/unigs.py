@@ -68,7 +68,7 @@ class ugs_upstream(C.Structure):
 class ugs_options(C.Structure):
     _fields_ = [("tile_w", C.c_int), ("tile_h", C.c_int), ("batch", C.c_int), ("step1", C.c_int),
                 ("step2", C.c_int), ("lambda_", C.c_float), ("orient_sign", C.c_int), ("prune_Tk", C.c_float),
-                ("depth_mode", C.c_int)]
+                ("depth_mode", C.c_int), ("half_outputs", C.c_int)]
 
 
 class ugs_targets(C.Structure):
@@ -339,13 +339,16 @@ def pixel_offsets(cams):
     return off
 
 
-def alloc_outputs(cams, C_o, device="cuda", state=True):
+def alloc_outputs(cams, C_o, device="cuda", state=True, half=False):
     """Output planes for all views; state=False leaves out T_final and
-    n_contrib (forward-only use: the backward needs them)."""
+    n_contrib (forward-only use: the backward needs them); half=True makes the
+    rgb, kmap, normal and sem planes float16 (for a rasterizer created with
+    half_outputs=1)."""
     import torch
     P = pixel_offsets(cams)[-1]
     f = lambda n: torch.empty(n, dtype=torch.float32, device=device)
-    o = dict(rgb=f(3 * P), depth=f(P), kmap=f(P), normal=f(3 * P), sem=f(max(C_o, 0) * P))
+    h = (lambda n: torch.empty(n, dtype=torch.float16, device=device)) if half else f
+    o = dict(rgb=h(3 * P), depth=f(P), kmap=h(P), normal=h(3 * P), sem=h(max(C_o, 0) * P))
     if state:
         o.update(T_final=f(P), n_contrib=torch.empty(P, dtype=torch.int32, device=device))
     return o

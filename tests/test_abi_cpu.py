@@ -54,6 +54,8 @@ def test_options_validation(U):
     assert L.ugs_set_options(ctx, C.byref(bad)) == U.UGS_ERR_INVALID_ARG
     bad = U.default_options(lambda_=1.5)
     assert L.ugs_set_options(ctx, C.byref(bad)) == U.UGS_ERR_INVALID_ARG
+    bad = U.default_options(half_outputs=2)
+    assert L.ugs_set_options(ctx, C.byref(bad)) == U.UGS_ERR_INVALID_ARG
     bad = U.default_options(depth_mode=3)
     assert L.ugs_set_options(ctx, C.byref(bad)) == U.UGS_ERR_INVALID_ARG
     assert o.depth_mode == 0

@@ -312,6 +312,40 @@ def test_forward_only_step(O):
         r2.backward(gd, o2, Hn.stack_upstream(ups, g["C_o"]))
 
 
+@pytest.mark.parametrize("kind", ["w4s", "w2c12", "w3s"])
+def test_half_outputs_forward_only(O, kind):
+    """Binary16 outputs (half_outputs = 1, forward-only use): the rgb, kmap,
+    normal and semantic maps are the FP32 maps rounded to nearest even, bit for
+    bit, the depth map is unchanged; w4s and w2c12 run the matrix-core forward,
+    w3s (64 channels) the vector one.  Training steps and the backward refuse
+    half outputs."""
+    import torch
+    from paper_2510_12174_amd import unigs as U
+    g, cams, opts = Hn.small_workload(kind)
+    C_o = int(g["C_o"])
+    gd = U.to_device(g)
+    ref = U.alloc_outputs(cams, C_o, state=False)
+    r32 = U.Rasterizer(prune_Tk=float(opts.get("prune_Tk", 0.0)))
+    r32.capture_step(gd, cams, ref, None, None)
+    r32.replay()
+    r16 = U.Rasterizer(prune_Tk=float(opts.get("prune_Tk", 0.0)), half_outputs=1)
+    out = U.alloc_outputs(cams, C_o, state=False, half=True)
+    r16.capture_step(gd, cams, out, None, None)
+    for rep in range(2):
+        r16.replay()
+        torch.cuda.synchronize()
+        for k in ("rgb", "kmap", "normal", "sem"):
+            a = out[k].cpu().numpy()
+            b = ref[k].cpu().numpy().astype(np.float16)
+            assert a.dtype == np.float16 and np.array_equal(a.view(np.uint16), b.view(np.uint16)), (rep, k)
+        assert np.array_equal(out["depth"].cpu().numpy(), ref["depth"].cpu().numpy())
+    Hn.say(f"[{kind}] half outputs equal the rounded FP32 outputs")
+    ups = Hn.stack_upstream(Hn.scenes.upstream(cams, C_o, seed=3), C_o)
+    full = U.alloc_outputs(cams, C_o, half=True)
+    with pytest.raises(U.UgsError):
+        r16.capture_step(gd, cams, full, ups, U.zeros_like_params(gd))
+
+
 def test_autograd_function_matches_oracle(O):
     import torch
     from paper_2510_12174_amd import unigs as U
