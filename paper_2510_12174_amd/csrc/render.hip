@@ -127,7 +127,7 @@ __device__ __forceinline__ float frag_adjoint(bool contrib, float4 r0, float4 r1
     const float w = contrib ? alpha * Tn : 0.f;
     const float B = kd * (r2.x * dx + r2.y * dy);
     const float Cq = kd * (r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy);
-    const float iden = rcp_nr(1.f + 2.f * B + Cq);
+    const float iden = __builtin_amdgcn_rcpf(1.f + 2.f * B + Cq);  // 1 ulp: feeds gradients only
     const float z0 = r1.w;
     const float d = z0 * (1.f + B) * iden;
     const float s = gR * r3.y + gG * r3.z + gB * r3.w + gDp * d + gK * r1.z + s_sem;
@@ -241,7 +241,7 @@ __device__ __forceinline__ void stage_batch(float4 *srec, float *ssem, const uin
     }
 }
 
-template <int TW, int TH, int CO, bool HIT>
+template <int TW, int TH, int CO, int DM>
 __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
     extern __shared__ float4 smem[];
     float4 *srec = smem;
     float *ssem = (float *)(smem + 4 * batch);
-    float *shh = HIT ? ssem + (size_t)batch * CO : nullptr;
+    float *shh = DM == 2 ? ssem + (size_t)batch * CO : nullptr;
     const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
@@ -267,7 +267,8 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
     for (int c = 0; c < (CO > 0 ? CO : 1); ++c) acc[c] = 0.f;
     uint32_t last = 0, n_eval = 0, n_con = 0;
     bool done = !ti.inside;
-    const float kd = depth_mode == 1 ? 0.f : 1.f;
+    constexpr bool HIT = DM == 2;
+    constexpr float kd = DM == 1 ? 0.f : 1.f;  // depth form fixed per instantiation
 
     for (uint32_t start = range.x; start < range.y; start += (uint32_t)batch) {
         if (__syncthreads_count(done) == NT) break;
@@ -373,7 +374,7 @@ __device__ __forceinline__ void emit_groups(const float (&v)[16], float w, const
     if constexpr (REM > G) emit_groups<OFF + G, REM - G, CO, CA>(v, w, gO, lane, grec_i, dsem_i, C_o);
 }
 
-template <int TW, int TH, int CO, bool HIT>
+template <int TW, int TH, int CO, int DM>
 __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
@@ -387,7 +388,7 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     __shared__ uint32_t s_max;
     float4 *srec = smem;
     float *ssem = (float *)(smem + 4 * batch);
-    float *shh = HIT ? ssem + (size_t)batch * CO : nullptr;
+    float *shh = DM == 2 ? ssem + (size_t)batch * CO : nullptr;
     const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
@@ -430,7 +431,8 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, o, 64));
     wave_last = __builtin_amdgcn_readfirstlane(wave_last);
     float A = 0.f;
-    const float kd = depth_mode == 1 ? 0.f : 1.f;
+    constexpr bool HIT = DM == 2;
+    constexpr float kd = DM == 1 ? 0.f : 1.f;  // depth form fixed per instantiation
 
     for (uint32_t end = end_all; end > range.x;) {
         const uint32_t start = end - range.x > (uint32_t)batch ? end - (uint32_t)batch : range.x;
@@ -518,7 +520,7 @@ __device__ __forceinline__ mf4 mfma3(const bf8 &ah, const bf8 &al, const bf8 &bh
     return c;
 }
 
-template <int TW, int TH, int CO, bool HIT>
+template <int TW, int TH, int CO, int DM>
 // Four wavefronts per SIMD (at most 128 registers per lane): the kernel is bound
 // by VALU issue and dependency latency, and a fourth wavefront hides enough of
 // the latter to pay for the tighter register budget (no spills).
@@ -539,7 +541,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
     uint32_t *sid = (uint32_t *)(ssem + (size_t)batch * kSemRow);
     const int wave = (int)(threadIdx.x >> 6);
     float *wb = (float *)(sid + batch) + wave * (kGrp * kWbStride);
-    float *shh = HIT ? (float *)(sid + batch) + (TW * TH / 64) * (kGrp * kWbStride) : nullptr;
+    float *shh = DM == 2 ? (float *)(sid + batch) + (TW * TH / 64) * (kGrp * kWbStride) : nullptr;
     const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
@@ -606,7 +608,8 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
     for (int o = 32; o > 0; o >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, o, 64));
     wave_last = __builtin_amdgcn_readfirstlane(wave_last);
     float A = 0.f;
-    const float kd = depth_mode == 1 ? 0.f : 1.f;
+    constexpr bool HIT = DM == 2;
+    constexpr float kd = DM == 1 ? 0.f : 1.f;  // depth form fixed per instantiation
 
     for (uint32_t end = end_all; end > range.x;) {
         const uint32_t start = end - range.x > (uint32_t)batch ? end - (uint32_t)batch : range.x;
@@ -747,7 +750,7 @@ __host__ __device__ constexpr size_t fwd_mfma_lds(int batch, int CO, int NW)
     return (size_t)batch * (64 + 4) + (size_t)2 * CO * fwd_semT_stride(batch) * 2 + (size_t)NW * kGrp * kWbStride * 4;
 }
 
-template <int TW, int TH, int CO, bool HIT>
+template <int TW, int TH, int CO, int DM>
 __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
@@ -764,7 +767,7 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
     short *seml = semh + CO * RS;
     const int wave = (int)(threadIdx.x >> 6);
     float *wb = (float *)(seml + CO * RS) + wave * (kGrp * kWbStride);
-    float *shh = HIT ? (float *)(seml + CO * RS) + (NT / 64) * (kGrp * kWbStride) : nullptr;
+    float *shh = DM == 2 ? (float *)(seml + CO * RS) + (NT / 64) * (kGrp * kWbStride) : nullptr;
     const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
@@ -783,7 +786,8 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
         for (int q = 0; q < NCB; ++q) acc[pb][q] = mf4{0.f, 0.f, 0.f, 0.f};
     uint32_t last = 0, n_eval = 0, n_con = 0;
     bool done = !ti.inside;
-    const float kd = depth_mode == 1 ? 0.f : 1.f;
+    constexpr bool HIT = DM == 2;
+    constexpr float kd = DM == 1 ? 0.f : 1.f;  // depth form fixed per instantiation
 
     for (uint32_t start = range.x; start < range.y; start += (uint32_t)batch) {
         if (__syncthreads_count(done) == NT) break;
@@ -927,13 +931,15 @@ hipError_t fwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
         constexpr int NW = TW * TH / 64;
         int b = (batch + kGrp - 1) / kGrp * kGrp;
         while (b > kGrp && fwd_mfma_lds(b, CO, NW) > 64 * 1024) b -= kGrp;
-        auto k = pb.depth_mode == 2 ? render_fwd_mfma_kernel<TW, TH, CO, true> : render_fwd_mfma_kernel<TW, TH, CO, false>;
+        auto k = pb.depth_mode == 2 ? render_fwd_mfma_kernel<TW, TH, CO, 2>
+                 : pb.depth_mode == 1 ? render_fwd_mfma_kernel<TW, TH, CO, 1> : render_fwd_mfma_kernel<TW, TH, CO, 0>;
         hipLaunchKernelGGL(k, dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), fwd_mfma_lds(b, CO, NW), s, cams, pb.V,
                            pb.N, ranges, vals, rec, g.sem, pb.C_o, out, b, cnt, (int)counters,
                            (uint32_t)pb.total_tiles, pb.depth_mode, hrec, pb.half_out);
     } else {
         size_t lds = (size_t)batch * (64 + 4 * CO + 4);
-        auto k = pb.depth_mode == 2 ? render_fwd_kernel<TW, TH, CO, true> : render_fwd_kernel<TW, TH, CO, false>;
+        auto k = pb.depth_mode == 2 ? render_fwd_kernel<TW, TH, CO, 2>
+                 : pb.depth_mode == 1 ? render_fwd_kernel<TW, TH, CO, 1> : render_fwd_kernel<TW, TH, CO, 0>;
         hipLaunchKernelGGL(k, dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s,
                            cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out, batch, cnt, (int)counters,
                            (uint32_t)pb.total_tiles, pb.depth_mode, hrec, pb.half_out);
@@ -958,13 +964,15 @@ hipError_t bwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
         constexpr int NW = TW * TH / 64;
         int b = (batch + kGrp - 1) / kGrp * kGrp;
         while (b > kGrp && bwd_mfma_lds(b, NW) > 64 * 1024) b -= kGrp;
-        auto k = pb.depth_mode == 2 ? render_bwd_mfma_kernel<TW, TH, CO, true> : render_bwd_mfma_kernel<TW, TH, CO, false>;
+        auto k = pb.depth_mode == 2 ? render_bwd_mfma_kernel<TW, TH, CO, 2>
+                 : pb.depth_mode == 1 ? render_bwd_mfma_kernel<TW, TH, CO, 1> : render_bwd_mfma_kernel<TW, TH, CO, 0>;
         hipLaunchKernelGGL(k, dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), bwd_mfma_lds(b, NW), s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o,
                            out.T_final, out.n_contrib, up.rgb, gd, up.kmap, up.sem, grec, dg.sem, b,
                            (uint32_t)pb.total_tiles, pb.depth_mode, hrec);
     } else {
         size_t lds = (size_t)batch * (64 + 4 * CO + 4);
-        auto k = pb.depth_mode == 2 ? render_bwd_kernel<TW, TH, CO, true> : render_bwd_kernel<TW, TH, CO, false>;
+        auto k = pb.depth_mode == 2 ? render_bwd_kernel<TW, TH, CO, 2>
+                 : pb.depth_mode == 1 ? render_bwd_kernel<TW, TH, CO, 1> : render_bwd_kernel<TW, TH, CO, 0>;
         hipLaunchKernelGGL(k, dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s,
                            cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out.T_final, out.n_contrib, up.rgb, gd,
                            up.kmap, up.sem, grec, dg.sem, batch, (uint32_t)pb.total_tiles, pb.depth_mode, hrec);
