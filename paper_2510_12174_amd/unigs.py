@@ -12,6 +12,7 @@ raises.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 
 import numpy as np
@@ -511,7 +512,31 @@ class Rasterizer:
     def replay(self):
         _chk(lib().ugs_step_replay(self.ctx, _stream()), "ugs_step_replay", self.ctx)
 
-    def autotune(self, g, cams, out, up, grads):
+    def autotune(self, g, cams, out, up, grads, cache=None):
+        """ugs_autotune, with its choice cached in a JSON file keyed by
+        tune_key() (GPU architecture, channels, SH degree, Gaussian-count and
+        megapixel buckets).  cache: a path, False for no cache, or None for
+        $UNIGS_TUNE_CACHE (default ~/.cache/unigs/autotune.json).  A cached
+        choice is applied without timing (the result then has cached=True)."""
+        path = tune_cache_path(cache)
+        key = tune_key(g, cams)
+        if path:
+            hit = _read_json(path).get(key)
+            if hit:
+                self.set_options(tile_w=int(hit["tile_w"]), tile_h=int(hit["tile_h"]), batch=int(hit["batch"]))
+                return dict(hit, cached=True)
+        res = self._autotune(g, cams, out, up, grads)
+        if path:
+            d = _read_json(path)
+            d[key] = res
+            os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+            tmp = path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(d, f, indent=1, sort_keys=True)
+            os.replace(tmp, path)
+        return dict(res, cached=False)
+
+    def _autotune(self, g, cams, out, up, grads):
         P = self.project_and_sort(g, cams)
         # the smallest tile needs the most pairs: leave room for it (candidates
         # that still overflow are skipped by the library)
@@ -524,6 +549,34 @@ class Rasterizer:
         _chk(rc, "ugs_autotune", self.ctx)
         self.opts = chosen
         return dict(tile_w=chosen.tile_w, tile_h=chosen.tile_h, batch=chosen.batch, ms=float(ms.value))
+
+
+def tune_key(g, cams):
+    """Autotune cache key: GPU architecture, C_o, SH degree, and power-of-two
+    buckets of the Gaussian count and of the pixel count."""
+    import torch
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    n = max(int(g["N"]), 1)
+    px = max(sum(int(c["W"]) * int(c["H"]) for c in cams), 1)
+    return f"{arch}|C_o={int(g['C_o'])}|sh={int(g['sh_deg'])}|N~2^{n.bit_length()}|px~2^{px.bit_length()}"
+
+
+def tune_cache_path(cache=None):
+    if cache is False:
+        return None
+    if cache:
+        return str(cache)
+    return os.environ.get("UNIGS_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "unigs",
+                                                              "autotune.json")
+
+
+def _read_json(path):
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
 
 
 def _autograd_function():

@@ -346,6 +346,76 @@ def test_half_outputs_forward_only(O, kind):
         r16.capture_step(gd, cams, full, ups, U.zeros_like_params(gd))
 
 
+def test_pair_capacity_overflow():
+    """Capacity handling of the pair buffer: an eager bin_sort with too small a
+    capacity refuses with the required count; a captured step whose Gaussians
+    grow past its capacity writes zero outputs and gradients on that replay
+    (nothing out of bounds: the emission is clipped to the capacity) and the
+    next replay reports UGS_ERR_CAPACITY."""
+    import ctypes as C
+    import torch
+    from paper_2510_12174_amd import unigs as U
+    g, cams, opts = Hn.small_workload("w4s")
+    C_o = int(g["C_o"])
+    gd = U.to_device(g)
+    rast = U.Rasterizer()
+    rast.ensure_workspace(gd, cams, 16)
+    s = U._stream()
+    U._chk(U.lib().ugs_project(rast.ctx, C.byref(U.make_gaussians(gd)), U.make_cameras(cams), len(cams),
+                               rast.ws_ptr, rast.ws_bytes, s), "ugs_project")
+    P = C.c_int64()
+    rc = U.lib().ugs_bin_sort(rast.ctx, rast.ws_ptr, s, C.byref(P))
+    Hn.say(f"[capacity] eager bin_sort with 16 pairs: rc={rc} required={P.value}")
+    assert rc == U.UGS_ERR_CAPACITY and P.value > 16
+    out = U.alloc_outputs(cams, C_o)
+    up = Hn.stack_upstream(Hn.scenes.upstream(cams, C_o, seed=2), C_o)
+    grads = U.zeros_like_params(gd)
+    rast2 = U.Rasterizer()
+    rast2.capture_step(gd, cams, out, up, grads, margin=1.0)
+    rast2.replay()
+    torch.cuda.synchronize()
+    assert float(out["rgb"].abs().sum()) > 0
+    cap = rast2.pair_cap
+    gd["log_scale"].add_(3.0)  # 20x larger splats: many more pairs than the capacity
+    rast2.replay()
+    torch.cuda.synchronize()
+    need = U.Rasterizer().project_and_sort(gd, cams)
+    Hn.say(f"[capacity] capacity {cap}, pairs after growth {need}")
+    assert need > cap
+    assert float(out["rgb"].abs().sum()) == 0 and bool((out["T_final"] == 1).all())
+    assert all(float(v.abs().sum()) == 0 for v in grads.values())
+    with pytest.raises(U.UgsError) as e:
+        rast2.replay()
+    assert e.value.code == U.UGS_ERR_CAPACITY
+
+
+def test_autotune_and_cache(tmp_path):
+    """ugs_autotune picks one of its candidates and leaves the forward outputs
+    unchanged (bit for bit except the semantic map, to rounding); the binding
+    caches the choice in JSON and a second rasterizer applies it untimed."""
+    import torch
+    from paper_2510_12174_amd import unigs as U
+    g, cams, opts = Hn.small_workload("w4s")
+    C_o = int(g["C_o"])
+    gd = U.to_device(g)
+    up = Hn.stack_upstream(Hn.scenes.upstream(cams, C_o, seed=4), C_o)
+    cache = tmp_path / "tune.json"
+    ref, _, _ = Hn.gpu_run(g, cams, opts)
+    r1 = U.Rasterizer()
+    t1 = r1.autotune(gd, cams, U.alloc_outputs(cams, C_o), up, U.zeros_like_params(gd), cache=cache)
+    Hn.say(f"[autotune] {t1}")
+    assert not t1["cached"] and (t1["tile_w"], t1["tile_h"]) in ((16, 16), (8, 8), (32, 8)) and t1["batch"] >= 16
+    r2 = U.Rasterizer()
+    t2 = r2.autotune(gd, cams, U.alloc_outputs(cams, C_o), up, U.zeros_like_params(gd), cache=cache)
+    assert t2["cached"] and (t2["tile_w"], t2["tile_h"], t2["batch"]) == (t1["tile_w"], t1["tile_h"], t1["batch"])
+    assert (r2.opts.tile_w, r2.opts.tile_h, r2.opts.batch) == (t1["tile_w"], t1["tile_h"], t1["batch"])
+    outs, _, _ = Hn.gpu_run(g, cams, opts, rast=r2)
+    for a, b in zip(outs, ref):
+        for k in ("rgb", "depth", "kmap", "normal", "T_final"):
+            assert np.array_equal(a[k], b[k]), k
+        assert np.abs(a["sem"] - b["sem"]).max() <= 1e-5
+
+
 def test_autograd_function_matches_oracle(O):
     import torch
     from paper_2510_12174_amd import unigs as U
