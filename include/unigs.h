@@ -93,9 +93,16 @@ typedef struct {
 } ugs_outputs;
 
 /* Upstream gradients dL/d(output), same layouts as ugs_outputs.  A NULL map
- * means zero.  These are the loss gradients Alg. backward_render takes. */
+ * means zero.  These are the loss gradients Alg. backward_render takes.
+ * Fused cosine seed: when `normal` is NULL and `normal_target` is set, the
+ * normal gradient is formed inside Alg. normal_gradient as
+ * (*normal_scale) * normal_target (the seed -N_target / |Omega| of
+ * Eq. gradientn, with the loss weight folded into the device scalar
+ * `normal_scale`, e.g. the coefficient ugs_loss writes at losses[10]); both
+ * pointers are device memory, normal_target laid out like the normal map. */
 typedef struct {
     const float *rgb, *depth, *kmap, *normal, *sem;
+    const float *normal_target, *normal_scale;
 } ugs_upstream;
 
 /* Options.  Zero-initialise and call ugs_default_options() to get the defaults. */
@@ -178,7 +185,9 @@ int ugs_render_fwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_out
  * semantics and alpha), and the chain into the parameters (supplementary S1.2
  * for depth -> (mu, s, R), R -> q by the tangent projection, EWA and SH
  * adjoints).  `out` must hold the outputs of the matching ugs_render_fwd.
- * Gradients are summed over views and ADDED to `dg`. */
+ * Gradients are summed over views and ADDED to `dg`.  One ugs_render_bwd per
+ * ugs_project: the projection clears the per-record gradient buffers of the
+ * workspace that this call accumulates into. */
 int ugs_render_bwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs *out,
                    const ugs_upstream *dout, const ugs_gaussian_grads *dg, void *stream);
 
@@ -293,6 +302,8 @@ typedef struct {
     const int32_t *label;  /* [H][W] class index in [0, C_o) per view, or NULL */
 } ugs_targets;
 
+#define UGS_LOSS_VALUES 14
+
 typedef struct {
     float lambda[6];  /* weights of l1, ssim, normal, depth, seg, K (1, 0.1 x 5) */
     int balance;      /* 1: scale terms by |L_l1| / |L_x| */
@@ -306,10 +317,13 @@ int ugs_loss_scratch_size(const ugs_camera *cams, int V, size_t *bytes);
 
 /* Evaluates the loss of `out` against `gt` and writes dL_all/d(map) into the
  * caller-owned device maps of `grad` (same layouts as ugs_outputs; rgb, kmap
- * always written, depth/normal/sem written as zero when their term is absent;
- * the pointers are written through despite the const of ugs_upstream).
- * `losses` is device memory for 8 floats: L_l1, L_ssim, L_normal, L_depth,
- * L_seg, L_K, L_all and the SSIM mean.  `scratch` (256-byte aligned,
+ * always written, depth/normal/sem written when non-NULL, as zero when their
+ * term is absent; the pointers are written through despite the const of
+ * ugs_upstream; a NULL grad->normal leaves the normal seed to the fused form of
+ * ugs_upstream).  `losses` is device memory for UGS_LOSS_VALUES floats: L_l1,
+ * L_ssim, L_normal, L_depth, L_seg, L_K, L_all and the SSIM mean, then the six
+ * per-term gradient coefficients (d L_all / d map element of the l1, ssim,
+ * normal, depth, seg and K terms; losses[10] is the fused normal seed's scale).  `scratch` (256-byte aligned,
  * ugs_loss_scratch_size bytes) is overwritten.  Asynchronous on `stream`.
  * Errors: UGS_ERR_INVALID_ARG (NULL rgb maps, NULL or misaligned buffers,
  * C_o out of range, labels without C_o). */

@@ -412,7 +412,8 @@ int check_bwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs 
     if (ctx->opt.half_outputs) return UGS_ERR_INVALID_ARG;  // half outputs are for forward-only use
     if ((rc = check_outputs(out, g->C_o, true))) return rc;
     if ((rc = check_grads(dg, g->C_o))) return rc;
-    return up ? UGS_OK : UGS_ERR_INVALID_ARG;
+    if (!up || (!up->normal && up->normal_target && !up->normal_scale)) return UGS_ERR_INVALID_ARG;
+    return UGS_OK;
 }
 
 // Stages of one step: 0 zero gradients, 1 project, 2 bin+sort, 3 compositing

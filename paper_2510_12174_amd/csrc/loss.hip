@@ -391,6 +391,7 @@ __global__ void __launch_bounds__(1024) finalize(const double *__restrict__ part
     h->coef[3] = (float)(opt.lambda[3] * w[3] / n1);
     h->coef[4] = (float)(opt.lambda[4] * w[4] / n1);
     h->coef[5] = (float)(opt.lambda[5] * w[5] / n1);
+    for (int k = 0; k < 6; ++k) losses[8 + k] = h->coef[k];
 }
 
 template <int NP>

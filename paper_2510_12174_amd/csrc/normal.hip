@@ -120,7 +120,9 @@ __global__ void __launch_bounds__(TW *TH) normal_fwd_kernel(const DevCam *__rest
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW *TH) normal_adj_kernel(const DevCam *__restrict__ cams, int V, uint32_t ntiles,
                                                            const float *__restrict__ depth,
-                                                           const float *__restrict__ dnormal, int64_t total_pix,
+                                                           const float *__restrict__ dnormal,
+                                                           const float *__restrict__ ntgt,
+                                                           const float *__restrict__ nscale, int64_t total_pix,
                                                            float *__restrict__ adj, int s1, int s2, float lam,
                                                            int orient)
 {
@@ -136,6 +138,11 @@ __global__ void __launch_bounds__(TW *TH) normal_adj_kernel(const DevCam *__rest
         gw[0] = dn[p];
         gw[1] = dn[HW + p];
         gw[2] = dn[2 * HW + p];
+    } else if (ntgt) {  // fused cosine seed: scale * N_target
+        const float *nt = ntgt + 3 * cam.pix_off, sc = *nscale;
+        gw[0] = sc * nt[p];
+        gw[1] = sc * nt[HW + p];
+        gw[2] = sc * nt[2 * HW + p];
     }
     if (gw[0] != 0.f || gw[1] != 0.f || gw[2] != 0.f) {
         NState S;
@@ -220,7 +227,8 @@ hipError_t nbwd(const Problem &pb, const WsLayout &L, char *ws, const ugs_output
     auto adj = (float *)(ws + L.nadj);
     auto gd = (float *)(ws + L.gd);
     hipLaunchKernelGGL((normal_adj_kernel<TW, TH>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), 0, s, cams, pb.V,
-                       (uint32_t)pb.total_tiles, out.depth, up.normal, pb.total_pix, adj, o.step1, o.step2, o.lambda, o.orient_sign);
+                       (uint32_t)pb.total_tiles, out.depth, up.normal, up.normal_target, up.normal_scale, pb.total_pix, adj,
+                       o.step1, o.step2, o.lambda, o.orient_sign);
     hipLaunchKernelGGL((normal_gather_kernel<TW, TH>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), 0, s, cams,
                        pb.V, (uint32_t)pb.total_tiles, (const float *)adj, pb.total_pix, up.depth, gd, o.step1, o.step2);
     return hipGetLastError();

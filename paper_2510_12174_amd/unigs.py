@@ -63,7 +63,7 @@ class ugs_outputs(C.Structure):
 
 
 class ugs_upstream(C.Structure):
-    _fields_ = [(k, C.c_void_p) for k in ("rgb", "depth", "kmap", "normal", "sem")]
+    _fields_ = [(k, C.c_void_p) for k in ("rgb", "depth", "kmap", "normal", "sem", "normal_target", "normal_scale")]
 
 
 class ugs_options(C.Structure):
@@ -80,7 +80,9 @@ class ugs_loss_options(C.Structure):
     _fields_ = [("lambda_", C.c_float * 6), ("balance", C.c_int)]
 
 
-LOSS_NAMES = ("l1", "ssim", "normal", "depth", "seg", "K", "all", "ssim_mean")
+LOSS_NAMES = ("l1", "ssim", "normal", "depth", "seg", "K", "all", "ssim_mean",
+              "coef_l1", "coef_ssim", "coef_normal", "coef_depth", "coef_seg", "coef_K")
+UGS_LOSS_VALUES = 14
 
 _lib = None
 
@@ -203,7 +205,7 @@ def make_outputs(o):
 
 def make_upstream(u):
     s = ugs_upstream()
-    for k in ("rgb", "depth", "kmap", "normal", "sem"):
+    for k in ("rgb", "depth", "kmap", "normal", "sem", "normal_target", "normal_scale"):
         t = u.get(k) if u else None
         setattr(s, k, t.data_ptr() if t is not None and t.numel() > 0 else None)
     return s
@@ -306,7 +308,7 @@ class Loss:
     scratch buffer, the 8-float loss vector and the gradient maps, which are
     the upstream of Rasterizer.backward."""
 
-    def __init__(self, cams, C_o, lambdas=None, balance=True, device="cuda"):
+    def __init__(self, cams, C_o, lambdas=None, balance=True, device="cuda", fuse_normal=False):
         import torch
         self.cams_c = make_cameras(cams)
         self.V, self.C_o = len(cams), int(C_o)
@@ -314,10 +316,14 @@ class Loss:
         _chk(lib().ugs_loss_scratch_size(self.cams_c, self.V, C.byref(nb)), "ugs_loss_scratch_size")
         self.scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
         self.nb = int(nb.value)
-        self.losses = torch.zeros(8, dtype=torch.float32, device=device)
+        self.losses = torch.zeros(UGS_LOSS_VALUES, dtype=torch.float32, device=device)
         P = pixel_offsets(cams)[-1]
         f = lambda n: torch.empty(n, dtype=torch.float32, device=device)
-        self.grad = dict(rgb=f(3 * P), depth=f(P), kmap=f(P), normal=f(3 * P), sem=f(max(self.C_o, 0) * P))
+        # fuse_normal: no normal gradient map; the backward forms the cosine seed
+        # itself from the target normals and the coefficient in losses[10]
+        self.fuse_normal = bool(fuse_normal)
+        self.grad = dict(rgb=f(3 * P), depth=f(P), kmap=f(P), normal=None if fuse_normal else f(3 * P),
+                         sem=f(max(self.C_o, 0) * P))
         self.opts = loss_options(lambdas, balance)
 
     def __call__(self, out, gt):
@@ -330,6 +336,11 @@ class Loss:
         o, u = make_outputs(out), make_upstream(self.grad)
         _chk(lib().ugs_loss(self.cams_c, self.V, self.C_o, C.byref(o), C.byref(t), C.byref(self.opts), C.byref(u),
                             _ptr(self.losses), _ptr(self.scratch), self.nb, _stream()), "ugs_loss")
+        if self.fuse_normal:
+            up = dict(self.grad)
+            if gt.get("normal") is not None:
+                up.update(normal_target=gt["normal"], normal_scale=self.losses[10:11])
+            return self.losses, up
         return self.losses, self.grad
 
 

@@ -45,7 +45,7 @@ def run_gpu(cams, C_o, outs, gts, balance=True):
     loss = U.Loss(cams, C_o, balance=balance)
     losses, grad = loss(out, gt)
     torch.cuda.synchronize()
-    Lv = dict(zip(NAMES, losses.cpu().numpy().astype(np.float64)))
+    Lv = dict(zip(U.LOSS_NAMES, losses.cpu().numpy().astype(np.float64)))
     gv = []
     views = {k: U.split_views(grad[k], cams, c) for k, c in (("rgb", 3), ("depth", 1), ("kmap", 1), ("normal", 3))}
     views["sem"] = U.split_views(grad["sem"], cams, C_o)
@@ -65,6 +65,17 @@ def compare(cams, C_o, outs, gts, balance=True, tag=""):
         err = abs(Lg[k] - Lr[k])
         Hn.say(f"[loss {tag}] {k}: gpu {Lg[k]:.8g} ref {Lr[k]:.8g} err {err:.3g}")
         assert err <= LOSS_REL * abs(Lr[k]) + 1e-6, k
+    # per-term gradient coefficients (d L_all / d map element), from the FP64 values
+    P = sum(int(c["W"]) * int(c["H"]) for c in cams)
+    lam = OL.DEFAULT_LAMBDAS
+    on = dict(l1=True, ssim=True, normal=gts[0].get("normal") is not None, depth=gts[0].get("depth") is not None,
+              seg=gts[0].get("label") is not None, K=True)
+    for k, (n, sign, den) in enumerate([("l1", 1, 3), ("ssim", -1, 3), ("normal", -1, 1), ("depth", 1, 1),
+                                        ("seg", 1, 1), ("K", 1, 1)]):
+        w = 1.0 if (n == "l1" or not balance) else (abs(Lr["l1"]) / abs(Lr[n]) if Lr[n] != 0 else 0.0)
+        ref = sign * lam[k] * (w if on[n] else 0.0) / (den * P)
+        got = Lg["coef_" + n]
+        assert abs(got - ref) <= LOSS_REL * abs(ref) + 1e-12, (n, got, ref)
     for key in ("rgb", "depth", "kmap", "normal", "sem"):
         a = np.concatenate([g[key].reshape(-1) for g in gg])
         b = np.concatenate([np.asarray(g[key], np.float64).reshape(-1) for g in gr])
@@ -109,6 +120,41 @@ def test_loss_on_rendered_maps():
     outs = [{k: np.ascontiguousarray(o[k], np.float32) for k in ("rgb", "depth", "kmap", "normal", "sem")}
             for o in outs]
     compare(cams, C_o, outs, gts, True, "rendered w4s")
+
+
+def test_fused_cosine_seed_matches_map():
+    """The cosine seed formed inside the normal backward (normal_target and the
+    device coefficient losses[10]) gives the same parameter gradients as the
+    loss's explicit normal-gradient map."""
+    import torch
+    from paper_2510_12174_amd import unigs as U
+    g, cams, opts = Hn.small_workload("w4s")
+    C_o = int(g["C_o"])
+    gd = U.to_device(g)
+    rast = U.Rasterizer()
+    out = rast.forward(gd, cams)
+    _, gts = synth(5, [(c["W"], c["H"]) for c in cams], C_o, bad_labels=False)
+    cat = lambda key: torch.from_numpy(np.concatenate([np.asarray(d[key]).reshape(-1) for d in gts])).cuda()
+    gt = {k: cat(k) for k in ("rgb", "depth", "normal", "label")}
+    _, up_map = U.Loss(cams, C_o)(out, gt)
+    _, up_fused = U.Loss(cams, C_o, fuse_normal=True)(out, gt)
+    assert up_fused["normal"] is None and up_fused["normal_scale"].numel() == 1
+    # G_D (depth upstream plus the normal branch, the normal backward's output)
+    # is formed without atomics: bit-identical; the parameter gradients go
+    # through float atomics, so they agree to rounding
+    a = rast.backward(gd, out, up_map)
+    gd_map = rast.debug_buffer("depth_grad").clone()
+    rast.forward(gd, cams, out)  # one backward per projection
+    b = rast.backward(gd, out, up_fused)
+    gd_fused = rast.debug_buffer("depth_grad").clone()
+    torch.cuda.synchronize()
+    assert float(gd_map.abs().sum()) > 0 and torch.equal(gd_map, gd_fused)
+    for k in U.PARAM_KEYS:
+        x, y = a[k].cpu().numpy().astype(np.float64), b[k].cpu().numpy().astype(np.float64)
+        if x.size:
+            rms = np.sqrt(np.mean(x * x)) + 1e-30
+            assert np.max(np.abs(x - y)) <= 1e-4 * rms, (k, np.max(np.abs(x - y)) / rms)
+    Hn.say("[loss] fused cosine seed equals the explicit normal map")
 
 
 def test_loss_full_resolution_views():
