@@ -133,20 +133,22 @@ int check_grads(const ugs_gaussian_grads *d, int C_o)
 }
 
 // The forward needs the image planes; T_final and n_contrib are optional for
-// it (forward-only use) and required by the backward.
-int check_outputs(const ugs_outputs *o, int C_o, bool need_state)
+// it (forward-only use) and required by the backward.  Binary16 maps need
+// 2-byte alignment, FP32 ones 4.
+int check_outputs(const ugs_outputs *o, int C_o, bool need_state, bool half)
 {
     if (!o) return UGS_ERR_INVALID_ARG;
-    const void *ps[] = {o->rgb, o->depth, o->kmap, o->normal};
+    const size_t a = half ? 2 : 4;
+    const void *ps[] = {o->rgb, o->kmap, o->normal};
     for (auto p : ps)
-        if (!p || !aligned(p, 2)) return UGS_ERR_INVALID_ARG;
-    if (!aligned(o->depth, 4)) return UGS_ERR_INVALID_ARG;
+        if (!p || !aligned(p, a)) return UGS_ERR_INVALID_ARG;
+    if (!o->depth || !aligned(o->depth, 4)) return UGS_ERR_INVALID_ARG;
     const void *st[] = {o->T_final, o->n_contrib};
     for (auto p : st) {
         if (need_state && !p) return UGS_ERR_INVALID_ARG;
         if (p && !aligned(p, 4)) return UGS_ERR_INVALID_ARG;
     }
-    if (C_o > 0 && (!o->sem || !aligned(o->sem, 2))) return UGS_ERR_INVALID_ARG;
+    if (C_o > 0 && (!o->sem || !aligned(o->sem, a))) return UGS_ERR_INVALID_ARG;
     return UGS_OK;
 }
 
@@ -399,7 +401,7 @@ int check_fwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs 
 {
     int rc;
     if (!ctx->sorted || ws != ctx->ws) return UGS_ERR_STATE;
-    if ((rc = check_gaussians(g)) || (rc = check_outputs(out, g->C_o, false))) return rc;
+    if ((rc = check_gaussians(g)) || (rc = check_outputs(out, g->C_o, false, ctx->opt.half_outputs))) return rc;
     if (g->N != ctx->pb.N || g->C_o != ctx->pb.C_o || g->sh_deg != ctx->pb.sh_deg) return UGS_ERR_INVALID_ARG;
     return UGS_OK;
 }
@@ -410,7 +412,7 @@ int check_bwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs 
     int rc;
     if ((rc = check_fwd(ctx, g, ws, out))) return rc;
     if (ctx->opt.half_outputs) return UGS_ERR_INVALID_ARG;  // half outputs are for forward-only use
-    if ((rc = check_outputs(out, g->C_o, true))) return rc;
+    if ((rc = check_outputs(out, g->C_o, true, false))) return rc;
     if ((rc = check_grads(dg, g->C_o))) return rc;
     if (!up || (!up->normal && up->normal_target && !up->normal_scale)) return UGS_ERR_INVALID_ARG;
     return UGS_OK;
@@ -677,7 +679,7 @@ int ugs_step_capture(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cam
     int rc;
     // dout and dg both NULL: a forward-only step (project, bin_sort, render_fwd, normals)
     const bool fwd_only = !dout && !dg;
-    if ((rc = check_gaussians(g)) || (rc = check_cams(cams, V)) || (rc = check_outputs(out, g->C_o, !fwd_only)) ||
+    if ((rc = check_gaussians(g)) || (rc = check_cams(cams, V)) || (rc = check_outputs(out, g->C_o, !fwd_only, ctx->opt.half_outputs)) ||
         (!fwd_only && (rc = check_grads(dg, g->C_o))))
         return rc;
     if ((!fwd_only && !dout) || !ws) return UGS_ERR_INVALID_ARG;
