@@ -377,7 +377,7 @@ def main():
         b_l = (96 + 8 * C_o) * Px  # every input map read once, every gradient map written once
         loss_res = dict(ms=round(t_l * 1e3, 3), alg_bytes=int(b_l), achieved_gbps=round(b_l / t_l / 1e9, 1),
                         peak_gbps=PEAK_HBM / 1e9, frac=round(b_l / t_l / PEAK_HBM, 4),
-                        values=dict(zip(U.LOSS_NAMES, [round(float(x), 6) for x in lv.cpu()])))
+                        values=dict(zip(U.LOSS_NAMES, [float(f"{float(x):.6g}") for x in lv.cpu()])))
         log(f"[bench] loss {loss_res}")
         del gt, lossf
 

@@ -137,10 +137,11 @@ __global__ void __launch_bounds__(kScanThreads) scan_down(ScanIn si, const uint3
     }
 }
 
-// Visible records -> (view << 32 | depth bits, record index), in index order.
+// Visible records -> (depth bits, record index), in index order.  zbits holds
+// the record's depth bits, written densely by the projection.
 __global__ void __launch_bounds__(256) compact_visible(int64_t N, int64_t VN, const uint32_t *__restrict__ touched,
                                                        const uint32_t *__restrict__ voff,
-                                                       const float4 *__restrict__ rec,
+                                                       const uint32_t *__restrict__ zbits,
                                                        uint32_t *__restrict__ dkey, uint32_t *__restrict__ didx,
                                                        uint32_t *__restrict__ vlist)
 {
@@ -150,7 +151,7 @@ __global__ void __launch_bounds__(256) compact_visible(int64_t N, int64_t VN, co
     // the camera depth is > z_near > 0, so its float bits order as integers;
     // the view needs no key bits (tile ids keep views apart and the tile sort
     // is stable)
-    dkey[r] = __float_as_uint(rec[idx * 4 + 1].w);
+    dkey[r] = zbits[idx];
     didx[r] = (uint32_t)idx;
     vlist[r] = (uint32_t)idx;
 }
@@ -461,14 +462,30 @@ __global__ void __launch_bounds__(kScatThreads) radix_scatter(const K *__restric
     }
 }
 
+// Four sorted keys per thread (one 16-byte load; the neighbours across the
+// group boundary come from the same cache lines as the adjacent threads' loads).
 __global__ void __launch_bounds__(256) tile_ranges(const uint32_t *__restrict__ keys,
                                                    const uint32_t *__restrict__ n_dev, uint2 *__restrict__ ranges)
 {
-    const uint32_t P = *n_dev;
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (uint64_t)gridDim.x * 256) {
-        uint32_t tile = keys[i];
-        if (i == 0 || keys[i - 1] != tile) ranges[tile].x = (uint32_t)i;
-        if (i + 1 == P || keys[i + 1] != tile) ranges[tile].y = (uint32_t)(i + 1);
+    const uint64_t P = *n_dev;
+    for (uint64_t b = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 4; b < P; b += (uint64_t)gridDim.x * 256 * 4) {
+        uint32_t k[6];  // keys b-1 .. b+4 (sentinels beyond the ends)
+        if (b + 4 <= P) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(keys + b);
+            k[1] = q.x, k[2] = q.y, k[3] = q.z, k[4] = q.w;
+        } else {
+            for (int j = 0; j < 4; ++j) k[1 + j] = b + j < P ? keys[b + j] : 0xffffffffu;
+        }
+        k[0] = b > 0 ? keys[b - 1] : 0xffffffffu;
+        k[5] = b + 4 < P ? keys[b + 4] : 0xffffffffu;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t i = b + j;
+            if (i >= P) break;
+            const uint32_t tile = k[1 + j];
+            if (i == 0 || k[j] != tile) ranges[tile].x = (uint32_t)i;
+            if (i + 1 == P || k[2 + j] != tile) ranges[tile].y = (uint32_t)(i + 1);
+        }
     }
 }
 
@@ -553,7 +570,7 @@ hipError_t launch_binsort(const Problem &pb, const WsLayout &L, char *ws, hipStr
     scan(ScanIn{touched, VN, nullptr, 1}, L.nb_scan, part, voff, -1, &cnt->R, nullptr, nullptr, cnt, s);
     if (VN > 0)
         hipLaunchKernelGGL(compact_visible, dim3(vn_blocks), dim3(256), 0, s, L.N, VN, (const uint32_t *)touched,
-                           (const uint32_t *)voff, rec, dk0, di0, (uint32_t *)(ws + L.vlist));
+                           (const uint32_t *)voff, (const uint32_t *)dk1, dk0, di0, (uint32_t *)(ws + L.vlist));
     // 2. sort by depth
     const int dcur = radix_sort<uint32_t>(dk0, di0, dk1, di1, &cnt->R, L.depth_bits, hist, dtot, s);
     uint32_t *didx = dcur ? di1 : di0;

@@ -239,7 +239,8 @@ __global__ void __launch_bounds__(kProjThreads) project_fwd_kernel(ugs_gaussians
                                                                    float4 *__restrict__ rec, uint2 *__restrict__ rect,
                                                                    uint32_t *__restrict__ touched,
                                                                    float4 *__restrict__ grec, int zero_grad,
-                                                                   float *__restrict__ hrec)
+                                                                   float *__restrict__ hrec,
+                                                                   uint32_t *__restrict__ zbits)
 {
     const int64_t N = g.N;
     const int64_t i = (int64_t)blockIdx.x * kProjThreads + threadIdx.x;
@@ -293,6 +294,7 @@ __global__ void __launch_bounds__(kProjThreads) project_fwd_kernel(ugs_gaussians
                 const float4 q1 = make_float4((float)l22, (float)G.o, (float)G.k, (float)S.z);
                 r[0] = q0;
                 r[1] = q1;
+                zbits[idx] = __float_as_uint(q1.w);  // depth key bits for the binning's compaction
                 r[2] = make_float4((float)(S.Qp0x * iA / fx), (float)(S.Qp0y * iA / fy), (float)(S.Q00 * iA / (fx * fx)),
                                    (float)(S.Q01 * iA / (fx * fy)));
                 r[3] = make_float4((float)(S.Q11 * iA / (fy * fy)), col[0], col[1], col[2]);
@@ -590,11 +592,12 @@ hipError_t launch_project_fwd(const ugs_gaussians &g, const Problem &pb, const W
     auto touched = (uint32_t *)(ws + L.touched);
     auto grec = (float4 *)(ws + L.grec);
     auto hrec = pb.depth_mode == 2 ? (float *)(ws + L.hrec) : nullptr;
+    auto zbits = (uint32_t *)(ws + L.dkey1);  // free until the binning's depth sort
     switch (g.sh_deg) {
-    case 0: hipLaunchKernelGGL(project_fwd_kernel<0>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad, hrec); break;
-    case 1: hipLaunchKernelGGL(project_fwd_kernel<1>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad, hrec); break;
-    case 2: hipLaunchKernelGGL(project_fwd_kernel<2>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad, hrec); break;
-    default: hipLaunchKernelGGL(project_fwd_kernel<3>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad, hrec); break;
+    case 0: hipLaunchKernelGGL(project_fwd_kernel<0>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad, hrec, zbits); break;
+    case 1: hipLaunchKernelGGL(project_fwd_kernel<1>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad, hrec, zbits); break;
+    case 2: hipLaunchKernelGGL(project_fwd_kernel<2>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad, hrec, zbits); break;
+    default: hipLaunchKernelGGL(project_fwd_kernel<3>, grid, dim3(kProjThreads), 0, s, g, cams, pb.V, pb.tile_w, pb.tile_h, pb.prune_Tk, rec, rect, touched, grec, (int)zero_grad, hrec, zbits); break;
     }
     return hipGetLastError();
 }
