@@ -154,7 +154,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the rasterizer's multi-GPU form (views sharded "
-              "across GPUs with one gradient all-reduce) is not part of this build.", file=sys.stderr)
+              "across GPUs with one gradient all-reduce) is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
