@@ -14,7 +14,9 @@
  *   - transform into the ellipsoid's local scaled frame and the unit-sphere
  *     quadratic, section 3.2 and supplementary S1.1 (coefficients a, b, c);
  *   - midpoint depth t_mid = -b / 2a and the camera-frame z of C + t_mid d,
- *     Eq. (midpoint), taken for every fragment (hit or miss);
+ *     Eq. (midpoint), taken for every fragment, hit or miss (depth_mode 0);
+ *     depth_mode 1 takes the centre's camera depth, depth_mode 2 the midpoint
+ *     where the quadratic has a real root and the centre depth elsewhere;
  *   - alpha-blended depth, gradient-factor and semantic maps, Eq.
  *     (depth_render), Eq. (t_render), Eq. (semantic_render), Alg. forward_render;
  *   - normals from depth, Alg. normal_estimation with the back-projection and
