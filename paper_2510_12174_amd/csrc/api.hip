@@ -755,6 +755,9 @@ int ugs_autotune(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, i
         o.batch = 0;
         int b = auto_batch(o, g->C_o);
         cands.push_back({t[0], t[1], b});
+        // twice the default batch: fewer barriers, more LDS (at most 64 KB,
+        // since the default fits in 32 KB)
+        if (2 * b <= 1024) cands.push_back({t[0], t[1], 2 * b});
         if (b / 2 >= 16) cands.push_back({t[0], t[1], b / 2});
         if (b / 4 >= 16) cands.push_back({t[0], t[1], b / 4});
     }
