@@ -100,14 +100,17 @@ __device__ __forceinline__ void ld_label(const int32_t *p, int (&l)[NP])
     }
 }
 
-// Online softmax over the channels of NP pixels: the log-sum-exp of each.
+// Online softmax over the channels of NP pixels: the log-sum-exp of each, and
+// the logit of each pixel's label channel picked on the way (0 when the label
+// is out of range), so that no second read of that channel is needed.
 template <int NP>
-__device__ __forceinline__ Px<NP> logsumexp(const float *o, int64_t HW, int C)
+__device__ __forceinline__ Px<NP> logsumexp(const float *o, int64_t HW, int C, const int (&lab)[NP],
+                                            float (&picked)[NP])
 {
     constexpr int U = NP == 4 ? 4 : 8;  // channels in flight
     float m[NP], s[NP];
 #pragma unroll
-    for (int i = 0; i < NP; ++i) m[i] = -INFINITY, s[i] = 0.f;
+    for (int i = 0; i < NP; ++i) m[i] = -INFINITY, s[i] = 0.f, picked[i] = 0.f;
     int c = 0;
     for (; c + U <= C; c += U) {
         Px<NP> x[U];
@@ -115,6 +118,8 @@ __device__ __forceinline__ Px<NP> logsumexp(const float *o, int64_t HW, int C)
         for (int j = 0; j < U; ++j) x[j] = ld<NP>(o + (int64_t)(c + j) * HW);
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
+#pragma unroll
+            for (int j = 0; j < U; ++j) picked[i] = c + j == lab[i] ? x[j].v[i] : picked[i];
             float mb = x[0].v[i];
 #pragma unroll
             for (int j = 1; j < U; ++j) mb = fmaxf(mb, x[j].v[i]);
@@ -130,6 +135,7 @@ __device__ __forceinline__ Px<NP> logsumexp(const float *o, int64_t HW, int C)
         const Px<NP> x = ld<NP>(o + (int64_t)c * HW);
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
+            picked[i] = c == lab[i] ? x.v[i] : picked[i];
             const float mn = fmaxf(m[i], x.v[i]);
             s[i] = s[i] * __expf(m[i] - mn) + __expf(x.v[i] - mn);
             m[i] = mn;
@@ -173,13 +179,14 @@ __global__ void __launch_bounds__(256) pix_fwd(ViewTable vt, ugs_outputs out, ug
             }
             if (gt.label) {
                 const float *o = out.sem + (int64_t)C_o * off + p;
-                const Px<NP> l = logsumexp<NP>(o, HW, C_o);
-                st<NP>(lse + off + p, l);
                 int lab[NP];
                 ld_label<NP>(gt.label + off + p, lab);
+                float picked[NP];
+                const Px<NP> l = logsumexp<NP>(o, HW, C_o, lab, picked);
+                st<NP>(lse + off + p, l);
 #pragma unroll
                 for (int i = 0; i < NP; ++i)
-                    if (lab[i] >= 0 && lab[i] < C_o) a[3] += (double)(l.v[i] - o[(int64_t)lab[i] * HW + i]);
+                    if (lab[i] >= 0 && lab[i] < C_o) a[3] += (double)(l.v[i] - picked[i]);
             }
             const Px<NP> k = ld<NP>(out.kmap + off + p);
 #pragma unroll
