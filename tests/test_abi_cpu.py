@@ -174,3 +174,36 @@ def test_loss_rejections(U):
     gt.rgb = 256
     out.kmap = 258
     assert ok() == U.UGS_ERR_INVALID_ARG                  # misaligned map
+
+
+def test_plain_c_program_links_the_abi(U, tmp_path):
+    """The header is plain C99 and a C program links the library and calls its
+    host-side entry points (defaults, status strings, argument rejection)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include "unigs.h"
+int main(void) {
+    ugs_options o;
+    ugs_default_options(&o);
+    ugs_loss_options lo;
+    ugs_default_loss_options(&lo);
+    size_t nb = 0;
+    int bad = ugs_prune_scratch_size(-1, &nb);
+    printf("%d %d %d %.2f %d %s\n", o.tile_w, o.tile_h, o.depth_mode, lo.lambda[1], bad,
+           ugs_status_string(UGS_ERR_CAPACITY));
+    return 0;
+}
+''')
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(U.LIB)
+    subprocess.check_call([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                           "-o", str(exe), "-L", libdir, "-lunigs", "-Wl,-rpath," + libdir])
+    out = subprocess.check_output([str(exe)], text=True).split()
+    assert out[:5] == ["16", "16", "0", "0.10", str(U.UGS_ERR_INVALID_ARG)]
+    assert "capacity" in " ".join(out[5:]).lower()
