@@ -416,6 +416,34 @@ def test_autotune_and_cache(tmp_path):
         assert np.abs(a["sem"] - b["sem"]).max() <= 1e-5
 
 
+def test_maximum_view_count(O):
+    """UGS_MAX_VIEWS (64) ragged views in one batched forward+backward, against
+    the oracle view by view, and 65 views refused."""
+    from paper_2510_12174_amd import unigs as U
+    g, cams16, opts = Hn.scenes.make_scene(4, N=4000)
+    cams = []
+    for v in range(U.UGS_MAX_VIEWS):
+        c = dict(cams16[v % 16])
+        W, H = 24 + (v * 7) % 37, 18 + (v * 5) % 23
+        s = W / c["W"]
+        c.update(W=W, H=H, fx=c["fx"] * s, fy=c["fy"] * s, cx=W / 2.0, cy=H / 2.0)
+        cams.append(c)
+    ups = Hn.scenes.upstream(cams, g["C_o"], seed=11)
+    ora = Hn.oracle_forward(O, g, cams, opts)
+    ms = Hn.masks(O, g, cams, opts, ora)
+    ups = Hn.masked_upstream(ups, ms)
+    outs, grads, _ = Hn.gpu_run(g, cams, opts, ups=ups)
+    err = Hn.image_errors(outs, ora, ms, normals=False)
+    Hn.say(f"[64 views] image max-abs {err}")
+    assert all(e <= Hn.IMG_TOL for e in err.values()), err
+    ref, _ = O.backward_all(g, cams, ups, ora, opts)
+    gerr = Hn.grad_errors(grads, ref, Hn.gauss_exclusions(O, g, cams, opts))
+    Hn.say(f"[64 views] grad err/tol {gerr}")
+    assert all(e <= 1.0 for e in gerr.values()), gerr
+    with pytest.raises(U.UgsError):
+        Hn.gpu_run(g, cams + cams[:1], opts)
+
+
 def test_autograd_function_matches_oracle(O):
     import torch
     from paper_2510_12174_amd import unigs as U
