@@ -91,6 +91,20 @@ def traffic_for(name, workload, launches_per_step):
     return d.get("bytes_per_launch")
 
 
+def valu_fraction_for(name, workload):
+    """VALU issue fraction of the kernel (SQ_INSTS_VALU x 4 cycles over the
+    SIMD cycles) from the committed counter summary, if taken on the current
+    kernel source (null otherwise)."""
+    p = os.path.join(ROOT, "profiles", "valu.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p)).get(f"{name}@w{workload}")
+    if not d or d.get("source_sha") != source_sha(name):
+        return None
+    v = d.get("valu_issue_fraction")
+    return None if v is None else round(v, 4)
+
+
 def cpu_baseline(g, cams, opts, budget_s=15.0):
     """FP64 oracle (forward + normals + backward) on a bounded sample of the
     workload: whole views in order, then a band of central rows of the next
@@ -417,7 +431,8 @@ def main():
         achieved = b_alg / (k_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM / 1e9, unit="GB/s",
                     frac=round(achieved * 1e9 / PEAK_HBM, 4))
-    roof.update(kernel=dominant, ms=round(k_ms, 4), traffic=traffic_for(dominant, wl, 1))
+    roof.update(kernel=dominant, ms=round(k_ms, 4), traffic=traffic_for(dominant, wl, 1),
+                valu_issue=valu_fraction_for(dominant, wl))
 
     res = dict(metric=METRIC, value=round(Px / t_batched / 1e6, 2), unit="MP/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(t_batched * 1e3, 3), higher_is_better=True, scaling="weak",

@@ -5,6 +5,7 @@ WRITE_SIZE counter runs scaled by a plain copy kernel of known size).
   python -m paper_2510_12174_amd.profsum stats <kernel_stats.csv> <command>
   python -m paper_2510_12174_amd.profsum traffic <fetch counter csv> <write counter csv> \
         <kernel substring> <key> <source file> <command>
+  python -m paper_2510_12174_amd.profsum valu <counter csv> <kernel substring> <key> <source file> <command>
 """
 from __future__ import annotations
 
@@ -70,8 +71,37 @@ def traffic(fetch_csv, write_csv, kernel_sub, key, source, command):
     return entry
 
 
+def valu(pmc_csv, kernel_sub, key, source, command, simds=1024, xcds=8):
+    """VALU issue fraction of one kernel from a pass with SQ_INSTS_VALU,
+    SQ_INSTS_MFMA and GRBM_GUI_ACTIVE: a wave64 VALU instruction occupies a
+    16-lane SIMD for 4 cycles, GRBM_GUI_ACTIVE is summed over the XCDs."""
+    per = {}
+    for r in csv.DictReader(open(pmc_csv)):
+        if kernel_sub not in r["Kernel_Name"]:
+            continue
+        d = per.setdefault(r.get("Dispatch_Id"), {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    fr, mf = [], []
+    for d in per.values():
+        cyc = d.get("GRBM_GUI_ACTIVE", 0.0) / xcds
+        if cyc > 0:
+            fr.append(4.0 * d.get("SQ_INSTS_VALU", 0.0) / (simds * cyc))
+            mf.append(d.get("SQ_INSTS_MFMA", 0.0))
+    fr.sort()
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2510_12174_amd", "csrc", source), "rb").read()).hexdigest()[:16]
+    entry = dict(source_sha=sha, valu_issue_fraction=fr[len(fr) // 2] if fr else None,
+                 mfma_insts=sorted(mf)[len(mf) // 2] if mf else None, dispatches=len(fr), command=command)
+    path = os.path.join(ROOT, "profiles", "valu.json")
+    dd = json.load(open(path)) if os.path.exists(path) else {}
+    dd[key] = entry
+    json.dump(dd, open(path, "w"), indent=1, sort_keys=True)
+    return entry
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         sys.stdout.write(stats(sys.argv[2], sys.argv[3]))
     elif sys.argv[1] == "traffic":
         print(json.dumps(traffic(*sys.argv[2:8]), indent=1))
+    elif sys.argv[1] == "valu":
+        print(json.dumps(valu(*sys.argv[2:7]), indent=1))
