@@ -100,6 +100,13 @@ __device__ __forceinline__ float reduce_scatter(const float (&x)[NV])
     return z[0];
 }
 
+// exp(-(t1^2 + t2^2) / 2) as one multiply and the hardware 2^x: the constant
+// -log2(e) / 2 is folded, so forward and backward evaluate the same expression.
+__device__ __forceinline__ float gauss_of(float t1, float t2)
+{
+    return __builtin_amdgcn_exp2f((t1 * t1 + t2 * t2) * -0.72134752044448170f);
+}
+
 // 1/x: hardware reciprocal (1 ulp) refined by one Newton step.
 __device__ __forceinline__ float rcp_nr(float x)
 {
@@ -281,8 +288,7 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
                 const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
                 const float dx = fx - r0.x, dy = fy - r0.y;
                 const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
-                const float power = -0.5f * (t1 * t1 + t2 * t2);
-                const float alpha = fminf(kAlphaMax, r1.y * __expf(power));
+                const float alpha = fminf(kAlphaMax, r1.y * gauss_of(t1, t2));
                 ++n_eval;
                 if (alpha < kAlphaMin) continue;
                 const double tT = T * (1.0 - (double)alpha);
@@ -447,8 +453,7 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
             const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
             const float dx = fx - r0.x, dy = fy - r0.y;
             const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
-            const float power = -0.5f * (t1 * t1 + t2 * t2);
-            const float G = __expf(power);
+            const float G = gauss_of(t1, t2);
             const float oG = r1.y * G;
             const float alpha = fminf(kAlphaMax, oG);
             const bool contrib = entry < last && alpha >= kAlphaMin;
@@ -657,8 +662,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
                     const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
                     const float dx = fx - r0.x, dy = fy - r0.y;
                     const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
-                    const float power = -0.5f * (t1 * t1 + t2 * t2);
-                    const float G = __expf(power);
+                    const float G = gauss_of(t1, t2);
                     const float oG = r1.y * G;
                     const float alpha = fminf(kAlphaMax, oG);
                     const bool contrib = entry < last && alpha >= kAlphaMin;
@@ -818,8 +822,7 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
                     const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
                     const float dx = fx - r0.x, dy = fy - r0.y;
                     const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
-                    const float power = -0.5f * (t1 * t1 + t2 * t2);
-                    const float alpha = fminf(kAlphaMax, r1.y * __expf(power));
+                    const float alpha = fminf(kAlphaMax, r1.y * gauss_of(t1, t2));
                     ++n_eval;
                     if (alpha >= kAlphaMin) {
                         const double tT = T * (1.0 - (double)alpha);
