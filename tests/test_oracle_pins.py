@@ -188,6 +188,26 @@ def test_normals_of_a_plane(oracle_mod, lam, steps):
     assert np.abs(N - want[:, None]).max() < 1e-10
 
 
+def test_normal_fusion_weight_selects_one_step(oracle_mod):
+    """n_fused = lambda n1 + (1 - lambda) n2: with lambda = 1 the normal cannot
+    depend on STEP_2, with lambda = 0 not on STEP_1 (a curved depth map, away
+    from the border where the larger stencil leaves the image)."""
+    O = oracle_mod
+    cam = _orthonormal(scenes.look_at([0.3, -2.0, 0.8], [0.0, 0.2, 0.0], 40, 30, 35.0))
+    v, u = np.mgrid[0:30, 0:40].astype(np.float64)
+    D = 2.0 + 0.3 * np.sin(u / 5.0) * np.cos(v / 7.0) + 0.01 * u
+    b = 4
+    for lam, a, c in ((1.0, dict(step1=1, step2=2), dict(step1=1, step2=3)),
+                      (0.0, dict(step1=1, step2=2), dict(step1=2, step2=2))):
+        n_a = O.normals(D, cam, dict(a, lambda_=lam))["normal"][:, b:-b, b:-b]
+        n_c = O.normals(D, cam, dict(c, lambda_=lam))["normal"][:, b:-b, b:-b]
+        assert np.abs(n_a - n_c).max() < 1e-12, lam
+    # and the two steps do differ on this surface
+    n_1 = O.normals(D, cam, dict(step1=1, step2=2, lambda_=1.0))["normal"][:, b:-b, b:-b]
+    n_2 = O.normals(D, cam, dict(step1=1, step2=2, lambda_=0.0))["normal"][:, b:-b, b:-b]
+    assert np.abs(n_1 - n_2).max() > 1e-4
+
+
 def test_normal_of_constant_depth_faces_camera(oracle_mod):
     O = oracle_mod
     cam = _orthonormal(scenes.look_at([1.0, 2.0, -0.5], [0.0, 0.0, 0.3], 24, 20, 30.0))
