@@ -157,6 +157,40 @@ def test_fused_cosine_seed_matches_map():
     Hn.say("[loss] fused cosine seed equals the explicit normal map")
 
 
+def test_loss_graph_capture_replays():
+    """ugs_loss is asynchronous and allocation-free, so it can be captured in a
+    graph: every replay on new map contents equals an eager call on them (the
+    partial sums are added in a fixed order, so bit for bit)."""
+    import torch
+    from paper_2510_12174_amd import unigs as U
+    sizes = SIZES4
+    cams = cams_of(sizes)
+    C_o = 12
+    outs, gts = synth(7, sizes, C_o)
+    cat = lambda key, lst: torch.from_numpy(np.concatenate([np.asarray(d[key]).reshape(-1) for d in lst])).cuda()
+    out = {k: cat(k, outs) for k in ("rgb", "depth", "kmap", "normal", "sem")}
+    gt = {k: cat(k, gts) for k in ("rgb", "depth", "normal", "label")}
+    cap = U.Loss(cams, C_o)
+    cap(out, gt)  # warm-up outside the capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        cap(out, gt)
+    eager = U.Loss(cams, C_o)
+    for rep in range(3):
+        with torch.no_grad():
+            out["rgb"].copy_(torch.rand_like(out["rgb"]))
+            out["kmap"].mul_(1.01)
+        graph.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(10, device="cuda").sum().item()
+        lv, gv = eager(out, gt)
+        torch.cuda.synchronize()
+        assert torch.equal(cap.losses, lv), rep
+        for k in ("rgb", "depth", "kmap", "normal", "sem"):
+            assert torch.equal(cap.grad[k], gv[k]), (rep, k)
+
+
 def test_loss_full_resolution_views():
     """Two views at the batched workload's 1200x680 and 1296x968 resolutions,
     32 channels, launched as in the benchmark (one launch per view and pass)."""
