@@ -444,6 +444,28 @@ def test_maximum_view_count(O):
         Hn.gpu_run(g, cams + cams[:1], opts)
 
 
+@pytest.mark.parametrize("kind,batch", [("w4s", 24), ("w3s", 10), ("w1", 200)])
+def test_odd_batch_sizes(O, kind, batch):
+    """User-chosen LDS batch sizes that are not multiples of the matrix-core
+    group (rounded up there) or exceed the tile's pixel count: forward outputs
+    equal the default batch's (the semantic map to rounding), gradients agree
+    to float-atomic reordering."""
+    g, cams, opts = Hn.small_workload(kind)
+    ups = Hn.scenes.upstream(cams, g["C_o"], seed=5)
+    a, ga, _ = Hn.gpu_run(g, cams, opts, ups=ups)
+    b, gb, _ = Hn.gpu_run(g, cams, opts, ups=ups, batch=batch)
+    for x, y in zip(a, b):
+        for k in ("rgb", "depth", "kmap", "normal", "T_final", "n_contrib"):
+            assert np.array_equal(x[k], y[k]), k
+        if x["sem"].size:
+            assert np.abs(x["sem"] - y["sem"]).max() <= 1e-5
+    for k in Hn.PARAMS:
+        u, w = ga[k], gb[k]
+        if u.size:
+            rms = np.sqrt(np.mean(u * u)) + 1e-30
+            assert np.abs(u - w).max() <= 1e-4 * rms, k
+
+
 def test_autograd_function_matches_oracle(O):
     import torch
     from paper_2510_12174_amd import unigs as U
