@@ -12,8 +12,10 @@
  *
  * Conventions shared by every entry point
  *  - All tensor pointers are DEVICE pointers owned by the caller, FP32 unless
- *    stated, contiguous, at least 16-byte aligned.  Struct arguments and camera
- *    arrays are HOST memory, read during the call only.
+ *    stated, contiguous, 4-byte aligned (binary16 maps 2-byte; misaligned
+ *    pointers are rejected); 16-byte alignment lets some kernels use vector
+ *    loads.  Struct arguments and camera arrays are HOST memory, read during
+ *    the call only.
  *  - Layouts are planar.  Gaussian parameters (structure of arrays):
  *      mean [3][N], quat [4][N] as (w,x,y,z) (need not be normalised),
  *      log_scale [3][N], opacity_logit [N], mask_logit [N] (gradient factor
