@@ -389,11 +389,24 @@ def main():
         torch.cuda.synchronize()
         t_l = s0.elapsed_time(s1) / reps * 1e-3
         b_l = (96 + 8 * C_o) * Px  # every input map read once, every gradient map written once
-        loss_res = dict(ms=round(t_l * 1e3, 3), alg_bytes=int(b_l), achieved_gbps=round(b_l / t_l / 1e9, 1),
+        # the same loss with the cosine and cross-entropy seeds left to the
+        # backward (no normal or semantic gradient maps written)
+        lossx = U.Loss(cams, C_o, fuse_normal=True, fuse_seg=True)
+        for _ in range(2):
+            lossx(out, gt)
+        torch.cuda.synchronize()
+        s0.record()
+        for _ in range(reps):
+            lossx(out, gt)
+        s1.record()
+        torch.cuda.synchronize()
+        t_lx = s0.elapsed_time(s1) / reps * 1e-3
+        loss_res = dict(ms=round(t_l * 1e3, 3), fused_seeds_ms=round(t_lx * 1e3, 3), alg_bytes=int(b_l),
+                        achieved_gbps=round(b_l / t_l / 1e9, 1),
                         peak_gbps=PEAK_HBM / 1e9, frac=round(b_l / t_l / PEAK_HBM, 4),
                         values=dict(zip(U.LOSS_NAMES, [float(f"{float(x):.6g}") for x in lv.cpu()])))
         log(f"[bench] loss {loss_res}")
-        del gt, lossf
+        del gt, lossf, lossx
 
     # quick parity spot check of the timed batched outputs (view 0, sampled pixels)
     parity = None

@@ -101,10 +101,18 @@ typedef struct {
  * (*normal_scale) * normal_target (the seed -N_target / |Omega| of
  * Eq. gradientn, with the loss weight folded into the device scalar
  * `normal_scale`, e.g. the coefficient ugs_loss writes at losses[10]); both
- * pointers are device memory, normal_target laid out like the normal map. */
+ * pointers are device memory, normal_target laid out like the normal map.
+ * Fused cross-entropy seed: when `sem` is NULL and `sem_label` is set
+ * ([H][W] int32 per view), Alg. backward_render forms the semantic upstream
+ * itself from the rendered logits of `out` as (*sem_scale) *
+ * (softmax(O~) - onehot(label)) per pixel (0 for a label outside [0, C_o)),
+ * e.g. with the coefficient ugs_loss writes at losses[12]; the semantic
+ * gradient map is then never stored. */
 typedef struct {
     const float *rgb, *depth, *kmap, *normal, *sem;
     const float *normal_target, *normal_scale;
+    const int32_t *sem_label;
+    const float *sem_scale;
 } ugs_upstream;
 
 /* Options.  Zero-initialise and call ugs_default_options() to get the defaults. */
@@ -321,8 +329,8 @@ int ugs_loss_scratch_size(const ugs_camera *cams, int V, size_t *bytes);
  * caller-owned device maps of `grad` (same layouts as ugs_outputs; rgb, kmap
  * always written, depth/normal/sem written when non-NULL, as zero when their
  * term is absent; the pointers are written through despite the const of
- * ugs_upstream; a NULL grad->normal leaves the normal seed to the fused form of
- * ugs_upstream).  `losses` is device memory for UGS_LOSS_VALUES floats: L_l1,
+ * ugs_upstream; a NULL grad->normal or grad->sem leaves that seed to the fused
+ * forms of ugs_upstream).  `losses` is device memory for UGS_LOSS_VALUES floats: L_l1,
  * L_ssim, L_normal, L_depth, L_seg, L_K, L_all and the SSIM mean, then the six
  * per-term gradient coefficients (d L_all / d map element of the l1, ssim,
  * normal, depth, seg and K terms; losses[10] is the fused normal seed's scale).  `scratch` (256-byte aligned,

@@ -415,6 +415,7 @@ int check_bwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs 
     if ((rc = check_outputs(out, g->C_o, true, false))) return rc;
     if ((rc = check_grads(dg, g->C_o))) return rc;
     if (!up || (!up->normal && up->normal_target && !up->normal_scale)) return UGS_ERR_INVALID_ARG;
+    if (!up->sem && up->sem_label && (!up->sem_scale || g->C_o < 1 || !out->sem)) return UGS_ERR_INVALID_ARG;
     return UGS_OK;
 }
 

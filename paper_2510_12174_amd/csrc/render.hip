@@ -114,6 +114,32 @@ __device__ __forceinline__ float rcp_nr(float x)
     return fmaf(r, fmaf(-x, r, 1.f), r);
 }
 
+// Fused cross-entropy seed: with no upstream semantic map, the backward forms
+// dL/dO~ = scale (softmax(O~) - onehot(label)) per pixel from the rendered
+// logits (a label outside [0, C_o) gives 0).
+struct SemSeed {
+    const float *logits;   // rendered O~, layout of ugs_outputs.sem
+    const int32_t *label;  // [H][W] per view, NULL: no fused seed
+    const float *scale;    // device scalar
+};
+
+// Log-sum-exp over the C_o channels of one pixel (stride HW), the label and
+// the seed's scale for that pixel (0 for an out-of-range label).
+__device__ __forceinline__ void seed_pixel(const SemSeed &sd, int C_o, int64_t off, int64_t HW, int64_t p,
+                                           float &lse, int &lab, float &sc)
+{
+    const float *o = sd.logits + (int64_t)C_o * off + p;
+    float m = -INFINITY, s = 0.f;
+    for (int c = 0; c < C_o; ++c) {
+        const float x = o[(int64_t)c * HW], mn = fmaxf(m, x);
+        s = s * __expf(m - mn) + __expf(x - mn);
+        m = mn;
+    }
+    lse = m + __logf(s);
+    lab = sd.label[off + p];
+    sc = (lab >= 0 && lab < C_o) ? *sd.scale : 0.f;
+}
+
 // One reverse step of Alg. backward_render for one pixel and one list entry.
 // Restores T (T <- T / (1 - alpha)), advances the running sum A of w_j s_j
 // over the later fragments, and fills v[0..15] with this pixel's share of the
@@ -386,7 +412,8 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
     const float *__restrict__ T_final, const uint32_t *__restrict__ n_contrib, const float *__restrict__ up_rgb,
     const float *__restrict__ gD_img, const float *__restrict__ up_kmap, const float *__restrict__ up_sem,
-    float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, int depth_mode, const float *__restrict__ hrec)
+    float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, int depth_mode, const float *__restrict__ hrec,
+    SemSeed seed)
 {
     constexpr int NT = TW * TH;
     constexpr int CA = CO > 0 ? CO : 1;
@@ -425,6 +452,14 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
 #pragma unroll
                 for (int c = 0; c < CO; ++c)
                     if (c < C_o) gO[c] = up_sem[(int64_t)C_o * off + c * HW + p];
+            } else if (seed.label) {
+                float lse, sc;
+                int lab;
+                seed_pixel(seed, C_o, off, HW, p, lse, lab, sc);
+#pragma unroll
+                for (int c = 0; c < CO; ++c)
+                    if (c < C_o)
+                        gO[c] = sc * (__expf(seed.logits[(int64_t)C_o * off + c * HW + p] - lse) - (c == lab ? 1.f : 0.f));
             }
         }
     }
@@ -534,7 +569,8 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o,
     const float *__restrict__ T_final, const uint32_t *__restrict__ n_contrib, const float *__restrict__ up_rgb,
     const float *__restrict__ gD_img, const float *__restrict__ up_kmap, const float *__restrict__ up_sem,
-    float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, int depth_mode, const float *__restrict__ hrec)
+    float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, int depth_mode, const float *__restrict__ hrec,
+    SemSeed seed)
 {
     static_assert(CO == 16 || CO == 32, "MFMA backward: C_o padded to 16 or 32");
     constexpr int NT = TW * TH;
@@ -562,8 +598,21 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
     // G[32 kk + 8 h16 + e][16 cb + l16] (dO product, pixel = reduction index)
     const int W = cams[ti.v].W, H = cams[ti.v].H;
     const int qx0 = ti.px - (lane & 7), qy0 = ti.py - (lane >> 3);
+    // fused seed: each lane's own pixel's log-sum-exp, label and scale, read by
+    // the lanes that stage that pixel's values
+    const bool fused = !up_sem && seed.label;
+    float my_lse = 0.f, my_sc = 0.f;
+    int my_lab = -1;
+    if (fused && ti.inside) seed_pixel(seed, C_o, ti.off, ti.HW, ti.pix, my_lse, my_lab, my_sc);
     auto up_at = [&](int p, int c) -> float {
         const int x = qx0 + (p & 7), y = qy0 + (p >> 3);
+        if (fused) {
+            const float l = __shfl(my_lse, p, 64), sc = __shfl(my_sc, p, 64);
+            const int lb = __shfl(my_lab, p, 64);
+            if (c >= C_o || x >= W || y >= H) return 0.f;
+            const float o = seed.logits[(int64_t)C_o * ti.off + (int64_t)c * ti.HW + (int64_t)y * W + x];
+            return sc * (__expf(o - l) - (c == lb ? 1.f : 0.f));
+        }
         if (!up_sem || c >= C_o || x >= W || y >= H) return 0.f;
         return up_sem[(int64_t)C_o * ti.off + (int64_t)c * ti.HW + (int64_t)y * W + x];
     };
@@ -962,6 +1011,7 @@ hipError_t bwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
     auto grec = (float *)(ws + L.grec);
     auto gd = (const float *)(ws + L.gd);
     auto hrec = (const float *)(ws + L.hrec);
+    const SemSeed seed{out.sem, up.sem ? nullptr : up.sem_label, up.sem_scale};
     if constexpr (CO == 16 || CO == 32) {
         // whole MFMA groups per batch, at most 64 KB of LDS per workgroup
         constexpr int NW = TW * TH / 64;
@@ -971,14 +1021,14 @@ hipError_t bwd_dispatch(const ugs_gaussians &g, const Problem &pb, const WsLayou
                  : pb.depth_mode == 1 ? render_bwd_mfma_kernel<TW, TH, CO, 1> : render_bwd_mfma_kernel<TW, TH, CO, 0>;
         hipLaunchKernelGGL(k, dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), bwd_mfma_lds(b, NW), s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o,
                            out.T_final, out.n_contrib, up.rgb, gd, up.kmap, up.sem, grec, dg.sem, b,
-                           (uint32_t)pb.total_tiles, pb.depth_mode, hrec);
+                           (uint32_t)pb.total_tiles, pb.depth_mode, hrec, seed);
     } else {
         size_t lds = (size_t)batch * (64 + 4 * CO + 4);
         auto k = pb.depth_mode == 2 ? render_bwd_kernel<TW, TH, CO, 2>
                  : pb.depth_mode == 1 ? render_bwd_kernel<TW, TH, CO, 1> : render_bwd_kernel<TW, TH, CO, 0>;
         hipLaunchKernelGGL(k, dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), lds, s,
                            cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, out.T_final, out.n_contrib, up.rgb, gd,
-                           up.kmap, up.sem, grec, dg.sem, batch, (uint32_t)pb.total_tiles, pb.depth_mode, hrec);
+                           up.kmap, up.sem, grec, dg.sem, batch, (uint32_t)pb.total_tiles, pb.depth_mode, hrec, seed);
     }
     return hipGetLastError();
 }

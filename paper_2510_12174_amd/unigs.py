@@ -63,7 +63,8 @@ class ugs_outputs(C.Structure):
 
 
 class ugs_upstream(C.Structure):
-    _fields_ = [(k, C.c_void_p) for k in ("rgb", "depth", "kmap", "normal", "sem", "normal_target", "normal_scale")]
+    _fields_ = [(k, C.c_void_p) for k in ("rgb", "depth", "kmap", "normal", "sem", "normal_target", "normal_scale",
+                                          "sem_label", "sem_scale")]
 
 
 class ugs_options(C.Structure):
@@ -205,7 +206,7 @@ def make_outputs(o):
 
 def make_upstream(u):
     s = ugs_upstream()
-    for k in ("rgb", "depth", "kmap", "normal", "sem", "normal_target", "normal_scale"):
+    for k in ("rgb", "depth", "kmap", "normal", "sem", "normal_target", "normal_scale", "sem_label", "sem_scale"):
         t = u.get(k) if u else None
         setattr(s, k, t.data_ptr() if t is not None and t.numel() > 0 else None)
     return s
@@ -308,7 +309,7 @@ class Loss:
     scratch buffer, the 8-float loss vector and the gradient maps, which are
     the upstream of Rasterizer.backward."""
 
-    def __init__(self, cams, C_o, lambdas=None, balance=True, device="cuda", fuse_normal=False):
+    def __init__(self, cams, C_o, lambdas=None, balance=True, device="cuda", fuse_normal=False, fuse_seg=False):
         import torch
         self.cams_c = make_cameras(cams)
         self.V, self.C_o = len(cams), int(C_o)
@@ -321,9 +322,11 @@ class Loss:
         f = lambda n: torch.empty(n, dtype=torch.float32, device=device)
         # fuse_normal: no normal gradient map; the backward forms the cosine seed
         # itself from the target normals and the coefficient in losses[10]
-        self.fuse_normal = bool(fuse_normal)
+        # fuse_seg: no semantic gradient map; the backward forms the
+        # cross-entropy seed from the rendered logits, the labels and losses[12]
+        self.fuse_normal, self.fuse_seg = bool(fuse_normal), bool(fuse_seg)
         self.grad = dict(rgb=f(3 * P), depth=f(P), kmap=f(P), normal=None if fuse_normal else f(3 * P),
-                         sem=f(max(self.C_o, 0) * P))
+                         sem=None if fuse_seg else f(max(self.C_o, 0) * P))
         self.opts = loss_options(lambdas, balance)
 
     def __call__(self, out, gt):
@@ -336,10 +339,12 @@ class Loss:
         o, u = make_outputs(out), make_upstream(self.grad)
         _chk(lib().ugs_loss(self.cams_c, self.V, self.C_o, C.byref(o), C.byref(t), C.byref(self.opts), C.byref(u),
                             _ptr(self.losses), _ptr(self.scratch), self.nb, _stream()), "ugs_loss")
-        if self.fuse_normal:
+        if self.fuse_normal or self.fuse_seg:
             up = dict(self.grad)
-            if gt.get("normal") is not None:
+            if self.fuse_normal and gt.get("normal") is not None:
                 up.update(normal_target=gt["normal"], normal_scale=self.losses[10:11])
+            if self.fuse_seg and gt.get("label") is not None:
+                up.update(sem_label=gt["label"], sem_scale=self.losses[12:13])
             return self.losses, up
         return self.losses, self.grad
 

@@ -157,6 +157,40 @@ def test_fused_cosine_seed_matches_map():
     Hn.say("[loss] fused cosine seed equals the explicit normal map")
 
 
+def test_fused_cross_entropy_seed_matches_map():
+    """The cross-entropy seed formed inside the render backward from the
+    rendered logits, the labels and losses[12] gives the parameter gradients of
+    the loss's explicit semantic-gradient map (to the rounding of the two
+    log-sum-exp evaluations and float-atomic order); both forward kernels'
+    backward forms run (32 channels on the matrix cores, 64 on the vector
+    path)."""
+    import torch
+    from paper_2510_12174_amd import unigs as U
+    for kind in ("w4s", "w3s"):
+        g, cams, opts = Hn.small_workload(kind)
+        C_o = int(g["C_o"])
+        gd = U.to_device(g)
+        rast = U.Rasterizer()
+        out = rast.forward(gd, cams)
+        _, gts = synth(6, [(c["W"], c["H"]) for c in cams], C_o)
+        cat = lambda key: torch.from_numpy(np.concatenate([np.asarray(d[key]).reshape(-1) for d in gts])).cuda()
+        gt = {k: cat(k) for k in ("rgb", "depth", "normal", "label")}
+        _, up_map = U.Loss(cams, C_o)(out, gt)
+        lf, up_fused = U.Loss(cams, C_o, fuse_normal=True, fuse_seg=True)(out, gt)
+        assert up_fused["sem"] is None and up_fused["normal"] is None
+        a = rast.backward(gd, out, up_map)
+        rast.forward(gd, cams, out)  # one backward per projection
+        b = rast.backward(gd, out, up_fused)
+        torch.cuda.synchronize()
+        for k in U.PARAM_KEYS:
+            x, y = a[k].cpu().numpy().astype(np.float64), b[k].cpu().numpy().astype(np.float64)
+            if x.size:
+                rms = np.sqrt(np.mean(x * x)) + 1e-30
+                err = np.max(np.abs(x - y)) / rms
+                Hn.say(f"[loss {kind}] fused seeds vs maps, {k}: max err / rms {err:.2e}")
+                assert err <= 1e-4, k
+
+
 def test_loss_graph_capture_replays():
     """ugs_loss is asynchronous and allocation-free, so it can be captured in a
     graph: every replay on new map contents equals an eager call on them (the
