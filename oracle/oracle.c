@@ -18,7 +18,11 @@
  *     depth_mode 1 takes the centre's camera depth, depth_mode 2 the midpoint
  *     where the quadratic has a real root and the centre depth elsewhere;
  *   - alpha-blended depth, gradient-factor and semantic maps, Eq.
- *     (depth_render), Eq. (t_render), Eq. (semantic_render), Alg. forward_render;
+ *     (depth_render), Eq. (t_render), Eq. (semantic_render), Alg. forward_render,
+ *     front to back in the order of the per-Gaussian sort key of the tile-based
+ *     rasterizer (section 3.4): the camera depth of the centre, computed in FP64
+ *     from the FP32 inputs and rounded to FP32 (the depth key of 3DGS's
+ *     (tile, depth) sort), ties going to the lower Gaussian index;
  *   - normals from depth, Alg. normal_estimation with the back-projection and
  *     view-facing flip of supplementary S1.3.
  * The splatting part the paper inherits from 3DGS (EWA projection with a
@@ -108,6 +112,8 @@ typedef struct {
     double Y[16], dY[16][3];
     double raw[3], rgb[3];
     double z;
+    float zkey;     /* the sort key: the camera depth rounded to FP32 */
+    double zmargin; /* margin of that rounding (common 1e-5 scale) */
     double rx, ry; /* pixel half-widths of the alpha >= 1/255 region */
 } proj_t;
 
@@ -229,6 +235,28 @@ static void project_one(const orc_gs *g, const orc_cam *cam, const orc_opt *opt,
     P->k = sigm(g->mask_logit[i]);
     for (int a = 0; a < 3; ++a) P->mc[a] = R[3 * a] * mu[0] + R[3 * a + 1] * mu[1] + R[3 * a + 2] * mu[2] + cam->t[a];
     P->z = P->mc[2];
+    P->zkey = (float)P->z;
+    {
+        /* The FP32 key is the rounding of mu_c.z = R_3 . mu + t_z.  With FP32
+         * inputs the three products are exact in FP64, so the only rounding is
+         * in the additions: when the left-to-right sum is exact (every TwoSum
+         * residual zero) the key is the rounding of the exact depth and nothing
+         * is ambiguous; otherwise the key is ambiguous only if z lies within the
+         * summation error bound (4 eps sum |terms|) of a midpoint between two
+         * FP32 values.  The distance is mapped onto the common 1e-5 margin scale. */
+        double terms[4] = {R[6] * mu[0], R[7] * mu[1], R[8] * mu[2], cam->t[2]};
+        double s = terms[0], resid = 0.0, mag = fabs(terms[0]);
+        for (int k = 1; k < 4; ++k) {
+            double t = s + terms[k], bb = t - s;
+            resid += fabs((s - (t - bb)) + (terms[k] - bb));
+            s = t;
+            mag += fabs(terms[k]);
+        }
+        double up = (double)nextafterf(P->zkey, INFINITY), dn = (double)nextafterf(P->zkey, -INFINITY);
+        double dm = fmin(fabs(P->z - 0.5 * ((double)P->zkey + up)), fabs(P->z - 0.5 * ((double)P->zkey + dn)));
+        double bound = 4.0 * 1.1102230246251565e-16 * mag;
+        P->zmargin = resid == 0.0 ? INFINITY : 1e-5 * dm / bound;
+    }
     int vis = P->mc[2] > cam->z_near;
     int amb = relmargin(P->mc[2], cam->z_near) < 1e-5;
     if (opt->prune_Tk > 0) {
@@ -296,7 +324,7 @@ static const proj_t *g_sort_P;
 static int cmp_zid(const void *a, const void *b)
 {
     int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
-    double zi = g_sort_P[i].z, zj = g_sort_P[j].z;
+    float zi = g_sort_P[i].zkey, zj = g_sort_P[j].zkey;
     if (zi < zj) return -1;
     if (zi > zj) return 1;
     return (i > j) - (i < j);
@@ -421,14 +449,16 @@ typedef struct {
     double grad_margin; /* alpha clamp */
     double T;
     int n, n_clamped;
+    int64_t term_id; /* the fragment whose alpha would take T below 1e-4, -1 if none */
 } pixinfo_t;
 
 /* Fragments of pixel (u,v) in (depth, id) order that pass alpha >= 1/255, up
  * to (excluding) the first one that would take T below 1e-4. */
 static int pixel_frags(const ctx_t *c, int u, int v, frag_t *F, pixinfo_t *info)
 {
-    double T = 1.0, margin = INFINITY, gmargin = INFINITY, zprev = -1.0;
+    double T = 1.0, margin = INFINITY, gmargin = INFINITY;
     int n = 0, ncl = 0;
+    int64_t term = -1;
     int64_t jb, je;
     const int64_t *items;
     if (c->path == 1) { items = c->row_items; jb = c->row_start[v]; je = c->row_start[v + 1]; }
@@ -445,30 +475,13 @@ static int pixel_frags(const ctx_t *c, int u, int v, frag_t *F, pixinfo_t *info)
         double m1 = relmargin(alpha, ALPHA_MIN);
         if (m1 < margin) margin = m1;
         if (alpha < ALPHA_MIN) continue;
-        if (zprev > 0) {
-            /* depth-order ties: ambiguous below 1e-6 relative (scaled onto the
-             * common 1e-5 margin scale) */
-            double mo = 10.0 * fabs(P->z - zprev) / P->z;
-            if (mo < margin) margin = mo;
-        }
-        zprev = P->z;
+        /* the order of the fragments is exact given the FP32 keys */
+        if (P->zmargin < margin) margin = P->zmargin;
         double tT = T * (1.0 - alpha);
         double m2 = relmargin(tT, T_STOP);
         if (m2 < margin) margin = m2;
         if (tT < T_STOP) {
-            /* the terminating fragment and the next one in depth order could swap
-             * under a rounding of the depth key: compare their depths too */
-            for (int64_t k = j + 1; k < je; ++k) {
-                const proj_t *Q = &c->P[items[k]];
-                if (c->path == 1 && (u < Q->m2[0] - Q->rx - 1.0 || u > Q->m2[0] + Q->rx + 1.0)) continue;
-                double ex = u - Q->m2[0], ey = v - Q->m2[1];
-                double pw = -0.5 * (Q->conic[0] * ex * ex + Q->conic[2] * ey * ey) - Q->conic[1] * ex * ey;
-                double a2 = Q->o * exp(pw);
-                if ((a2 < ALPHA_MAX ? a2 : ALPHA_MAX) < ALPHA_MIN) continue;
-                double mo = 10.0 * fabs(Q->z - P->z) / Q->z;
-                if (mo < margin) margin = mo;
-                break;
-            }
+            term = id;
             break;
         }
         double mc = relmargin(oG, ALPHA_MAX);
@@ -502,6 +515,7 @@ static int pixel_frags(const ctx_t *c, int u, int v, frag_t *F, pixinfo_t *info)
     info->T = T;
     info->n = n;
     info->n_clamped = ncl;
+    info->term_id = term;
     return n;
 }
 
@@ -546,7 +560,7 @@ int orc_project(const orc_gs *g, const orc_cam *cam, const orc_opt *opt,
 int orc_render(const orc_gs *g, const orc_cam *cam, const orc_opt *opt, int path,
                const uint8_t *pixmask, double *rgb, double *depth, double *kmap, double *sem,
                double *T_final, int32_t *last_id, int32_t *n_frag, int32_t *n_clamped,
-               double *margin, double *grad_margin)
+               double *margin, double *grad_margin, int32_t *term_id)
 {
     ctx_t c;
     if (ctx_init(&c, g, cam, opt, path)) { ctx_free(&c); return -1; }
@@ -584,6 +598,7 @@ int orc_render(const orc_gs *g, const orc_cam *cam, const orc_opt *opt, int path
                 n_clamped[pix] = info.n_clamped;
                 margin[pix] = info.margin;
                 grad_margin[pix] = info.grad_margin;
+                if (term_id) term_id[pix] = (int32_t)info.term_id;
             }
         }
         free(F);

@@ -127,17 +127,20 @@ def project(g, cam, opts=None):
 def render(g, cam, opts=None, path=1, pixmask=None):
     """Forward maps of one view: rgb [3][H][W], depth, kmap, sem [C_o][H][W],
     T_final, last_id (id of the last contributor, -1 if none), n_frag,
-    n_clamped, and the per-pixel decision margins."""
+    n_clamped, term_id (id of the fragment at which the walk stops because it
+    would take T below 1e-4, -1 if the walk reaches the end of the list) and
+    the per-pixel decision margins."""
     S = _scene(g)
     H, W = int(cam["H"]), int(cam["W"])
     out = dict(rgb=np.zeros((3, H, W)), depth=np.zeros((H, W)), kmap=np.zeros((H, W)),
                sem=np.zeros((S.C_o, H, W)), T_final=np.ones((H, W)), last_id=np.full((H, W), -1, np.int32),
                n_frag=np.zeros((H, W), np.int32), n_clamped=np.zeros((H, W), np.int32),
-               margin=np.full((H, W), np.inf), grad_margin=np.full((H, W), np.inf))
+               margin=np.full((H, W), np.inf), grad_margin=np.full((H, W), np.inf),
+               term_id=np.full((H, W), -1, np.int32))
     pm = None if pixmask is None else np.ascontiguousarray(pixmask, dtype=np.uint8)
     rc = lib().orc_render(C.byref(S.s), C.byref(_cam(cam)), C.byref(_opt(opts)), int(path), _p(pm),
                           *[_p(out[k]) for k in ("rgb", "depth", "kmap", "sem", "T_final", "last_id",
-                                                 "n_frag", "n_clamped", "margin", "grad_margin")])
+                                                 "n_frag", "n_clamped", "margin", "grad_margin", "term_id")])
     if rc != 0:
         raise RuntimeError(f"orc_render failed ({rc})")
     return out

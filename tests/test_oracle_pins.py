@@ -584,3 +584,203 @@ def test_prune_reference(oracle_mod):
         if T == 0.0:
             assert res["N"] == 5
     assert abs(1.0 / (1.0 + math.exp(-math.log(9.0))) - 0.9) < 1e-15
+
+
+def _pixel_map(cam, X):
+    """World point -> pixel coordinates of a pinhole camera (the projection the
+    splats are drawn with), written directly from x_cam = R x + t."""
+    R = np.asarray(cam["R"], np.float64)
+    t = np.asarray(cam["t"], np.float64)
+    xc = R @ X + t
+    return np.array([cam["fx"] * xc[0] / xc[2] + cam["cx"], cam["fy"] * xc[1] / xc[2] + cam["cy"]])
+
+
+def _fd_jacobian(cam, X, h=1e-6):
+    J = np.zeros((2, 3))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        J[:, k] = (_pixel_map(cam, X + e) - _pixel_map(cam, X - e)) / (2 * h)
+    return J
+
+
+def _offaxis_scene(n, seed, cam):
+    """Gaussians spread over a rotated camera's whole field of view (and beyond
+    it), with random rotations and anisotropic scales."""
+    rng = np.random.default_rng(seed)
+    R = np.asarray(cam["R"], np.float64)
+    t = np.asarray(cam["t"], np.float64)
+    z = rng.uniform(1.5, 4.0, n)
+    # normalised image coordinates up to 2.2x the half field of view, so that
+    # some centres fall outside the 1.3x clamp of the Jacobian
+    tx = rng.uniform(-2.2, 2.2, n) * cam["W"] / (2 * cam["fx"])
+    ty = rng.uniform(-2.2, 2.2, n) * cam["H"] / (2 * cam["fy"])
+    xc = np.stack([tx * z, ty * z, z])
+    mu = np.linalg.solve(R, xc - t[:, None])
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    g = dict(N=n, sh_deg=0, C_o=0, mean=np.ascontiguousarray(mu, np.float32),
+             quat=np.ascontiguousarray(q.T, np.float32),
+             log_scale=np.ascontiguousarray(rng.normal(-2.5, 0.6, (3, n)), np.float32),
+             opacity_logit=np.zeros(n, np.float32), mask_logit=np.full(n, 2.0, np.float32),
+             sh=np.full((1, 3, n), 0.5, np.float32), sem=np.zeros((n, 0), np.float32))
+    return g
+
+
+def test_ewa_footprint_offaxis_rotated_camera(oracle_mod):
+    """EWA footprint of off-axis Gaussians seen by a rotated camera (section 3.4,
+    the 3DGS projection): Sigma_2D = J Sigma J^T + 0.3 I with J an FP64
+    central-difference Jacobian of the world -> pixel map, Sigma from a scipy
+    rotation, and the 2D mean the map itself.  For centres outside 1.3 times
+    the half field of view the Jacobian is taken at the point clamped to that
+    cone (same camera depth), which is the FOV-clamp branch; both branches are
+    populated.  A wrong sign or column of J, or R^T in place of R, fails."""
+    O = oracle_mod
+    cam = scenes.look_at([1.3, -2.1, 0.7], [-0.4, 0.5, -0.2], 160, 120, 150.0)
+    cam["fy"] = 135.0  # distinct focal lengths: a swapped fx/fy fails too
+    g = _offaxis_scene(300, 21, cam)
+    P = O.project(g, cam)
+    R = np.asarray(cam["R"], np.float64)
+    t = np.asarray(cam["t"], np.float64)
+    limx = 1.3 * cam["W"] / (2 * cam["fx"])
+    limy = 1.3 * cam["H"] / (2 * cam["fy"])
+    n_clamped = 0
+    for i in range(g["N"]):
+        mu = g["mean"][:, i].astype(np.float64)
+        xc = R @ mu + t
+        assert P["visible"][i] == 1
+        rx, ry = xc[0] / xc[2], xc[1] / xc[2]
+        clamped = abs(rx) > limx or abs(ry) > limy
+        n_clamped += clamped
+        xcl = np.array([np.clip(rx, -limx, limx) * xc[2], np.clip(ry, -limy, limy) * xc[2], xc[2]])
+        # the FP32-rounded R is not exactly orthogonal: invert it, not transpose
+        J = _fd_jacobian(cam, np.linalg.solve(R, xcl - t))
+        q = g["quat"][:, i].astype(np.float64)
+        Rg = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        s = np.exp(g["log_scale"][:, i].astype(np.float64))
+        S2 = J @ (Rg @ np.diag(s * s) @ Rg.T) @ J.T + 0.3 * np.eye(2)
+        scale = np.abs(S2).max()
+        got = P["cov2d"][i]
+        assert abs(got[0] - S2[0, 0]) < 1e-7 * scale
+        assert abs(got[1] - S2[0, 1]) < 1e-7 * scale
+        assert abs(got[2] - S2[1, 1]) < 1e-7 * scale
+        inv = np.linalg.inv(S2)
+        cs = np.abs(inv).max()
+        assert np.allclose(P["conic"][i], [inv[0, 0], inv[0, 1], inv[1, 1]], rtol=0, atol=1e-6 * cs)
+        m = _pixel_map(cam, mu)
+        assert np.allclose(P["mean2d"][i], m, rtol=0, atol=1e-9 * (1 + np.abs(m).max()))
+    assert 30 < n_clamped < g["N"] - 30
+
+
+def test_offaxis_footprint_renders_its_gaussian(oracle_mod):
+    """One off-axis, rotated Gaussian through a rotated camera: every pixel's
+    alpha equals o exp(-1/2 d^T Sigma_2D^-1 d) with Sigma_2D from the
+    finite-difference Jacobian (alpha cut-off 1/255, clamp 0.99), so the
+    rendered colour and T_final follow in closed form."""
+    O = oracle_mod
+    cam = scenes.look_at([0.9, 2.2, -0.6], [0.1, -0.3, 0.2], 96, 80, 110.0)
+    g = _offaxis_scene(1, 5, cam)
+    g["log_scale"] = np.array([[-1.6], [-2.3], [-1.9]], np.float32)
+    g["opacity_logit"] = np.array([1.2], np.float32)
+    g["sh"] = np.array([0.7, 0.2, 0.4], np.float32).reshape(1, 3, 1)
+    R = np.asarray(cam["R"], np.float64)
+    t = np.asarray(cam["t"], np.float64)
+    # place the centre off-axis but inside the clamp cone
+    z = 2.7
+    g["mean"] = np.ascontiguousarray(np.linalg.solve(R, np.array([0.35 * z, -0.2 * z, z]) - t).reshape(3, 1),
+                                      np.float32)
+    mu = g["mean"][:, 0].astype(np.float64)
+    J = _fd_jacobian(cam, mu)
+    q = g["quat"][:, 0].astype(np.float64)
+    Rg = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    s = np.exp(g["log_scale"][:, 0].astype(np.float64))
+    S2 = J @ (Rg @ np.diag(s * s) @ Rg.T) @ J.T + 0.3 * np.eye(2)
+    inv = np.linalg.inv(S2)
+    m = _pixel_map(cam, mu)
+    u, v = np.meshgrid(np.arange(cam["W"], dtype=np.float64), np.arange(cam["H"], dtype=np.float64))
+    du, dv = u - m[0], v - m[1]
+    o = 1.0 / (1.0 + math.exp(-1.2))
+    alpha = np.minimum(0.99, o * np.exp(-0.5 * (inv[0, 0] * du * du + 2 * inv[0, 1] * du * dv + inv[1, 1] * dv * dv)))
+    alpha = np.where(alpha >= 1 / 255, alpha, 0.0)
+    col = np.maximum(0.0, g["sh"][0, :, 0].astype(np.float64) / (2 * math.sqrt(math.pi)) + 0.5)
+    out = O.render(g, cam, path=0)
+    assert (alpha > 0).sum() > 200
+    assert np.abs(out["T_final"] - (1 - alpha)).max() < 1e-7
+    for c in range(3):
+        assert np.abs(out["rgb"][c] - alpha * col[c]).max() < 1e-7
+
+
+def _stack_scene(zs, opac, dcs):
+    """On-axis, axis-aligned Gaussians at camera depths zs in front of an
+    identity camera; at the central pixel each has alpha = min(0.99, o)."""
+    n = len(zs)
+    g = dict(N=n, sh_deg=0, C_o=2,
+             mean=np.array([[0.0] * n, [0.0] * n, zs], np.float32),
+             quat=np.tile(np.array([[1.0], [0.0], [0.0], [0.0]], np.float32), (1, n)),
+             log_scale=np.full((3, n), np.log(0.2), np.float32),
+             opacity_logit=np.log(np.asarray(opac) / (1 - np.asarray(opac))).astype(np.float32),
+             mask_logit=np.full(n, 3.0, np.float32),
+             sh=np.asarray(dcs, np.float32).T.reshape(1, 3, n),
+             sem=np.stack([np.arange(n, dtype=np.float32), np.ones(n, np.float32)], 1))
+    cam = scenes.camera(33, 33, 40.0, 40.0, 16.0, 16.0, np.eye(3), [0, 0, 0])
+    return g, cam
+
+
+def _composite_centre(g, order):
+    """Front-to-back compositing of the central pixel in a given order, from the
+    closed-form alphas (min(0.99, o)) and colours (Y00 dc + 0.5)."""
+    o = 1.0 / (1.0 + np.exp(-g["opacity_logit"].astype(np.float64)))
+    a = np.minimum(0.99, o)
+    col = np.maximum(0.0, g["sh"][0].astype(np.float64).T / (2 * math.sqrt(math.pi)) + 0.5)
+    T, C, last, n = 1.0, np.zeros(3), -1, 0
+    for i in order:
+        if a[i] < 1 / 255:
+            continue
+        if T * (1 - a[i]) < 1e-4:
+            break
+        C += a[i] * T * col[i]
+        T *= 1 - a[i]
+        last, n = i, n + 1
+    return C, T, last, n
+
+
+def test_occlusion_order_two_and_three_gaussians(oracle_mod):
+    """Front-to-back occlusion (Eq. depth_render, Alg. forward_render): for
+    two overlapping Gaussians C = a1 c1 + (1 - a1) a2 c2 with 1 the nearer;
+    swapping the depths swaps the roles; equal FP32 depths go to the lower
+    index; a three-deep stack with a 0.99-clamped front and a 0.98 second
+    Gaussian leaves T = 2e-4, so the third (alpha 0.9) would take T below
+    1e-4 and neither it nor anything behind contributes."""
+    O = oracle_mod
+    dcs = [[1.2, -0.6, 0.1], [-0.8, 0.9, 0.4], [0.3, 0.3, -0.9], [0.9, 0.9, 0.9]]
+    c = lambda i: np.maximum(0.0, np.asarray(dcs[i], np.float32).astype(np.float64) / (2 * math.sqrt(math.pi)) + 0.5)
+    sig = lambda x: 1.0 / (1.0 + math.exp(-float(np.float32(math.log(x / (1 - x))))))
+    for zs, front in (([2.0, 3.0], 0), ([3.0, 2.0], 1), ([2.5, 2.5], 0)):
+        g, cam = _stack_scene(zs, [0.6, 0.7], dcs[:2])
+        out = O.render(g, cam, path=0)
+        a = [sig(0.6), sig(0.7)]
+        back = 1 - front
+        want = a[front] * c(front) + (1 - a[front]) * a[back] * c(back)
+        assert np.abs(out["rgb"][:, 16, 16] - want).max() < 1e-12
+        assert abs(out["T_final"][16, 16] - (1 - a[0]) * (1 - a[1])) < 1e-12
+        assert out["last_id"][16, 16] == back
+        # the semantic channel 0 carries the Gaussian's index
+        assert abs(out["sem"][0, 16, 16] - (a[front] * front + (1 - a[front]) * a[back] * back)) < 1e-12
+        assert abs(out["depth"][16, 16] - (a[front] * zs[front] + (1 - a[front]) * a[back] * zs[back])) < 1e-12
+    # three-deep stack crossing the termination threshold, plus one behind it
+    g, cam = _stack_scene([3.0, 1.5, 2.0, 4.0], [0.95, 0.999, 0.98, 0.9], dcs)
+    g["opacity_logit"] = np.array([math.log(0.9 / 0.1), 8.0, math.log(0.98 / 0.02), 0.0], np.float32)
+    out = O.render(g, cam, path=0)
+    o = 1.0 / (1.0 + np.exp(-g["opacity_logit"].astype(np.float64)))
+    a1, a2 = 0.99, o[2]  # Gaussian 1 (nearest) clamps at 0.99, then Gaussian 2
+    assert 0.97 < a2 < 0.99 and o[0] > 0.5
+    want = a1 * c(1) + (1 - a1) * a2 * c(2)
+    assert np.abs(out["rgb"][:, 16, 16] - want).max() < 1e-12
+    assert abs(out["T_final"][16, 16] - (1 - a1) * (1 - a2)) < 1e-12
+    assert (1 - a1) * (1 - a2) * (1 - o[0]) < 1e-4 <= (1 - a1) * (1 - a2)
+    assert out["last_id"][16, 16] == 2 and out["n_frag"][16, 16] == 2
+    C, T, last, n = _composite_centre(g, [1, 2, 0, 3])
+    assert np.abs(out["rgb"][:, 16, 16] - C).max() < 1e-12 and last == 2 and n == 2
+    # the reversed order would give a different image: the pin separates them
+    Cr, _, _, _ = _composite_centre(g, [3, 0, 2, 1])
+    assert np.abs(Cr - C).max() > 1e-2
