@@ -50,7 +50,7 @@ extern "C" {
 #define UGS_ERR_NOT_CAPTURED (-5) /* ugs_step_replay without a captured step          */
 #define UGS_ERR_STATE (-6)        /* calls out of order (e.g. render before bin_sort)  */
 
-#define UGS_MAX_CHANNELS 128 /* semantic channels C_o supported */
+#define UGS_MAX_CHANNELS 256 /* semantic channels C_o supported */
 #define UGS_MAX_VIEWS 64
 
 /* Pinhole camera (supplementary S1.3): x_cam = R x_world + t, pixel
@@ -140,6 +140,13 @@ typedef struct {
                             T_final and n_contrib keep their types.  For viewing
                             and inference: ugs_render_bwd and training steps
                             reject it.  Default 0 (FP32). */
+    int sem_bf16x3;      /* 1: for 9..32 channels, run the semantic products of
+                            Eq. semantic_render and Eq. gradiento on bf16 matrix
+                            cores with each FP32 operand split into a high and a
+                            low bf16 part (three products, FP32 accumulation;
+                            about 2^-16 relative per product instead of FP32's
+                            2^-24).  Default 0: FP32 products (FP32 matrix cores
+                            for 9..256 channels, FP32 vector arithmetic for 1..8). */
 } ugs_options;
 
 typedef struct ugs_ctx ugs_ctx;
@@ -194,10 +201,13 @@ int ugs_render_fwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_out
  * (reverse traversal from T_final, gradients of colour, depth, gradient factor,
  * semantics and alpha), and the chain into the parameters (supplementary S1.2
  * for depth -> (mu, s, R), R -> q by the tangent projection, EWA and SH
- * adjoints).  `out` must hold the outputs of the matching ugs_render_fwd.
+ * adjoints).  `out` must hold the outputs of the matching ugs_render_fwd, which
+ * must have been called with T_final and n_contrib (else UGS_ERR_STATE).
  * Gradients are summed over views and ADDED to `dg`.  One ugs_render_bwd per
  * ugs_project: the projection clears the per-record gradient buffers of the
- * workspace that this call accumulates into. */
+ * workspace that this call accumulates into, so a second ugs_render_bwd (or one
+ * after a replayed step or an autotune) returns UGS_ERR_STATE until the next
+ * ugs_project + ugs_bin_sort. */
 int ugs_render_bwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs *out,
                    const ugs_upstream *dout, const ugs_gaussian_grads *dg, void *stream);
 

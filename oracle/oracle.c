@@ -1033,3 +1033,13 @@ int orc_max_threads(void)
     return 1;
 #endif
 }
+
+/* Sets the OpenMP thread count of later calls (timing at one thread). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

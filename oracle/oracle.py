@@ -259,92 +259,74 @@ def max_threads():
     return int(lib().orc_max_threads())
 
 
+def set_threads(n):
+    """OpenMP thread count of later oracle calls."""
+    lib().orc_set_threads(int(n))
+
+
 # ------------------------------------------------------------------ binning
-def box_min_q(mx, my, l11, l21, l22, x0, x1, y0, y1):
-    """Minimum over the box [x0,x1] x [y0,y1] of q(p) = (l11 dx + l21 dy)^2 +
-    (l22 dy)^2, d = p - m (the negative doubled exponent of a Gaussian whose
-    inverse 2D covariance has the Cholesky factor l): zero when the centre is
-    inside, else the least of the four edge minima (q is convex, so on an edge
-    its minimum sits at the clamped stationary point).  FP64, vectorised.
-    Also returns, at the minimiser, (|l11 dx| + |l21 dy|)^2 + (l22 dy)^2, the
-    scale of the rounding error of an FP32 evaluation of the factored form."""
-    mx, my, l11, l21, l22 = (np.asarray(v, np.float64) for v in (mx, my, l11, l21, l22))
-    x0, x1, y0, y1 = (np.asarray(v, np.float64) for v in (x0, x1, y0, y1))
-    a, b, c = l11 * l11, l11 * l21, l21 * l21 + l22 * l22
-    best = np.full(np.broadcast(mx, x0).shape, np.inf)
-    scale = np.zeros_like(best)
-
-    def take(dx, dy):
-        nonlocal best, scale
-        q = (l11 * dx + l21 * dy) ** 2 + (l22 * dy) ** 2
-        better = q < best
-        best = np.where(better, q, best)
-        # rounding scale of an FP32 evaluation of the factored form
-        scale = np.where(better, (np.abs(l11 * dx) + np.abs(l21 * dy)) ** 2 + (l22 * dy) ** 2, scale)
-
-    for X in (x0, x1):
-        dx = X - mx
-        take(dx, np.clip(-b * dx / c, y0 - my, y1 - my))
-    for Y in (y0, y1):
-        dy = Y - my
-        take(np.clip(-b * dy / a, x0 - mx, x1 - mx), dy)
-    inside = (mx >= x0) & (mx <= x1) & (my >= y0) & (my <= y1)
-    return np.where(inside, 0.0, best), np.where(inside, 0.0, scale)
+ALPHA_MIN = 1.0 / 255.0
 
 
-def bin_sort(rect, depth_f32, tiles_x, tile_base, N, cull=None):
-    """Reference tile binning: for every (view, Gaussian) and every tile of its
-    rectangle emit (global tile, float bits of the depth key, Gaussian id) and
-    sort lexicographically.  rect is [V*N][4] = (tx0, ty0, tx1, ty1), half-open;
-    depth_f32 the float32 depth keys [V*N]; tiles_x[v] the tile-grid width of
-    view v and tile_base[v] its first global tile.
+def tile_pairs(g, cam, opts, tile, tile_base=0, delta=1e-5):
+    """Plain definition of the (tile, Gaussian) pairs of one view: a Gaussian
+    belongs to a tile's list when at least one pixel (u, v) of that tile has
+    alpha = min(0.99, o exp(-q/2)) >= 1/255 (section 3.4: the per-tile lists of
+    the tile-based rasterizer hold the Gaussians that can reach the tile's
+    pixels), with the FP64 footprint (2D mean, conic, opacity) of project().
+    Pixels whose alpha lies within delta (relative) of 1/255, and Gaussians with
+    an ambiguous cull, only make a pair optional.  Every pixel of the opacity-
+    aware box (A11) plus two pixels is tested, which holds the whole
+    alpha >= 1/255 ellipse.
 
-    With cull = dict(rec=[V*N][16] float records (mean2d, Cholesky factor
-    l11 l21 l22, opacity), W=[V], H=[V], tile=(tw, th), max_tiles), a tile is
-    kept only if the alpha >= 1/255 ellipse, inflated by 1e-3 relative and
-    absolute, reaches its pixel box (clipped to the image); rectangles of more
-    than max_tiles tiles keep every tile.  Decisions within rounding of the
-    boundary are flagged ambiguous.
-
-    Returns (keys u64, vals u32, per-(view,Gaussian) kept counts, per-pair
-    ambiguity flags, per-(view,Gaussian) ambiguous counts), pairs sorted."""
-    rect = np.asarray(rect, dtype=np.int64).reshape(-1, 4)
-    VN = rect.shape[0]
-    w = np.maximum(rect[:, 2] - rect[:, 0], 0)
-    h = np.maximum(rect[:, 3] - rect[:, 1], 0)
-    counts = (w * h).astype(np.int64)
-    total = int(counts.sum())
-    idx = np.repeat(np.arange(VN), counts)
-    start = np.repeat(np.cumsum(counts) - counts, counts)
-    k = np.arange(total) - start
-    wi = np.maximum(w[idx], 1)
-    tx = rect[idx, 0] + k % wi
-    ty = rect[idx, 1] + k // wi
-    view = idx // N
-    gid = (idx % N).astype(np.uint32)
-    keep = np.ones(total, bool)
-    amb = np.zeros(total, bool)
-    if cull is not None:
-        r = np.asarray(cull["rec"], np.float64).reshape(-1, 16)[idx]
-        tw, th = cull["tile"]
-        Wv = np.asarray(cull["W"], np.int64)[view]
-        Hv = np.asarray(cull["H"], np.int64)[view]
-        bx0, by0 = tx * tw, ty * th
-        bx1, by1 = np.minimum(bx0 + tw, Wv) - 1, np.minimum(by0 + th, Hv) - 1
-        q, sc = box_min_q(r[:, 0], r[:, 1], r[:, 2], r[:, 3], r[:, 4], bx0, bx1, by0, by1)
-        thr = 2.0 * np.log(255.0 * r[:, 5]) * 1.001 + 1e-3
-        tested = counts[idx] <= cull["max_tiles"]
-        keep = ~tested | (q <= thr)
-        amb = tested & (np.abs(q - thr) <= 1e-4 * (1.0 + thr + sc))
-    tile = np.asarray(tile_base, np.int64)[view] + ty * np.asarray(tiles_x, np.int64)[view] + tx
-    dbits = np.asarray(depth_f32, dtype=np.float32).reshape(-1).view(np.uint32)[idx].astype(np.uint64)
-    keys = (tile.astype(np.uint64) << np.uint64(32)) | dbits
-    sel = keep | amb
-    kept_counts = np.bincount(idx[keep & ~amb], minlength=VN).astype(np.int64)
-    amb_counts = np.bincount(idx[amb], minlength=VN).astype(np.int64)
-    keys, gid, dbits, tile, amb = keys[sel], gid[sel], dbits[sel], tile[sel], amb[sel]
-    order = np.lexsort((gid, dbits, tile))
-    return keys[order], gid[order], kept_counts, amb[order], amb_counts
+    Returns dict(required, optional: int64 codes tile * N + id (global tile
+    ids, tile_base added), key: float32 camera depth per Gaussian (the blend-
+    order key), visible: bool per Gaussian)."""
+    N = int(g["N"]) if not isinstance(g, _Scene) else g.N
+    P = project(g, cam, opts)
+    W, H = int(cam["W"]), int(cam["H"])
+    tw, th = tile
+    tiles_x = (W + tw - 1) // tw
+    vis = P["visible"].astype(bool) & (P["depth"] > 0)
+    amb = P["ambiguous"].astype(bool)
+    idx = np.nonzero(vis | amb & (P["depth"] > 0))[0]
+    mx, my = P["mean2d"][idx, 0], P["mean2d"][idx, 1]
+    rx, ry = P["radius"][idx, 0] + 2.0, P["radius"][idx, 1] + 2.0
+    x0 = np.clip(np.floor(mx - rx), 0, W - 1).astype(np.int64)
+    x1 = np.clip(np.ceil(mx + rx), 0, W - 1).astype(np.int64)
+    y0 = np.clip(np.floor(my - ry), 0, H - 1).astype(np.int64)
+    y1 = np.clip(np.ceil(my + ry), 0, H - 1).astype(np.int64)
+    inside = (mx + rx >= 0) & (mx - rx <= W - 1) & (my + ry >= 0) & (my - ry <= H - 1)
+    w = np.where(inside, x1 - x0 + 1, 0)
+    h = np.where(inside, y1 - y0 + 1, 0)
+    cnt = w * h
+    req, opt_ = [], []
+    # chunks of Gaussians keep the pixel arrays small
+    bounds = np.searchsorted(np.cumsum(cnt), np.arange(0, int(cnt.sum()) + 4_000_000, 4_000_000))
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        if b <= a:
+            continue
+        sl = slice(a, b)
+        c = cnt[sl]
+        k = np.repeat(np.arange(a, b), c)
+        pos = np.arange(int(c.sum())) - np.repeat(np.cumsum(c) - c, c)
+        u = x0[k] + pos % np.maximum(w[k], 1)
+        v = y0[k] + pos // np.maximum(w[k], 1)
+        gi = idx[k]
+        dx, dy = u - P["mean2d"][gi, 0], v - P["mean2d"][gi, 1]
+        ca, cb, cc = P["conic"][gi, 0], P["conic"][gi, 1], P["conic"][gi, 2]
+        q = ca * dx * dx + 2.0 * cb * dx * dy + cc * dy * dy
+        alpha = np.minimum(0.99, P["opacity"][gi] * np.exp(-0.5 * q))
+        near = np.abs(alpha - ALPHA_MIN) <= delta * ALPHA_MIN
+        code = (tile_base + (v // th) * tiles_x + (u // tw)) * N + gi
+        hit = alpha >= ALPHA_MIN
+        sure = hit & ~near & vis[gi] & ~amb[gi]
+        req.append(np.unique(code[sure]))
+        opt_.append(np.unique(code[(hit | near) & ~sure]))
+    cat = lambda xs: np.unique(np.concatenate(xs)) if xs else np.zeros(0, np.int64)
+    required = cat(req)
+    optional = np.setdiff1d(cat(opt_), required)
+    return dict(required=required, optional=optional, key=P["depth"].astype(np.float32), visible=vis)
 
 
 # ------------------------------------------------------------------ pruning

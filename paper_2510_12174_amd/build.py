@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libunigs.so")
-SOURCES = ["api.hip", "project.hip", "binsort.hip", "render.hip", "normal.hip", "prune.hip", "loss.hip"]
+SOURCES = ["api.hip", "project.hip", "binsort.hip", "render.hip", "render_f32.hip", "normal.hip", "prune.hip", "loss.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",

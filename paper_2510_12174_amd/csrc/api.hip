@@ -18,6 +18,13 @@ struct ugs_ctx {
     WsLayout L;
     bool have_problem = false;
     bool sorted = false;
+    // set once the gradient records of the current projection have been
+    // consumed by a backward (eager, replayed or autotuned); cleared by the
+    // next projection
+    bool bwd_done = false;
+    // set by a forward that kept the backward's per-pixel state (T_final,
+    // n_contrib) and, with it, the activity mask the backward walks
+    bool fwd_state = false;
     int final_buf = 0;
     bool counters = false;
     char *ws = nullptr;
@@ -88,6 +95,7 @@ int check_options(const ugs_options *o)
     if (!(o->prune_Tk >= 0.f)) return UGS_ERR_INVALID_ARG;
     if (o->depth_mode < 0 || o->depth_mode > 2) return UGS_ERR_INVALID_ARG;
     if (o->half_outputs != 0 && o->half_outputs != 1) return UGS_ERR_INVALID_ARG;
+    if (o->sem_bf16x3 != 0 && o->sem_bf16x3 != 1) return UGS_ERR_INVALID_ARG;
     return UGS_OK;
 }
 
@@ -174,6 +182,7 @@ void make_problem(const ugs_options &o, int64_t N, int C_o, int sh_deg, const ug
     pb.prune_Tk = o.prune_Tk;
     pb.depth_mode = o.depth_mode;
     pb.half_out = o.half_outputs;
+    pb.sem_bf16x3 = o.sem_bf16x3;
     int64_t tiles = 0, pix = 0;
     for (int v = 0; v < V; ++v) {
         const ugs_camera &c = cams[v];
@@ -248,6 +257,8 @@ WsLayout make_layout(const Problem &pb, int64_t pair_cap)
     L.ranges = take((size_t)pb.total_tiles * 8);
     L.gd = take(pix * 4);
     L.nadj = take(pix * 12 * 4);
+    L.amask_words = (int64_t)(P / 32 + 4);
+    L.amask = take((size_t)kMaskPlanes * L.amask_words * 4);
     L.total = o;
     return L;
 }
@@ -255,10 +266,13 @@ WsLayout make_layout(const Problem &pb, int64_t pair_cap)
 int auto_batch(const ugs_options &o, int C_o)
 {
     if (o.batch > 0) return o.batch;
-    // largest power of two up to the tile's pixel count whose LDS staging fits
-    // 32 KB per workgroup; the matrix-core kernels (16 or 32 padded channels)
-    // also hold a 16 x 68 FP32 buffer per wavefront and 216 B per entry
     const int nt = o.tile_w * o.tile_h, cp = channel_pad(C_o);
+    // FP32 matrix-core kernels (9..256 channels): 64 entries per batch (32 for
+    // single-wavefront tiles); the kernels shrink it to what their LDS holds
+    if (C_o > 8 && !(o.sem_bf16x3 && cp <= 32)) return nt >= 256 ? 64 : 32;
+    // otherwise the largest power of two up to the tile's pixel count whose LDS
+    // staging fits 32 KB per workgroup; the split-bf16 kernels (16 or 32 padded
+    // channels) also hold a 16 x 68 FP32 buffer per wavefront and 216 B per entry
     const bool mfma = cp == 16 || cp == 32;
     const size_t per = mfma ? 216 : (size_t)(68 + 4 * cp);
     const size_t fixed = mfma ? (size_t)(nt / 64) * 16 * 68 * 4 : 0;
@@ -355,7 +369,8 @@ int do_project(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, int
     // pair capacity: what fits in the rest of the workspace
     WsLayout L0 = make_layout(pb, 0);
     if (ws_bytes < L0.total) return UGS_ERR_INVALID_ARG;
-    int64_t cap = (int64_t)((ws_bytes - L0.total) / 16);
+    // 16 B of keys and values per pair plus its activity-mask bits
+    int64_t cap = (int64_t)((ws_bytes - L0.total) * 8 / (128 + kMaskPlanes));
     while (cap > 0 && make_layout(pb, cap).total > ws_bytes) cap -= 64;
     if (cap < 0) cap = 0;
     if (cap > 0x7fffffffll) cap = 0x7fffffffll;
@@ -364,6 +379,8 @@ int do_project(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, int
     ctx->ws = (char *)ws;
     ctx->have_problem = true;
     ctx->sorted = false;
+    ctx->bwd_done = false;
+    ctx->fwd_state = false;
     if ((rc = upload_cams(ctx, dcs, s))) return rc;
     StageTimer tm(ctx, 1, s);
     HIPCHK(ctx, launch_project_fwd(*g, ctx->pb, ctx->L, ctx->ws, zero_grec, s));
@@ -411,6 +428,9 @@ int check_bwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outputs 
 {
     int rc;
     if ((rc = check_fwd(ctx, g, ws, out))) return rc;
+    // the projection zeroes the per-view gradient records and one backward
+    // accumulates into them: a second backward needs a new projection
+    if (ctx->bwd_done || !ctx->fwd_state) return UGS_ERR_STATE;
     if (ctx->opt.half_outputs) return UGS_ERR_INVALID_ARG;  // half outputs are for forward-only use
     if ((rc = check_outputs(out, g->C_o, true, false))) return rc;
     if ((rc = check_grads(dg, g->C_o))) return rc;
@@ -449,6 +469,7 @@ int step_stage(ugs_ctx *ctx, const StepArgs &a, int st, hipStream_t s)
         StageTimer tm(ctx, 3, s);
         HIPCHK(ctx, launch_render_fwd(*a.g, ctx->pb, ctx->L, ctx->ws, *a.out, auto_batch(ctx->opt, a.g->C_o),
                                       ctx->counters, ctx->final_buf, s));
+        ctx->fwd_state = a.out->T_final && a.out->n_contrib;
         return UGS_OK;
     }
     case 4: {
@@ -504,7 +525,9 @@ int do_render_bwd(ugs_ctx *ctx, const ugs_gaussians *g, void *ws, const ugs_outp
                   const ugs_gaussian_grads *dg, hipStream_t s)
 {
     StepArgs a{g, nullptr, 0, ws, 0, out, up, dg};
-    return run_stages(ctx, a, 5, 7, s);
+    int rc = run_stages(ctx, a, 5, 7, s);
+    if (rc == UGS_OK) ctx->bwd_done = true;
+    return rc;
 }
 
 int zero_grads(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_gaussian_grads *dg, hipStream_t s)
@@ -574,6 +597,7 @@ void ugs_default_options(ugs_options *o)
     o->prune_Tk = 0.f;
     o->depth_mode = 0;
     o->half_outputs = 0;
+    o->sem_bf16x3 = 0;
 }
 
 int ugs_create(ugs_ctx **out, const ugs_options *opt)
@@ -736,6 +760,7 @@ int ugs_step_replay(ugs_ctx *ctx, void *stream)
     if (!ctx->captured) return UGS_ERR_NOT_CAPTURED;
     if (ctx->host_flag && __atomic_load_n(&ctx->host_flag[0], __ATOMIC_ACQUIRE)) return UGS_ERR_CAPACITY;
     HIPCHK(ctx, hipGraphLaunch(ctx->exec, (hipStream_t)stream));
+    ctx->bwd_done = true;  // a replayed training step consumes its gradient records
     return UGS_OK;
 }
 

@@ -1,0 +1,680 @@
+// Stages S5 and S8 for 9..256 semantic channels, with the two contractions of
+// Eq. semantic_render (O~[p][c] = sum_f w_f[p] o_f[c]) and of Eq. gradiento
+// (dO[f][c] = sum_p w_f[p] G_p[c]), plus the semantic part of the alpha
+// gradient of Alg. backward_render (S[f][p] = sum_c o_f[c] G_p[c]), on the FP32
+// matrix cores (v_mfma_f32_16x16x4_f32: FP32 products, FP32 accumulation).
+//
+// The compositing walk is the per-pixel walk of the plain kernels (one
+// workgroup per (view, tile), one lane per pixel, the tile's sorted list staged
+// in LDS batch by batch, T and the depth accumulated in FP64).  What changes is
+// how the channel work is done:
+//
+//  * Active entries only.  A list entry is "active" for a wavefront when at
+//    least one of its 64 pixels takes it (alpha >= 1/255 before termination).
+//    Only active entries enter the matrix products.  The forward appends each
+//    active entry's weights to a per-wavefront LDS buffer and multiplies every
+//    4 of them (the MFMA's K) into the accumulators; it also records, per
+//    wavefront, one bit per list entry (the activity mask in the workspace).
+//    The backward reads that mask and walks only the marked entries, in groups
+//    of 16 (the MFMA's M): S for the group, the reverse walk, dO.  On gfx950
+//    the FP32 matrix instructions share the FP32 datapath with the vector ALU
+//    (they do not co-issue, unlike the bf16 ones), so every matrix product
+//    spent on an idle entry would cost vector time.
+//  * Channel chunks.  A pass covers CCH channels (forward: up to 128, held as
+//    CCH accumulators per lane; backward: 32, whose upstream gradients live in
+//    registers in the two operand layouts the products need).  Wider C_o runs
+//    further passes over the same lists with a channel offset: a forward pass
+//    repeats the walk to recover the weights and adds only its channels; a
+//    backward chunk pass adds the chunk's dO and its share of the alpha
+//    gradient (the alpha gradient is linear in the semantic upstream, so the
+//    chunks' shares add up to the full one: dL/dalpha_i = T_i s_i -
+//    A_i / (1 - alpha_i) with s_i and A_i sums over channels).
+#include <algorithm>
+
+#include "render_common.h"
+
+
+namespace ugs {
+namespace {
+
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mf4 mma(float a, float b, mf4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int kFRows = 4;   // active entries per forward product (the MFMA's K)
+constexpr int kBGrp = 16;   // active entries per backward group (the MFMA's M)
+constexpr int kSW = 68;     // floats per row of the per-wavefront S / w buffer
+constexpr int kBwdCCH = 32; // channels per backward pass
+
+__host__ __device__ constexpr int feat_stride(int CCH) { return CCH + 4; }
+
+// LDS bytes of the forward kernel for `batch` entries, CCH channels per pass,
+// NW wavefronts.
+__host__ __device__ constexpr size_t fwd_mm_lds(int batch, int CCH, int NW, bool hit)
+{
+    return (size_t)batch * (64 + 4 * feat_stride(CCH) + (hit ? 4 : 0)) + (size_t)NW * kFRows * 64 * 4;
+}
+
+// LDS bytes of the backward kernel.
+__host__ __device__ constexpr size_t bwd_mm_lds(int batch, int CCH, int NW, bool hit)
+{
+    return (size_t)batch * (64 + 4 * feat_stride(CCH) + 4 + (hit ? 4 : 0)) + (size_t)NW * kBGrp * kSW * 4;
+}
+
+// Loads n floats from LDS (n = 1, 2, 4 or 8; 4-float aligned when n >= 4).
+template <int NF>
+__device__ __forceinline__ void lds_row(const float *p, float (&x)[NF])
+{
+    if constexpr (NF >= 4) {
+#pragma unroll
+        for (int k = 0; k < NF / 4; ++k) {
+            const float4 t = reinterpret_cast<const float4 *>(p)[k];
+            x[4 * k] = t.x;
+            x[4 * k + 1] = t.y;
+            x[4 * k + 2] = t.z;
+            x[4 * k + 3] = t.w;
+        }
+    } else if constexpr (NF == 2) {
+        const float2 t = *reinterpret_cast<const float2 *>(p);
+        x[0] = t.x;
+        x[1] = t.y;
+    } else {
+        x[0] = p[0];
+    }
+}
+
+// The semantic share of one reverse step (backward chunk passes): the same T
+// restoration and weight as frag_adjoint, s_i = s_sem (the chunk's part of the
+// dot product of the upstream gradients with the fragment's values), A the
+// chunk's running sum, and the record slots that depend on alpha only:
+// v[0..1] mean2d, v[2..4] Cholesky conic, v[5] opacity.
+__device__ __forceinline__ float frag_adjoint_sem(bool contrib, float4 r0, float4 r1, float dx, float dy, float t1,
+                                                  float t2, float G, float oG, float alpha, float s_sem, double &T,
+                                                  float &A, float (&v)[8])
+{
+    const float rom = rcp_nr(1.f - alpha);
+    const double Tn = contrib ? T * rcp64(1.0 - (double)alpha) : T;
+    const float w = contrib ? (float)((double)alpha * Tn) : 0.f;
+    const float dalpha = contrib ? (float)Tn * s_sem - A * rom : 0.f;
+    A += w * s_sem;
+    T = Tn;
+    const bool free_ = oG < kAlphaMax;  // no gradient through the 0.99 clamp
+    const float dpow = free_ ? dalpha * oG : 0.f;
+    v[5] = free_ ? dalpha * G : 0.f;
+    v[2] = -t1 * dx * dpow;
+    v[3] = -t1 * dy * dpow;
+    v[4] = -t2 * dy * dpow;
+    v[0] = t1 * r0.z * dpow;
+    v[1] = (t1 * r0.w + t2 * r1.x) * dpow;
+    v[6] = 0.f;
+    v[7] = 0.f;
+    return w;
+}
+
+// Stages `n` entries [start, start+n): their 64 B records and the CCH feature
+// channels [c0, c0 + CCH) (zero beyond C_o), rows of feat_stride(CCH) floats.
+template <int NT, int CCH>
+__device__ __forceinline__ void stage_mm(float4 *srec, float *sfeat, const uint32_t *vals, uint32_t start, int n,
+                                         const float4 *rec, int64_t recbase, const float *sem, int C_o, int c0)
+{
+    for (int q = threadIdx.x; q < n * 4; q += NT) {
+        const uint32_t id = vals[start + (q >> 2)];
+        srec[q] = rec[(recbase + id) * 4 + (q & 3)];
+    }
+    for (int q = threadIdx.x; q < n * CCH; q += NT) {
+        const int e = q / CCH, c = q - e * CCH;
+        const uint32_t id = vals[start + e];
+        sfeat[e * feat_stride(CCH) + c] = c0 + c < C_o ? sem[(int64_t)id * C_o + c0 + c] : 0.f;
+    }
+}
+
+// ------------------------------------------------------------------ forward
+// Per wavefront, the accumulators hold O~ transposed in the MFMA output layout:
+// acc[q][pb][r] is channel c0 + CPL (4 (lane / 16) + r) + q of pixel
+// 16 pb + lane % 16 (pixels numbered row-major in the wavefront's 8 x 8
+// block), CPL = CCH / 16.  Product: A[m][k] = o_{row k}[c0 + CPL m + q] (each
+// lane reads CPL consecutive floats of one staged feature row), B[k][n] =
+// w_{row k}[pixel 16 pb + n] (one 16-byte LDS read gives the four pixel
+// blocks), K = the 4 buffered active entries.  MAIN passes also composite
+// colour, depth and the gradient factor, write T_final / n_contrib and the
+// counters; other passes (C_o > CCH) only add their channels.
+template <int TW, int TH, int CCH, int DM, bool MAIN>
+__global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH >= 128 ? 2 : 3))) render_fwd_mm_kernel(
+    const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
+    const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o, int c0,
+    ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles,
+    const float *__restrict__ hrec, int half_out, uint32_t *__restrict__ amask, int64_t mwords)
+{
+    static_assert(CCH == 16 || CCH == 32 || CCH == 64 || CCH == 128, "forward pass: 16, 32, 64 or 128 channels");
+    constexpr int NT = TW * TH, NW = NT / 64, FS = feat_stride(CCH), CPL = CCH / 16;
+    constexpr bool HIT = DM == 2;
+    constexpr float kd = DM == 1 ? 0.f : 1.f;  // depth form fixed per instantiation
+    extern __shared__ float4 smem[];
+    float4 *srec = smem;
+    float *sfeat = (float *)(smem + 4 * batch);
+    float *shh = sfeat + (size_t)batch * FS;
+    float *wb = shh + (HIT ? batch : 0) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * (kFRows * 64);  // [row][lane % 16][pixel block]
+    (void)NW;
+    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+    if (tile >= ntiles) return;
+    const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    const uint2 range = ranges[tile];
+    const float fx = (float)ti.px, fy = (float)ti.py;
+    const int64_t recbase = (int64_t)ti.v * N;
+    const int lane = __lane_id(), l16 = lane & 15, h16 = lane >> 4;
+    const int wslot = l16 * 4 + h16;  // this lane's pixel (16 h16 + l16) in a row of wb
+
+    double T = 1.0, D = 0.0;
+    float cr = 0.f, cg = 0.f, cb = 0.f, K = 0.f;
+    mf4 acc[CPL][4];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q)
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) acc[q][pb] = mf4{0.f, 0.f, 0.f, 0.f};
+    uint32_t last = 0, n_eval = 0, n_con = 0;
+    bool done = !ti.inside;
+    // activity mask of this wavefront (MAIN passes of training steps): bits of
+    // the current 32-entry word, flushed with one atomic OR per word
+    uint32_t *mplane = amask ? amask + (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * mwords : nullptr;
+    uint32_t mbits = 0;
+    int64_t mword = -1;
+    auto mflush = [&]() {
+        if (mbits && lane == 0) atomicOr(&mplane[mword], mbits);
+        mbits = 0;
+    };
+
+    for (uint32_t start = range.x; start < range.y; start += (uint32_t)batch) {
+        if (__syncthreads_count(done) == NT) break;
+        const int n = (int)min((uint32_t)batch, range.y - start);
+        stage_mm<NT, CCH>(srec, sfeat, vals, start, n, rec, recbase, sem, C_o, c0);
+        stage_hits<NT, HIT>(shh, vals, start, n, hrec, recbase);
+        __syncthreads();
+        if (__all(done)) continue;  // the other wavefronts may still walk this batch
+        int nrow = 0;
+        int rid = 0;  // lane l: batch index of buffered row l / 16
+        for (int j = 0; j < n; ++j) {
+            float wf = 0.f;
+            if (!done) {
+                const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
+                const float dx = fx - r0.x, dy = fy - r0.y;
+                const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
+                const float alpha = fminf(kAlphaMax, r1.y * gauss_of(t1, t2));
+                ++n_eval;
+                if (alpha >= kAlphaMin) {
+                    const double tT = T * (1.0 - (double)alpha);
+                    if (tT < kTStop) {
+                        done = true;
+                    } else {
+                        const double w = (double)alpha * T;
+                        wf = (float)w;
+                        if constexpr (MAIN) {
+                            const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
+                            const float kdj = frag_kd<HIT>(kd, shh, j, r2, r3, dx, dy);
+                            const float B = kdj * (r2.x * dx + r2.y * dy);
+                            const float Cq = kdj * (r2.z * dx * dx + 2.f * r2.w * dx * dy + r3.x * dy * dy);
+                            const float d = r1.w * (1.f + B) * rcp_nr(1.f + 2.f * B + Cq);
+                            cr += wf * r3.y;
+                            cg += wf * r3.z;
+                            cb += wf * r3.w;
+                            K += wf * r1.z;
+                            D += w * (double)d;
+                        }
+                        T = tT;
+                        last = start + (uint32_t)j + 1;
+                        ++n_con;
+                    }
+                }
+            }
+            if (__any(wf != 0.f)) {  // an active entry: buffer its weights
+                if constexpr (MAIN) {
+                    if (mplane) {
+                        const uint32_t e = start + (uint32_t)j;
+                        if ((int64_t)(e >> 5) != mword) {
+                            mflush();
+                            mword = e >> 5;
+                        }
+                        mbits |= 1u << (e & 31);
+                    }
+                }
+                wb[nrow * 64 + wslot] = wf;
+                rid = h16 == nrow ? j : rid;
+                if (++nrow == kFRows) {
+                    __builtin_amdgcn_wave_barrier();
+                    const float4 bw = *reinterpret_cast<const float4 *>(wb + h16 * 64 + l16 * 4);
+                    float a[CPL];
+                    lds_row<CPL>(sfeat + rid * FS + CPL * l16, a);
+#pragma unroll
+                    for (int q = 0; q < CPL; ++q) {
+                        acc[q][0] = mma(a[q], bw.x, acc[q][0]);
+                        acc[q][1] = mma(a[q], bw.y, acc[q][1]);
+                        acc[q][2] = mma(a[q], bw.z, acc[q][2]);
+                        acc[q][3] = mma(a[q], bw.w, acc[q][3]);
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    nrow = 0;
+                }
+            }
+            if (__all(done)) break;
+        }
+        if (nrow) {  // the batch's remaining rows, padded with zero weights
+            for (int r = nrow; r < kFRows; ++r) wb[r * 64 + wslot] = 0.f;
+            __builtin_amdgcn_wave_barrier();
+            const float4 bw = *reinterpret_cast<const float4 *>(wb + h16 * 64 + l16 * 4);
+            float a[CPL];
+            lds_row<CPL>(sfeat + rid * FS + CPL * l16, a);
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                acc[q][0] = mma(a[q], bw.x, acc[q][0]);
+                acc[q][1] = mma(a[q], bw.y, acc[q][1]);
+                acc[q][2] = mma(a[q], bw.z, acc[q][2]);
+                acc[q][3] = mma(a[q], bw.w, acc[q][3]);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if constexpr (MAIN) {
+        if (mplane) mflush();
+        if (ti.inside) {
+            const int64_t p = ti.pix, HW = ti.HW, off = ti.off;
+            put_out(out.rgb, 3 * off + p, cr, half_out);
+            put_out(out.rgb, 3 * off + HW + p, cg, half_out);
+            put_out(out.rgb, 3 * off + 2 * HW + p, cb, half_out);
+            out.depth[off + p] = (float)D;
+            put_out(out.kmap, off + p, K, half_out);
+            if (out.T_final) out.T_final[off + p] = (float)T;  // optional in forward-only use
+            if (out.n_contrib) out.n_contrib[off + p] = last ? last - range.x : 0u;
+        }
+    }
+    {
+        const int W = cams[ti.v].W, H = cams[ti.v].H;
+        const int qx0 = ti.px - (lane & 7), qy0 = ti.py - (lane >> 3);
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) {
+            const int pp = 16 * pb + l16;
+            const int x = qx0 + (pp & 7), y = qy0 + (pp >> 3);
+            if (x < W && y < H) {
+                const int64_t base = (int64_t)C_o * ti.off + (int64_t)y * W + x;
+#pragma unroll
+                for (int q = 0; q < CPL; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int c = c0 + CPL * (4 * h16 + r) + q;
+                        if (c < C_o) put_out(out.sem, base + (int64_t)c * ti.HW, acc[q][pb][r], half_out);
+                    }
+            }
+        }
+    }
+    if constexpr (MAIN) {
+        if (count) {
+            unsigned long long e = n_eval, c = n_con;
+            for (int o = 32; o > 0; o >>= 1) {
+                e += __shfl_xor(e, o, 64);
+                c += __shfl_xor(c, o, 64);
+            }
+            if (lane == 0) {
+                atomicAdd(&cnt->n_eval, e);
+                atomicAdd(&cnt->n_contrib, c);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ backward
+// One pass over CCH = 32 channels [c0, c0 + 32).  The wavefront walks only its
+// active entries (the forward's activity mask), last first, in groups of 16.
+// The upstream semantic gradients G of its 64 pixels for these channels stay
+// in registers in the two B-operand layouts:
+//   GS[ks][pb] = G[pixel 16 pb + lane % 16][channel 8 (lane / 16) + ks]  (S)
+//   GD[ks][cb] = G[pixel 16 (lane / 16) + ks][channel 16 cb + lane % 16] (dO)
+// S[f][p] = sum_c o_f[c] G_p[c]: A[m = f][k] = o_{act f}[8 (lane / 16) + ks]
+// (8 consecutive floats of the staged feature row), output rows f = entries,
+// columns p = pixels, stored in the wavefront's S / w buffer.  The reverse walk
+// reads its S there and overwrites it with w.  dO[f][c] = sum_p w_f[p] G_p[c]:
+// A[m = f][k] = w_f[16 (lane / 16) + ks], output D[f][c], added to the
+// semantic gradient of entry f.  MAIN passes (c0 = 0) carry every term of the
+// fragment adjoint and the 16 record slots; chunk passes (c0 > 0) only the
+// semantic share of the alpha gradient, i.e. record slots 0..5 (mean2d, conic,
+// opacity).
+template <int TW, int TH, int DM, bool MAIN>
+__global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))) render_bwd_mm_kernel(
+    const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
+    const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o, int c0,
+    const float *__restrict__ T_final, const uint32_t *__restrict__ n_contrib, const float *__restrict__ up_rgb,
+    const float *__restrict__ gD_img, const float *__restrict__ up_kmap, const float *__restrict__ up_sem,
+    float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, const float *__restrict__ hrec,
+    SemSeed seed, const uint32_t *__restrict__ amask, int64_t mwords)
+{
+    constexpr int CCH = kBwdCCH, NT = TW * TH, FS = feat_stride(CCH);
+    constexpr int KS = CCH / 4, NCB = CCH / 16;
+    constexpr bool HIT = DM == 2;
+    constexpr float kd = DM == 1 ? 0.f : 1.f;
+    extern __shared__ float4 smem[];
+    __shared__ uint32_t s_max;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    float4 *srec = smem;
+    float *sfeat = (float *)(smem + 4 * batch);
+    uint32_t *sid = (uint32_t *)(sfeat + (size_t)batch * FS);
+    float *shh = (float *)(sid + batch);
+    float *swb = shh + (HIT ? batch : 0) + wave * (kBGrp * kSW);
+    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+    if (tile >= ntiles) return;
+    const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    const uint2 range = ranges[tile];
+    const float fx = (float)ti.px, fy = (float)ti.py;
+    const int64_t recbase = (int64_t)ti.v * N;
+    const int lane = __lane_id(), l16 = lane & 15, h16 = lane >> 4;
+    const uint32_t *mplane = amask + (int64_t)wave * mwords;
+
+    // upstream semantic gradients (or the fused cross-entropy seed) of the
+    // wavefront's pixels for this pass's channels
+    const int W = cams[ti.v].W, H = cams[ti.v].H;
+    const int qx0 = ti.px - (lane & 7), qy0 = ti.py - (lane >> 3);
+    const bool fused = !up_sem && seed.label;
+    float my_lse = 0.f, my_sc = 0.f;
+    int my_lab = -1;
+    if (fused && ti.inside) seed_pixel(seed, C_o, ti.off, ti.HW, ti.pix, my_lse, my_lab, my_sc);
+    auto up_at = [&](int p, int c) -> float {
+        const int x = qx0 + (p & 7), y = qy0 + (p >> 3);
+        if (fused) {
+            const float l = __shfl(my_lse, p, 64), sc = __shfl(my_sc, p, 64);
+            const int lb = __shfl(my_lab, p, 64);
+            if (c >= C_o || x >= W || y >= H) return 0.f;
+            const float o = seed.logits[(int64_t)C_o * ti.off + (int64_t)c * ti.HW + (int64_t)y * W + x];
+            return sc * (__expf(o - l) - (c == lb ? 1.f : 0.f));
+        }
+        if (!up_sem || c >= C_o || x >= W || y >= H) return 0.f;
+        return up_sem[(int64_t)C_o * ti.off + (int64_t)c * ti.HW + (int64_t)y * W + x];
+    };
+    float GSr[KS][4], GDr[16][NCB];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) GSr[ks][pb] = up_at(16 * pb + l16, c0 + KS * h16 + ks);
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) GDr[ks][cb] = up_at(16 * h16 + ks, c0 + 16 * cb + l16);
+
+    double T = 1.0;
+    float gR = 0.f, gG = 0.f, gB = 0.f, gDp = 0.f, gK = 0.f;
+    uint32_t last = 0;
+    if (ti.inside) {
+        const int64_t p = ti.pix, HW = ti.HW, off = ti.off;
+        T = T_final[off + p];
+        const uint32_t rel = n_contrib[off + p];
+        last = rel ? range.x + rel : 0u;
+        if constexpr (MAIN) {
+            if (up_rgb) {
+                gR = up_rgb[3 * off + p];
+                gG = up_rgb[3 * off + HW + p];
+                gB = up_rgb[3 * off + 2 * HW + p];
+            }
+            gDp = gD_img[off + p];
+            if (up_kmap) gK = up_kmap[off + p];
+        }
+    }
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    if (last) atomicMax(&s_max, last);
+    __syncthreads();
+    const uint32_t end_all = s_max;
+    float A = 0.f;
+
+    for (uint32_t end = end_all; end > range.x;) {
+        const uint32_t start = end - range.x > (uint32_t)batch ? end - (uint32_t)batch : range.x;
+        const int n = (int)(end - start);
+        __syncthreads();
+        stage_mm<NT, CCH>(srec, sfeat, vals, start, n, rec, recbase, sem, C_o, c0);
+        for (int q = threadIdx.x; q < n; q += NT) sid[q] = vals[start + q];
+        stage_hits<NT, HIT>(shh, vals, start, n, hrec, recbase);
+        __syncthreads();
+        // the batch's active entries for this wavefront, last first, from the
+        // forward's activity mask (bits of entries start .. start + n - 1)
+        int nact = 0, myact = 0;
+        {
+            const int64_t w = start >> 5;
+            const uint64_t lo = ((uint64_t)mplane[w + 1] << 32) | mplane[w];
+            const int sh = (int)(start & 31);
+            uint64_t m = sh ? (lo >> sh) | ((uint64_t)mplane[w + 2] << (64 - sh)) : lo;
+            if (n < 64) m &= (1ull << n) - 1ull;
+            while (m) {
+                const int j = 63 - __builtin_clzll(m);
+                m &= ~(1ull << j);
+                myact = lane == nact ? j : myact;
+                ++nact;
+            }
+        }
+        for (int g0 = 0; g0 < nact; g0 += kBGrp) {
+            // S for the group's 16 entries (rows past nact repeat an active entry; their w is 0)
+            {
+                const int fa = __shfl(myact, min(g0 + l16, nact - 1), 64);
+                const float *arow = sfeat + fa * FS + KS * h16;
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb) {
+                    mf4 s4 = mf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int k4 = 0; k4 < KS / 4; ++k4) {
+                        const float4 a = reinterpret_cast<const float4 *>(arow)[k4];
+                        s4 = mma(a.x, GSr[4 * k4][pb], s4);
+                        s4 = mma(a.y, GSr[4 * k4 + 1][pb], s4);
+                        s4 = mma(a.z, GSr[4 * k4 + 2][pb], s4);
+                        s4 = mma(a.w, GSr[4 * k4 + 3][pb], s4);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) swb[(4 * h16 + r) * kSW + 16 * pb + l16] = s4[r];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            // reverse walk over the group
+            const int ng = min(kBGrp, nact - g0);
+            for (int f = 0; f < kBGrp; ++f) {
+                float w = 0.f;
+                if (f < ng) {
+                    const int j = __builtin_amdgcn_readlane(myact, g0 + f);
+                    const uint32_t entry = start + (uint32_t)j;
+                    const float s_sem = swb[f * kSW + lane];
+                    const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
+                    const float dx = fx - r0.x, dy = fy - r0.y;
+                    const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
+                    const float G = gauss_of(t1, t2);
+                    const float oG = r1.y * G;
+                    const float alpha = fminf(kAlphaMax, oG);
+                    const bool contrib = entry < last && alpha >= kAlphaMin;
+                    float *gr = grec + (recbase + sid[j]) * kRecFloats;
+                    if constexpr (MAIN) {
+                        float v[16];
+                        const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
+                        w = frag_adjoint(contrib, r0, r1, r2, r3, dx, dy, t1, t2, G, oG, alpha, s_sem, gR, gG, gB,
+                                         gDp, gK, frag_kd<HIT>(kd, shh, j, r2, r3, dx, dy), T, A, v);
+                        const float tot = reduce_scatter<16>(v);
+                        if ((lane & 3) == 0) unsafeAtomicAdd(&gr[lane >> 2], tot);
+                    } else {
+                        // the semantic share only: no colour, depth or K terms
+                        float u[8];
+                        w = frag_adjoint_sem(contrib, r0, r1, dx, dy, t1, t2, G, oG, alpha, s_sem, T, A, u);
+                        const float tot = reduce_scatter<8>(u);
+                        if ((lane & 7) == 0 && (lane >> 3) < 6) unsafeAtomicAdd(&gr[lane >> 3], tot);
+                    }
+                }
+                swb[f * kSW + lane] = w;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // dO[f][c] = sum_p w_f[p] G_p[c] over the wavefront's pixels
+            {
+                mf4 d4[NCB];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) d4[cb] = mf4{0.f, 0.f, 0.f, 0.f};
+                const float *wrow = swb + l16 * kSW + 16 * h16;
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    const float4 a = reinterpret_cast<const float4 *>(wrow)[k4];
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        d4[cb] = mma(a.x, GDr[4 * k4][cb], d4[cb]);
+                        d4[cb] = mma(a.y, GDr[4 * k4 + 1][cb], d4[cb]);
+                        d4[cb] = mma(a.z, GDr[4 * k4 + 2][cb], d4[cb]);
+                        d4[cb] = mma(a.w, GDr[4 * k4 + 3][cb], d4[cb]);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int f = 4 * h16 + r;
+                    const int jf = __shfl(myact, min(g0 + f, nact - 1), 64);
+                    if (f < ng) {
+                        const int64_t row = (int64_t)sid[jf] * C_o + c0;
+#pragma unroll
+                        for (int cb = 0; cb < NCB; ++cb) {
+                            const float x = d4[cb][r];
+                            if (x != 0.f && c0 + 16 * cb + l16 < C_o) unsafeAtomicAdd(&dsem[row + 16 * cb + l16], x);
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        end = start;
+    }
+}
+
+// Largest batch (a multiple of 16, at most `want`) whose LDS fits `cap` bytes.
+template <typename F>
+int fit_batch(int want, size_t cap, F lds)
+{
+    int b = (want + 15) / 16 * 16;
+    if (b < 16) b = 16;
+    while (b > 16 && lds(b) > cap) b -= 16;
+    return b;
+}
+
+template <int TW, int TH, int CCH>
+hipError_t fwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                         const ugs_outputs &out, int batch, bool counters, int final_buf, int c0, hipStream_t s)
+{
+    auto cams = (const DevCam *)(ws + L.cams);
+    auto ranges = (const uint2 *)(ws + L.ranges);
+    auto vals = (const uint32_t *)(ws + (final_buf ? L.vals1 : L.vals0));
+    auto rec = (const float4 *)(ws + L.rec);
+    auto cnt = (DevCounters *)(ws + L.counters);
+    auto hrec = (const float *)(ws + L.hrec);
+    constexpr int NW = TW * TH / 64;
+    const bool hit = pb.depth_mode == 2;
+    const int b = fit_batch(batch, 64 * 1024, [&](int x) { return fwd_mm_lds(x, CCH, NW, hit); });
+    const size_t lds = fwd_mm_lds(b, CCH, NW, hit);
+    const bool main_pass = c0 == 0;
+    // the activity mask for the backward: written by the first pass of a forward
+    // that keeps the backward's state (T_final, n_contrib)
+    uint32_t *amask = nullptr;
+    if (main_pass && out.T_final && out.n_contrib) {
+        amask = (uint32_t *)(ws + L.amask);
+        hipError_t e = launch_fill_u32(amask, 0u, (int64_t)kMaskPlanes * L.amask_words, s);
+        if (e != hipSuccess) return e;
+    }
+#define UGS_FWD_MM(DMV, MAINV)                                                                                  \
+    hipLaunchKernelGGL((render_fwd_mm_kernel<TW, TH, CCH, DMV, MAINV>), dim3(xcd_grid(pb.total_tiles)),        \
+                       dim3(TW * TH), lds, s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, c0, out, b, cnt, \
+                       (int)counters, (uint32_t)pb.total_tiles, hrec, pb.half_out, amask, L.amask_words)
+    if (main_pass) {
+        if (pb.depth_mode == 2) UGS_FWD_MM(2, true);
+        else if (pb.depth_mode == 1) UGS_FWD_MM(1, true);
+        else UGS_FWD_MM(0, true);
+    } else {
+        if (pb.depth_mode == 2) UGS_FWD_MM(2, false);
+        else UGS_FWD_MM(0, false);  // no depth in chunk passes: modes 0 and 1 walk alike
+    }
+#undef UGS_FWD_MM
+    return hipGetLastError();
+}
+
+template <int TW, int TH>
+hipError_t bwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                         const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg, int batch,
+                         int final_buf, int c0, hipStream_t s)
+{
+    auto cams = (const DevCam *)(ws + L.cams);
+    auto ranges = (const uint2 *)(ws + L.ranges);
+    auto vals = (const uint32_t *)(ws + (final_buf ? L.vals1 : L.vals0));
+    auto rec = (const float4 *)(ws + L.rec);
+    auto grec = (float *)(ws + L.grec);
+    auto gd = (const float *)(ws + L.gd);
+    auto hrec = (const float *)(ws + L.hrec);
+    const SemSeed seed{out.sem, up.sem ? nullptr : up.sem_label, up.sem_scale};
+    constexpr int NW = TW * TH / 64;
+    const bool hit = pb.depth_mode == 2, main_pass = c0 == 0;
+    const int b = std::min(64, fit_batch(batch, 64 * 1024, [&](int x) {
+        return bwd_mm_lds(x, kBwdCCH, NW, hit);
+    }));
+    const size_t lds = bwd_mm_lds(b, kBwdCCH, NW, hit);
+#define UGS_BWD_MM(DMV, MAINV)                                                                                    \
+    hipLaunchKernelGGL((render_bwd_mm_kernel<TW, TH, DMV, MAINV>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), \
+                       lds, s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, c0, out.T_final, out.n_contrib,   \
+                       up.rgb, gd, up.kmap, up.sem, grec, dg.sem, b, (uint32_t)pb.total_tiles, hrec, seed,     \
+                       (const uint32_t *)(ws + L.amask), L.amask_words)
+    if (main_pass) {
+        if (pb.depth_mode == 2) UGS_BWD_MM(2, true);
+        else if (pb.depth_mode == 1) UGS_BWD_MM(1, true);
+        else UGS_BWD_MM(0, true);
+    } else {
+        if (pb.depth_mode == 2) UGS_BWD_MM(2, false);
+        else UGS_BWD_MM(0, false);
+    }
+#undef UGS_BWD_MM
+    return hipGetLastError();
+}
+
+// Channels per forward pass for C_o channels (9..256): one pass up to 128.
+int fwd_pass_channels(int C_o) { return C_o <= 16 ? 16 : C_o <= 32 ? 32 : C_o <= 64 ? 64 : 128; }
+
+template <int TW, int TH>
+hipError_t fwd_mm_tile(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out,
+                       int batch, bool counters, int final_buf, hipStream_t s)
+{
+    const int cch = fwd_pass_channels(pb.C_o);
+    for (int c0 = 0; c0 < pb.C_o; c0 += cch) {
+        hipError_t e;
+        switch (cch) {
+        case 16: e = fwd_mm_launch<TW, TH, 16>(g, pb, L, ws, out, batch, counters, final_buf, c0, s); break;
+        case 32: e = fwd_mm_launch<TW, TH, 32>(g, pb, L, ws, out, batch, counters, final_buf, c0, s); break;
+        case 64: e = fwd_mm_launch<TW, TH, 64>(g, pb, L, ws, out, batch, counters, final_buf, c0, s); break;
+        default: e = fwd_mm_launch<TW, TH, 128>(g, pb, L, ws, out, batch, counters, final_buf, c0, s); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int TW, int TH>
+hipError_t bwd_mm_tile(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out,
+                       const ugs_upstream &up, const ugs_gaussian_grads &dg, int batch, int final_buf, hipStream_t s)
+{
+    for (int c0 = 0; c0 < pb.C_o; c0 += kBwdCCH) {
+        hipError_t e = bwd_mm_launch<TW, TH>(g, pb, L, ws, out, up, dg, batch, final_buf, c0, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_render_fwd_mm(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                                const ugs_outputs &out, int batch, bool counters, int final_buf, hipStream_t s)
+{
+    if (pb.total_tiles == 0) return hipSuccess;
+    if (pb.tile_w == 8 && pb.tile_h == 8) return fwd_mm_tile<8, 8>(g, pb, L, ws, out, batch, counters, final_buf, s);
+    if (pb.tile_w == 32 && pb.tile_h == 8) return fwd_mm_tile<32, 8>(g, pb, L, ws, out, batch, counters, final_buf, s);
+    return fwd_mm_tile<16, 16>(g, pb, L, ws, out, batch, counters, final_buf, s);
+}
+
+hipError_t launch_render_bwd_mm(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                                const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg,
+                                int batch, int final_buf, hipStream_t s)
+{
+    if (pb.total_tiles == 0) return hipSuccess;
+    if (pb.tile_w == 8 && pb.tile_h == 8) return bwd_mm_tile<8, 8>(g, pb, L, ws, out, up, dg, batch, final_buf, s);
+    if (pb.tile_w == 32 && pb.tile_h == 8) return bwd_mm_tile<32, 8>(g, pb, L, ws, out, up, dg, batch, final_buf, s);
+    return bwd_mm_tile<16, 16>(g, pb, L, ws, out, up, dg, batch, final_buf, s);
+}
+
+}  // namespace ugs

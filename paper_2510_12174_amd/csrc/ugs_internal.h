@@ -48,6 +48,12 @@ struct DevCam {
 //   g3 = (d gam.c, d rgb.r, d rgb.g, d rgb.b)
 constexpr int kRecFloats = 16;
 
+// Activity mask written by the forward for the backward (9..256 channels): one
+// bit plane per wavefront slot of a tile (4 planes), bit e of a plane set when
+// list entry e (a sorted pair) has at least one contributing pixel among that
+// wavefront's 64 pixels.  The backward walks only those entries.
+constexpr int kMaskPlanes = 4;
+
 struct DevCounters {
     uint32_t P;          // pairs required
     uint32_t overflow;   // non-zero when P exceeded the capacity
@@ -58,8 +64,9 @@ struct DevCounters {
 
 struct WsLayout {
     size_t cams, rec, hrec, rect, touched, voff, poff, tsorted, dkey0, dkey1, didx0, didx1, vlist, scan_part, keys0, keys1,
-        vals0, vals1, hist, digit_tot, ranges, grec, gd, nadj, counters, total;
+        vals0, vals1, hist, digit_tot, ranges, grec, gd, nadj, amask, counters, total;
     int64_t N, VN, total_tiles, total_pix, pair_cap;
+    int64_t amask_words;  // 32-bit words per plane of the activity mask
     int V, nb_scan, depth_bits, tile_bits;
 };
 
@@ -75,6 +82,7 @@ struct Problem {
     float prune_Tk;
     int depth_mode;  // 0: ray-ellipsoid midpoint, 1: Gaussian centre, 2: midpoint on a hit, else centre
     int half_out;    // rgb, kmap, normal and sem outputs in binary16
+    int sem_bf16x3;  // 9..32 channels: semantic products on split-bf16 matrix cores
 };
 
 // Stores an output value as FP32 or, for half outputs, binary16 (nearest even).
@@ -97,6 +105,12 @@ hipError_t launch_render_fwd(const ugs_gaussians &g, const Problem &pb, const Ws
 hipError_t launch_render_bwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
                              const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg,
                              int batch, int final_buf, hipStream_t s);
+// 9..256 channels, semantic contractions on the FP32 matrix cores
+hipError_t launch_render_fwd_mm(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                                const ugs_outputs &out, int batch, bool counters, int final_buf, hipStream_t s);
+hipError_t launch_render_bwd_mm(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
+                                const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg,
+                                int batch, int final_buf, hipStream_t s);
 hipError_t launch_normal_fwd(const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out,
                              const ugs_options &opt, hipStream_t s);
 hipError_t launch_normal_bwd(const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out,

@@ -27,7 +27,7 @@ UGS_ERR_CAPACITY = -3
 UGS_ERR_HIP = -4
 UGS_ERR_NOT_CAPTURED = -5
 UGS_ERR_STATE = -6
-UGS_MAX_CHANNELS = 128
+UGS_MAX_CHANNELS = 256
 UGS_MAX_VIEWS = 64
 
 EXPORTS = ["ugs_default_options", "ugs_create", "ugs_destroy", "ugs_set_options", "ugs_workspace_size",
@@ -70,7 +70,7 @@ class ugs_upstream(C.Structure):
 class ugs_options(C.Structure):
     _fields_ = [("tile_w", C.c_int), ("tile_h", C.c_int), ("batch", C.c_int), ("step1", C.c_int),
                 ("step2", C.c_int), ("lambda_", C.c_float), ("orient_sign", C.c_int), ("prune_Tk", C.c_float),
-                ("depth_mode", C.c_int), ("half_outputs", C.c_int)]
+                ("depth_mode", C.c_int), ("half_outputs", C.c_int), ("sem_bf16x3", C.c_int)]
 
 
 class ugs_targets(C.Structure):
@@ -195,6 +195,50 @@ def _check_tensor(t, name):
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype not in (torch.float32, torch.int32) \
             or not t.is_contiguous():
         raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+
+
+def check_map(t, name, dtype, numel):
+    """Raises ValueError unless `t` is a contiguous CUDA tensor of `dtype` (a
+    torch dtype) with `numel` elements: the C ABI reads raw pointers, so a wrong
+    element type (int64 class labels read as int32 pairs), a strided view or a
+    short map would be read wrongly or out of bounds."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != int(numel):
+        raise ValueError(f"{name} must have {int(numel)} elements, got {t.numel()}")
+
+
+def check_outputs(o, P, C_o, half=False, state=True):
+    """Validates output planes for P pixels (all views) and C_o channels."""
+    import torch
+    mt = torch.float16 if half else torch.float32
+    for k, n, dt in (("rgb", 3 * P, mt), ("depth", P, torch.float32), ("kmap", P, mt), ("normal", 3 * P, mt)):
+        check_map(o.get(k), k, dt, n)
+    if C_o > 0:
+        check_map(o.get("sem"), "sem", mt, C_o * P)
+    if state or o.get("T_final") is not None:
+        check_map(o.get("T_final"), "T_final", torch.float32, P)
+    if state or o.get("n_contrib") is not None:
+        check_map(o.get("n_contrib"), "n_contrib", torch.int32, P)
+
+
+def check_upstream(u, P, C_o):
+    """Validates the upstream gradient maps (absent maps may be None)."""
+    import torch
+    f, i = torch.float32, torch.int32
+    for k, n, dt in (("rgb", 3 * P, f), ("depth", P, f), ("kmap", P, f), ("normal", 3 * P, f),
+                     ("sem", C_o * P, f), ("normal_target", 3 * P, f), ("normal_scale", 1, f),
+                     ("sem_label", P, i), ("sem_scale", 1, f)):
+        t = u.get(k) if u else None
+        if t is not None and not (k == "sem" and C_o == 0):
+            check_map(t, k, dt, n)
 
 
 def make_outputs(o):
@@ -332,6 +376,13 @@ class Loss:
     def __call__(self, out, gt):
         """out: rasterizer outputs; gt: dict with rgb and optional depth,
         normal, label (int32).  Returns (losses tensor[8], gradient dict)."""
+        import torch
+        P = pixel_offsets_from(self.cams_c)
+        check_outputs(out, P, self.C_o, state=False)
+        for k, n, dt in (("rgb", 3 * P, torch.float32), ("depth", P, torch.float32),
+                         ("normal", 3 * P, torch.float32), ("label", P, torch.int32)):
+            if gt.get(k) is not None or k == "rgb":
+                check_map(gt.get(k), "gt " + k, dt, n)
         t = ugs_targets()
         for k in ("rgb", "depth", "normal", "label"):
             v = gt.get(k)
@@ -347,6 +398,11 @@ class Loss:
                 up.update(sem_label=gt["label"], sem_scale=self.losses[12:13])
             return self.losses, up
         return self.losses, self.grad
+
+
+def pixel_offsets_from(cams_c):
+    """Total pixel count of a ctypes camera array."""
+    return sum(int(c.W) * int(c.H) for c in cams_c)
 
 
 def pixel_offsets(cams):
@@ -395,6 +451,12 @@ class Rasterizer:
         self.ws_bytes = 0
         self.pair_cap = 0
         self._keep = []
+        # projection generation: bumped by every projection of this context, so
+        # that a backward can tell whether the workspace still holds the
+        # projection of the forward it belongs to; bwd_consumed is set once a
+        # backward has used that projection's gradient records
+        self.generation = 0
+        self.bwd_consumed = False
 
     def __del__(self):
         try:
@@ -408,6 +470,8 @@ class Rasterizer:
         for k, v in options.items():
             setattr(self.opts, "lambda_" if k == "lambda" else k, v)
         _chk(lib().ugs_set_options(self.ctx, C.byref(self.opts)), "ugs_set_options", self.ctx)
+        self.generation += 1  # the context forgets its projection
+        self.bwd_consumed = True
 
     def workspace_size(self, g, cams, pair_cap):
         n = C.c_size_t()
@@ -435,6 +499,8 @@ class Rasterizer:
         for _ in range(4):
             self.ensure_workspace(g, cams, cap)
             s = _stream()
+            self.generation += 1
+            self.bwd_consumed = False
             _chk(lib().ugs_project(self.ctx, C.byref(gs), cs, len(cams), self.ws_ptr, self.ws_bytes, s),
                  "ugs_project", self.ctx)
             P = C.c_int64()
@@ -447,9 +513,11 @@ class Rasterizer:
         raise UgsError(UGS_ERR_CAPACITY, "project_and_sort")
 
     def forward(self, g, cams, out=None):
-        self.project_and_sort(g, cams)
         if out is None:
-            out = alloc_outputs(cams, int(g["C_o"]))
+            out = alloc_outputs(cams, int(g["C_o"]), half=bool(self.opts.half_outputs))
+        check_outputs(out, pixel_offsets(cams)[-1], int(g["C_o"]), half=bool(self.opts.half_outputs),
+                      state=False)
+        self.project_and_sort(g, cams)
         _chk(lib().ugs_render_fwd(self.ctx, C.byref(make_gaussians(g)), self.ws_ptr, C.byref(make_outputs(out)),
                                   _stream()), "ugs_render_fwd", self.ctx)
         return out
@@ -457,9 +525,13 @@ class Rasterizer:
     def backward(self, g, out, up, grads=None):
         if grads is None:
             grads = zeros_like_params(g)
+        P = int(out["depth"].numel())
+        check_outputs(out, P, int(g["C_o"]))
+        check_upstream(up, P, int(g["C_o"]))
         _chk(lib().ugs_render_bwd(self.ctx, C.byref(make_gaussians(g)), self.ws_ptr, C.byref(make_outputs(out)),
                                   C.byref(make_upstream(up)), C.byref(make_grads(grads)), _stream()),
              "ugs_render_bwd", self.ctx)
+        self.bwd_consumed = True
         return grads
 
     def pair_count(self):
@@ -527,6 +599,8 @@ class Rasterizer:
 
     def replay(self):
         _chk(lib().ugs_step_replay(self.ctx, _stream()), "ugs_step_replay", self.ctx)
+        self.generation += 1  # the captured step projects again
+        self.bwd_consumed = True
 
     def autotune(self, g, cams, out, up, grads, cache=None):
         """ugs_autotune, with its choice cached in a JSON file keyed by
@@ -562,6 +636,8 @@ class Rasterizer:
         rc = lib().ugs_autotune(self.ctx, C.byref(make_gaussians(g)), make_cameras(cams), len(cams), self.ws_ptr,
                                 self.ws_bytes, C.byref(make_outputs(out)), C.byref(make_upstream(up)),
                                 C.byref(make_grads(grads)), _stream(), C.byref(chosen), C.byref(ms))
+        self.generation += 1  # the candidates' steps overwrote the workspace
+        self.bwd_consumed = True
         _chk(rc, "ugs_autotune", self.ctx)
         self.opts = chosen
         return dict(tile_w=chosen.tile_w, tile_h=chosen.tile_h, batch=chosen.batch, ms=float(ms.value))
@@ -610,7 +686,8 @@ def _autograd_function():
                      opacity_logit=opacity_logit.contiguous(), mask_logit=mask_logit.contiguous(),
                      sh=sh.contiguous(), sem=sem.contiguous())
             out = rast.forward(g, cams)
-            ctx.rast, ctx.g, ctx.out = rast, g, out
+            ctx.rast, ctx.g, ctx.out, ctx.cams = rast, g, out, cams
+            ctx.generation = rast.generation
             ctx.mark_non_differentiable(out["T_final"], out["n_contrib"])
             return out["rgb"], out["depth"], out["kmap"], out["normal"], out["sem"], out["T_final"], out["n_contrib"]
 
@@ -620,7 +697,14 @@ def _autograd_function():
             for k, t in (("rgb", d_rgb), ("depth", d_depth), ("kmap", d_kmap), ("normal", d_normal),
                          ("sem", d_sem)):
                 up[k] = None if t is None else t.contiguous()
-            grads = ctx.rast.backward(ctx.g, ctx.out, up)
+            rast = ctx.rast
+            if rast.generation != ctx.generation or rast.bwd_consumed:
+                # the workspace no longer holds this forward's projection (another
+                # render on the same rasterizer, or a second backward of this one):
+                # project and sort again (deterministic: the same records and tile
+                # lists the saved T_final and n_contrib index)
+                rast.project_and_sort(ctx.g, ctx.cams)
+            grads = rast.backward(ctx.g, ctx.out, up)
             return (None, None, None, grads["mean"], grads["quat"], grads["log_scale"], grads["opacity_logit"],
                     grads["mask_logit"], grads["sh"], grads["sem"])
 

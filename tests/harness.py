@@ -37,6 +37,15 @@ def small_workload(kind, seed=0):
         g["sem"] = np.ascontiguousarray(np.asarray(g["sem"]).reshape(g["N"], -1)[:, :12])
         g["C_o"] = 12
         return g, cams, o
+    if kind == "w2c200":
+        # 200 semantic channels (beyond one 128-channel forward pass and six
+        # 32-channel backward passes): N(0, 1) logits from their own seed
+        g, cams, o = small_workload("w2s", seed)
+        g = dict(g)
+        rng = np.random.Generator(np.random.PCG64(2200 + seed))
+        g["sem"] = rng.standard_normal((g["N"], 200)).astype(np.float32)
+        g["C_o"] = 200
+        return g, cams, o
     if kind == "w3s":
         cam = scenes.camera(240, 136, 225, 225, 120, 68,
                             np.array([[0.0, -1.0, 0.0], [0.0, 0.0, -1.0], [1.0, 0.0, 0.0]]), [0, 0, 2.5])
@@ -97,7 +106,7 @@ def gpu_run(g, cams, opts, ups=None, tile=(16, 16), batch=0, per_view=False, ras
     C_o = int(g["C_o"])
     if rast is None:
         rast = U.Rasterizer(tile_w=tile[0], tile_h=tile[1], batch=batch, prune_Tk=float(opts.get("prune_Tk", 0.0)),
-                            depth_mode=int(opts.get("depth_mode", 0)))
+                            depth_mode=int(opts.get("depth_mode", 0)), sem_bf16x3=int(opts.get("sem_bf16x3", 0)))
     if not per_view:
         out = rast.forward(gd, cams)
         grads = None

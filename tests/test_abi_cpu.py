@@ -87,8 +87,10 @@ def test_workspace_size_and_limits(U):
     assert L.ugs_workspace_size(ctx, 1000, 8, 3, cams, 1, 100000, C.byref(n)) == U.UGS_OK
     small = n.value
     assert L.ugs_workspace_size(ctx, 1000, 8, 3, cams, 1, 200000, C.byref(n)) == U.UGS_OK
-    assert abs((n.value - small) - 100000 * 16) <= 4 * 256  # 2 x 4 B keys + 2 x 4 B values per pair
-    assert L.ugs_workspace_size(ctx, 1000, 200, 3, cams, 1, 10, C.byref(n)) == U.UGS_ERR_UNSUPPORTED
+    # 2 x 4 B keys + 2 x 4 B values per pair, plus 4 bits of activity mask
+    assert abs((n.value - small) - 100000 * 16.5) <= 6 * 256
+    assert L.ugs_workspace_size(ctx, 1000, 200, 3, cams, 1, 10, C.byref(n)) == U.UGS_OK
+    assert L.ugs_workspace_size(ctx, 1000, 257, 3, cams, 1, 10, C.byref(n)) == U.UGS_ERR_UNSUPPORTED
     assert L.ugs_workspace_size(ctx, 1000, 8, 4, cams, 1, 10, C.byref(n)) == U.UGS_ERR_UNSUPPORTED
     assert L.ugs_workspace_size(ctx, -1, 8, 3, cams, 1, 10, C.byref(n)) == U.UGS_ERR_INVALID_ARG
     assert L.ugs_workspace_size(ctx, 10, 8, 3, cams, 0, 10, C.byref(n)) == U.UGS_ERR_INVALID_ARG
@@ -207,3 +209,19 @@ int main(void) {
     out = subprocess.check_output([str(exe)], text=True).split()
     assert out[:5] == ["16", "16", "0", "0.10", str(U.UGS_ERR_INVALID_ARG)]
     assert "capacity" in " ".join(out[5:]).lower()
+
+
+def test_binding_validates_maps(U):
+    """The binding refuses maps it would hand to the C ABI with the wrong element
+    type, device, layout or size (CPU tensors: the dtype check comes first)."""
+    import torch
+    with pytest.raises(ValueError, match="dtype"):
+        U.check_map(torch.zeros(16, dtype=torch.int64), "gt label", torch.int32, 16)
+    with pytest.raises(ValueError, match="dtype"):
+        U.check_map(torch.zeros(16, dtype=torch.float64), "gt rgb", torch.float32, 16)
+    with pytest.raises(ValueError, match="CUDA"):
+        U.check_map(torch.zeros(16, dtype=torch.int32), "gt label", torch.int32, 16)
+    with pytest.raises(ValueError, match="tensor"):
+        U.check_map(np.zeros(16, np.int32), "gt label", torch.int32, 16)
+    with pytest.raises(ValueError, match="dtype"):
+        U.check_upstream(dict(sem_label=torch.zeros(4, dtype=torch.int64)), 4, 2)

@@ -49,7 +49,9 @@ def _check_forward(O, kind, tile=(16, 16), normals_e2e=False, extra=None):
     Hn.say(f"[{kind}] image max-abs {err}  masked {nmask}/{npix}")
     for k, e in err.items():
         assert e <= Hn.IMG_TOL, (k, e)
-    assert nmask <= 0.05 * npix
+    # decisions within 1e-5 (relative) of their thresholds: at most 0.2 % of the
+    # pixels (measured: at most 0.13 %, workload 3 in the hit-or-centre depth form)
+    assert nmask <= 0.002 * npix
     # last contributor: GPU n_contrib indexes its tile list; compare the id
     vals = rast.debug_buffer("vals").cpu().numpy().astype(np.int64)
     ranges = rast.debug_buffer("ranges").cpu().numpy().astype(np.int64)
@@ -68,9 +70,35 @@ def _check_forward(O, kind, tile=(16, 16), normals_e2e=False, extra=None):
     return g, cams, opts, outs, ora, ms, rast
 
 
-@pytest.mark.parametrize("kind", ["w1", "w2s", "w2c12", "w3s", "w4s", "w5s"])
+@pytest.mark.parametrize("kind", ["w1", "w2s", "w2c12", "w2c200", "w3s", "w4s", "w5s"])
 def test_forward_parity(O, kind):
     _check_forward(O, kind, normals_e2e=(kind == "w1"))
+
+
+def test_forward_parity_w1_every_pixel(O):
+    """Workload 1 compared at every pixel, without the decision-margin mask:
+    every image channel within 1e-4 and the same last contributor everywhere
+    (its one pixel within the margin, where an alpha lies 7.9e-6 relative from
+    1/255, takes the oracle's decision)."""
+    g, cams, opts = Hn.small_workload("w1")
+    outs, _, rast = Hn.gpu_run(g, cams, opts)
+    ora = Hn.oracle_forward(O, g, cams, opts)
+    none = [dict(img=np.zeros((c["H"], c["W"]), bool), normal=np.zeros((c["H"], c["W"]), bool)) for c in cams]
+    err = Hn.image_errors(outs, ora, none, normals=False)
+    Hn.say(f"[w1 every pixel] image max-abs {err}")
+    for k, e in err.items():
+        assert e <= Hn.IMG_TOL, (k, e)
+    vals = rast.debug_buffer("vals").cpu().numpy().astype(np.int64)
+    ranges = rast.debug_buffer("ranges").cpu().numpy().astype(np.int64)
+    lid = Hn.gpu_last_id(outs[0]["n_contrib"], vals, ranges, cams[0], 0, (16, 16))
+    assert np.array_equal(lid, ora[0]["last_id"])
+
+
+@pytest.mark.parametrize("kind", ["w2s", "w2c12"])
+def test_forward_parity_bf16x3(O, kind):
+    """The opt-in split-bf16 semantic products (9..32 channels) stay within the
+    image tolerance."""
+    _check_forward(O, kind, extra={"sem_bf16x3": 1})
 
 
 def test_project_stage(O):
@@ -101,49 +129,57 @@ def test_project_stage(O):
 
 @pytest.mark.parametrize("kind,tile", [("w1", (16, 16)), ("w4s", (16, 16)), ("w4s", (8, 8)), ("w2s", (32, 8))])
 def test_binsort_bit_exact(O, kind, tile):
-    """Given the GPU's FP32 records, rectangles and depth keys, tile counts and
-    sorted (tile, depth, index) lists equal the plain definition (every tile of
-    the rectangle that the alpha ellipse reaches) exactly, up to the decisions
-    that FP32 rounding leaves ambiguous."""
+    """The GPU's tile lists against the plain definition (section 3.4: each
+    tile's list holds the Gaussians that reach one of its pixels with
+    alpha >= 1/255, in front-to-back order of the FP32 camera depth, ties by
+    index): every required (tile, Gaussian) pair is present; every list is in
+    exactly that order; the per-record tile counts equal the pairs emitted; the
+    depth keys equal the oracle's.  Pairs beyond the required set are allowed
+    (a conservative cull; they cannot change any pixel since alpha < 1/255
+    there)."""
     g, cams, opts = Hn.small_workload(kind)
     _, _, rast = Hn.gpu_run(g, cams, opts, tile=tile)
-    rect = rast.debug_buffer("rects").cpu().numpy().view(np.uint32).astype(np.int64)
+    N = int(g["N"])
     rec = rast.debug_buffer("records").cpu().numpy()
-    touched = rast.debug_buffer("touched").cpu().numpy()
-    keys = rast.debug_buffer("keys").cpu().numpy().view(np.uint32).astype(np.uint64)
-    vals = rast.debug_buffer("vals").cpu().numpy().view(np.uint32)
-    ranges = rast.debug_buffer("ranges").cpu().numpy().view(np.uint32)
-    r4 = np.stack([rect[:, 0] & 0xFFFF, rect[:, 0] >> 16, rect[:, 1] & 0xFFFF, rect[:, 1] >> 16], 1)
-    depth = rec[:, 7].astype(np.float32)
-    tw, th = tile
-    tiles_x = [(c["W"] + tw - 1) // tw for c in cams]
+    touched = rast.debug_buffer("touched").cpu().numpy().astype(np.int64)
+    gk = rast.debug_buffer("keys").cpu().numpy().view(np.uint32).astype(np.int64)
+    gv = rast.debug_buffer("vals").cpu().numpy().view(np.uint32).astype(np.int64)
+    ranges = rast.debug_buffer("ranges").cpu().numpy().view(np.uint32).astype(np.int64)
     bases = _tile_bases(cams, tile)
-    H = [c["H"] for c in cams]
-    W = [c["W"] for c in cams]
-    cull = dict(rec=rec, W=W, H=H, tile=tile, max_tiles=1024)
-    k_ref, v_ref, counts, amb, amb_counts = O.bin_sort(r4, depth, tiles_x, bases, g["N"], cull=cull)
-    # per-record tile counts: the kept tiles, give or take the decisions that
-    # rounding leaves ambiguous
-    t64 = touched.astype(np.int64)
-    assert np.all(t64 >= counts) and np.all(t64 <= counts + amb_counts)
-    Hn.say(f"[binsort {kind} {tile}] pairs {keys.size}, reference {int(counts.sum())} "
-           f"+ {int(amb_counts.sum())} ambiguous")
-    # sorted lists: equal once the ambiguous pairs are taken out of both
-    amb_set = set(zip((k_ref[amb] >> np.uint64(32)).astype(np.int64).tolist(), v_ref[amb].astype(np.int64).tolist()))
-    gk = keys.astype(np.int64)
-    gv = vals.astype(np.int64)
-    if amb_set:
-        g_amb = np.array([(a, b) in amb_set for a, b in zip(gk.tolist(), gv.tolist())], bool)
-    else:
-        g_amb = np.zeros(gk.size, bool)
-    assert np.array_equal(gk[~g_amb], (k_ref[~amb] >> np.uint64(32)).astype(np.int64))
-    assert np.array_equal(gv[~g_amb], v_ref[~amb].astype(np.int64))
-    tiles = gk
-    total_tiles = bases[-1] + tiles_x[-1] * ((cams[-1]["H"] + th - 1) // th)
-    lo = np.searchsorted(tiles, np.arange(total_tiles), "left")
-    hi = np.searchsorted(tiles, np.arange(total_tiles), "right")
-    ref_ranges = np.where((hi > lo)[:, None], np.stack([lo, hi], 1), 0)
-    assert np.array_equal(ranges.astype(np.int64), ref_ranges)
+    codes = gk * N + gv
+    assert np.all(np.diff(gk) >= 0)
+    n_req = n_opt = 0
+    key_bits = np.zeros(gk.size, np.int64)
+    for v, cam in enumerate(cams):
+        ref = O.tile_pairs(g, cam, opts, tile, tile_base=bases[v])
+        present = np.isin(ref["required"], codes)
+        missing = ref["required"][~present]
+        assert missing.size == 0, f"view {v}: {missing.size} required pairs missing, e.g. " \
+                                  f"tile {missing[:3] // N}, id {missing[:3] % N}"
+        n_req += ref["required"].size
+        n_opt += ref["optional"].size
+        # depth keys of the records the GPU emitted: equal to the oracle's
+        hi = bases[v + 1] if v + 1 < len(bases) else int(ranges.shape[0])
+        sel = (gk >= bases[v]) & (gk < hi)
+        ids = gv[sel]
+        assert np.array_equal(rec[v * N + ids, 7].astype(np.float32).view(np.uint32),
+                              ref["key"][ids].view(np.uint32))
+        key_bits[sel] = ref["key"][ids].view(np.uint32).astype(np.int64)
+        # tile counts: the pairs each record emitted
+        cnt = np.bincount(ids, minlength=N)
+        assert np.array_equal(cnt, touched[v * N:(v + 1) * N])
+    # order inside every tile's run: strictly increasing (depth bits, id)
+    same = gk[1:] == gk[:-1]
+    inc = (key_bits[1:] > key_bits[:-1]) | ((key_bits[1:] == key_bits[:-1]) & (gv[1:] > gv[:-1]))
+    assert np.all(inc[same])
+    # ranges: [start, end) of each tile's run (empty tiles: any empty range)
+    starts = np.searchsorted(gk, np.arange(ranges.shape[0]), "left")
+    ends = np.searchsorted(gk, np.arange(ranges.shape[0]), "right")
+    full = ends > starts
+    assert np.array_equal(ranges[full, 0], starts[full]) and np.array_equal(ranges[full, 1], ends[full])
+    assert np.all(ranges[~full, 0] == ranges[~full, 1])
+    Hn.say(f"[binsort {kind} {tile}] pairs {gk.size}: required {n_req}, optional {n_opt}, "
+           f"beyond the definition {gk.size - n_req}")
 
 
 def _check_backward(O, kind, tile=(16, 16), per_view=False, with_normals=True, extra=None):
@@ -165,12 +201,20 @@ def _check_backward(O, kind, tile=(16, 16), per_view=False, with_normals=True, e
     return err, gr, ref
 
 
-@pytest.mark.parametrize("kind", ["w1", "w2s", "w2c12", "w3s", "w4s", "w5s"])
+@pytest.mark.parametrize("kind", ["w1", "w2s", "w2c12", "w2c200", "w3s", "w4s", "w5s"])
 def test_backward_parity(O, kind):
     """Gradients of a random-weighted sum of all outputs (RGB, depth, gradient
     factor, semantics; normals only where the forward normal is end-to-end
     comparable, i.e. workload 1)."""
     err, _, _ = _check_backward(O, kind, with_normals=(kind == "w1"))
+    for k, e in err.items():
+        assert e <= 1.0, (k, e)
+
+
+@pytest.mark.parametrize("kind", ["w2s", "w2c12"])
+def test_backward_parity_bf16x3(O, kind):
+    """Gradients with the opt-in split-bf16 semantic products."""
+    err, _, _ = _check_backward(O, kind, with_normals=False, extra={"sem_bf16x3": 1})
     for k, e in err.items():
         assert e <= 1.0, (k, e)
 
@@ -308,7 +352,7 @@ def test_forward_only_step(O):
     r2 = U.Rasterizer(prune_Tk=float(opts.get("prune_Tk", 0.0)))
     o2 = r2.forward(gd, cams, U.alloc_outputs(cams, g["C_o"], state=False))
     ups = Hn.scenes.upstream(cams, g["C_o"], seed=9)
-    with pytest.raises(U.UgsError):
+    with pytest.raises((U.UgsError, ValueError)):
         r2.backward(gd, o2, Hn.stack_upstream(ups, g["C_o"]))
 
 
@@ -517,3 +561,56 @@ def test_edge_cases(O):
     gb["mean"][2] = -5.0
     outs, _, rast = Hn.gpu_run(gb, cams1, {})
     assert np.all(outs[0]["depth"] == 0) and rast.pair_count() == 0
+
+
+@pytest.mark.parametrize("kind", ["w1", "w2s", "w3s", "w4s", "w5s"])
+def test_roofline_counters_match_oracle(O, kind):
+    """The forward kernel's work counters, the numerator of the reported FLOP
+    roofline (Alg. forward_render): F_contrib, the fragments composited
+    (alpha >= 1/255, before termination), equals the oracle's fragment count
+    summed over the pixels; F_eval, the list entries evaluated before each walk
+    stops, equals the oracle's emulation on the GPU's tile lists: the position
+    of the terminating fragment (the oracle's term_id) in the pixel's tile list
+    plus one, or the whole list where the walk runs to its end.  Pixels whose
+    decisions lie within the rounding margin may differ by at most their list
+    length."""
+    import torch
+    from paper_2510_12174_amd import unigs as U
+    g, cams, opts = Hn.small_workload(kind)
+    gd = U.to_device(g)
+    rast = U.Rasterizer(prune_Tk=float(opts.get("prune_Tk", 0.0)))
+    rast.project_and_sort(gd, cams)
+    rast.enable_counters(True)
+    out = rast.forward(gd, cams)
+    F_eval, F_contrib = rast.read_counters()
+    rast.enable_counters(False)
+    torch.cuda.synchronize()
+    vals = rast.debug_buffer("vals").cpu().numpy().view(np.uint32).astype(np.int64)
+    ranges = rast.debug_buffer("ranges").cpu().numpy().view(np.uint32).astype(np.int64)
+    ora = Hn.oracle_forward(O, g, cams, opts)
+    ms = Hn.masks(O, g, cams, opts, ora)
+    bases = _tile_bases(cams, (16, 16))
+    e_ref = c_ref = slack = 0
+    for v, cam in enumerate(cams):
+        H, W = cam["H"], cam["W"]
+        yy, xx = np.mgrid[0:H, 0:W]
+        t = bases[v] + (yy // 16) * ((W + 15) // 16) + (xx // 16)
+        r0, r1 = ranges[t, 0], ranges[t, 1]
+        length = r1 - r0
+        term = ora[v]["term_id"]
+        pos = np.full((H, W), -1, np.int64)
+        for yv, xv in zip(*np.nonzero(term >= 0)):
+            lst = vals[r0[yv, xv]:r1[yv, xv]]
+            hit = np.nonzero(lst == term[yv, xv])[0]
+            assert hit.size == 1 or ms[v]["img"][yv, xv], (v, yv, xv)
+            pos[yv, xv] = hit[0] if hit.size else length[yv, xv] - 1
+        ev = np.where(term >= 0, pos + 1, length)
+        e_ref += int(ev.sum())
+        c_ref += int(ora[v]["n_frag"].sum())
+        slack += int(length[ms[v]["img"]].sum())
+    Hn.say(f"[{kind}] F_eval gpu {F_eval} oracle {e_ref}; F_contrib gpu {F_contrib} oracle {c_ref}; "
+           f"slack {slack}")
+    assert abs(F_eval - e_ref) <= slack
+    assert abs(F_contrib - c_ref) <= slack
+    if slack == 0:
+        assert F_eval == e_ref and F_contrib == c_ref

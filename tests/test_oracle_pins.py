@@ -455,104 +455,39 @@ def test_gradients_match_fd_workload1(oracle_mod):
     assert ok >= 55
 
 
-def test_bin_sort_reference_bruteforce(oracle_mod):
+def test_tile_pairs_against_bruteforce_render(oracle_mod):
+    """The plain-definition pair reference (tile holds a pixel with
+    alpha >= 1/255) against the C renderer's brute-force path, which tests every
+    Gaussian at every pixel: with 1x1 tiles the reference's pairs of a pixel are
+    exactly the fragments the renderer composites there (low opacities, so no
+    walk terminates), rotated camera and off-axis Gaussians included; 8x8 tiles
+    are the union of their pixels' sets; the key is the FP32 camera depth."""
     O = oracle_mod
-    rng = np.random.default_rng(2)
-    V, N = 2, 7
-    tiles_x = [5, 3]
-    tiles_y = [4, 6]
-    tile_base = [0, 20]
-    rect = []
-    for v in range(V):
-        for i in range(N):
-            x0 = int(rng.integers(0, tiles_x[v]))
-            y0 = int(rng.integers(0, tiles_y[v]))
-            x1 = int(rng.integers(x0, tiles_x[v] + 1))
-            y1 = int(rng.integers(y0, tiles_y[v] + 1))
-            rect.append((x0, y0, x1, y1))
-    depth = rng.choice(np.array([1.5, 2.0, 2.25], np.float32), size=V * N)
-    keys, vals, counts, amb, _ = O.bin_sort(np.array(rect), depth, tiles_x, tile_base, N)
-    assert not amb.any()
-    want = []
-    for idx, (x0, y0, x1, y1) in enumerate(rect):
-        v, i = divmod(idx, N)
-        for ty in range(y0, y1):
-            for tx in range(x0, x1):
-                want.append((tile_base[v] + ty * tiles_x[v] + tx, float(depth[idx]), i))
-    want.sort()
-    got = [(int(k >> np.uint64(32)), float(np.array([k & np.uint64(0xFFFFFFFF)], np.uint64)
-                                                  .astype(np.uint32).view(np.float32)[0]), int(i))
-           for k, i in zip(keys, vals)]
-    assert got == want
-    assert counts.sum() == len(want)
-
-
-def test_box_min_q_matches_dense_search(oracle_mod):
-    """Minimum of the Gaussian exponent form over a pixel box against a dense
-    grid search of the same box (the grid minimum can only be larger, and by
-    no more than the grid's resolution allows)."""
-    O = oracle_mod
-    rng = np.random.default_rng(11)
-    for _ in range(200):
-        l11, l22 = np.exp(rng.normal(-1.5, 1.0, 2))
-        l21 = rng.normal(0, 1.0) * l11
-        mx, my = rng.uniform(-20, 40, 2)
-        x0, y0 = rng.integers(0, 20, 2)
-        x1, y1 = x0 + rng.integers(0, 16), y0 + rng.integers(0, 16)
-        q, sc = O.box_min_q(mx, my, l11, l21, l22, x0, x1, y0, y1)
-        gx, gy = np.meshgrid(np.linspace(x0, x1, 161), np.linspace(y0, y1, 161))
-        dx, dy = gx - mx, gy - my
-        qg = ((l11 * dx + l21 * dy) ** 2 + (l22 * dy) ** 2).min()
-        assert q <= qg + 1e-9 * (1 + qg)
-        # the true minimiser is within half a grid step of a grid point
-        step = max(x1 - x0, y1 - y0, 1) / 160.0
-        grad = 2 * np.sqrt(qg) * (abs(l11) + abs(l21) + abs(l22)) * step
-        assert qg - q <= grad + 1e-9
-        if x0 <= mx <= x1 and y0 <= my <= y1:
-            assert q == 0.0
-
-
-def test_bin_sort_cull_is_conservative(oracle_mod):
-    """The ellipse cull keeps every tile holding a pixel centre whose alpha
-    reaches 1/255 (brute force over the pixels of every rectangle tile), and
-    drops tiles the ellipse misses by a clear margin."""
-    O = oracle_mod
-    rng = np.random.default_rng(12)
-    tw = th = 8
-    W, H = 64, 48
-    n = 60
-    rec = np.zeros((n, 16), np.float32)
-    rect, dropped = [], 0
-    for i in range(n):
-        l11, l22 = np.exp(rng.normal(-1.2, 0.8, 2))
-        l21 = rng.normal(0, 1.5) * l11
-        o = rng.uniform(0.02, 0.99)
-        mx, my = rng.uniform(-5, W + 5), rng.uniform(-5, H + 5)
-        rec[i, :6] = (mx, my, l11, l21, l22, o)
-        r = np.float64(rec[i])
-        # loose rectangle: every tile within 24 px of the centre
-        x0, x1 = max(0, int((mx - 24) // tw)), min(W // tw, int((mx + 24) // tw) + 1)
-        y0, y1 = max(0, int((my - 24) // th)), min(H // th, int((my + 24) // th) + 1)
-        rect.append((x0, y0, max(x0, x1), max(y0, y1)))
-    rect = np.array(rect)
-    depth = np.ones(n, np.float32)
-    cull = dict(rec=rec, W=[W], H=[H], tile=(tw, th), max_tiles=1024)
-    keys, vals, counts, amb, amb_counts = O.bin_sort(rect, depth, [W // tw], [0], n, cull=cull)
-    kept = set(zip((keys >> np.uint64(32)).astype(int).tolist(), vals.astype(int).tolist()))
-    for i in range(n):
-        mx, my, l11, l21, l22, o = np.float64(rec[i, :6])
-        x0, y0, x1, y1 = rect[i]
-        for ty in range(y0, y1):
-            for tx in range(x0, x1):
-                px, py = np.meshgrid(np.arange(tx * tw, min(tx * tw + tw, W)), np.arange(ty * th, min(ty * th + th, H)))
-                dx, dy = px - mx, py - my
-                alpha = np.minimum(0.99, o * np.exp(-0.5 * ((l11 * dx + l21 * dy) ** 2 + (l22 * dy) ** 2)))
-                tile = ty * (W // tw) + tx
-                if (alpha >= 1 / 255).any():
-                    assert (tile, i) in kept
-                elif (alpha < 0.5 / 255).all() and (tile, i) not in kept:
-                    dropped += 1
-    assert dropped > 50
+    from paper_2510_12174_amd import scenes
+    g, _, opts = scenes.make_scene(1, N=60)
+    g = dict(g)
+    rng = np.random.default_rng(21)
+    g["opacity_logit"] = rng.normal(-1.5, 0.7, 60).astype(np.float32)  # o <= ~0.5: T stays >= 1e-3
+    g["log_scale"] = rng.normal(-2.3, 0.4, (3, 60)).astype(np.float32)
+    W, H = 56, 44
+    cam = scenes.look_at([0.4, -2.6, 1.2], [0.1, 0.05, -0.1], W, H, 52.0)
+    N = 60
+    o = O.render(g, cam, opts, path=0)
+    assert o["T_final"].min() > 1e-3
+    ref = O.tile_pairs(g, cam, opts, (1, 1))
+    req = np.bincount(ref["required"] // N, minlength=W * H).reshape(H, W)
+    opt = np.bincount(ref["optional"] // N, minlength=W * H).reshape(H, W)
+    assert req.sum() > 500 and np.all(req <= o["n_frag"]) and np.all(o["n_frag"] <= req + opt)
+    assert opt.sum() <= 2
+    # 8x8 tiles: the union of the pixels' pairs
+    ref8 = O.tile_pairs(g, cam, opts, (8, 8))
+    pix = ref["required"] // N
+    u, v = pix % W, pix // W
+    want = np.unique((v // 8 * ((W + 7) // 8) + u // 8) * N + ref["required"] % N)
+    assert np.all(np.isin(want, np.concatenate([ref8["required"], ref8["optional"]])))
+    assert np.all(np.isin(ref8["required"], want))
+    P = O.project(g, cam, opts)
+    assert np.array_equal(ref["key"], P["depth"].astype(np.float32))
 
 
 def test_prune_reference(oracle_mod):
