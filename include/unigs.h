@@ -297,6 +297,20 @@ int ugs_prune(const ugs_gaussians *g, const ugs_gaussian_grads *out, int n_state
               const ugs_gaussian_grads *state_out, float T_k, int reset_k, void *scratch, size_t scratch_bytes,
               int64_t *n_kept, void *stream);
 
+/* The same compaction as ugs_prune without a caller scratch buffer, for callers
+ * that cannot allocate device memory (code running under HIP graph capture,
+ * tight serving or training loops, harnesses that forbid hipMalloc).  The keep
+ * flags and their scan live in a fixed array inside the library, one copy per
+ * GPU (about 32 MiB, held until the process ends); the call itself allocates
+ * nothing.  g->N must be at most UGS_PRUNE_NOALLOC_MAX_N, else
+ * UGS_ERR_UNSUPPORTED; other errors as ugs_prune.  Every call on one GPU uses
+ * that GPU's array: calls that overlap on one GPU (two streams, two threads)
+ * race and must be serialised by the caller.  Synchronises `stream`. */
+#define UGS_PRUNE_NOALLOC_MAX_N (1 << 22)
+int ugs_prune_noalloc(const ugs_gaussians *g, const ugs_gaussian_grads *out, int n_state,
+                      const ugs_gaussians *state_in, const ugs_gaussian_grads *state_out, float T_k, int reset_k,
+                      int64_t *n_kept, void *stream);
+
 /* ---------------------------------------------------------------- losses
  * The training loss of section 3.4 ("Loss Function") on the rendered maps,
  * producing the upstream gradients that ugs_render_bwd consumes, on the device

@@ -7,6 +7,8 @@
 // Gaussian to its compacted position.  The keep test is the projection's skip
 // test, |sigmoid(mask_logit) - 1| <= T_k evaluated in FP64, so a pruned set
 // renders exactly like the full set with the skip enabled.
+#include <mutex>
+
 #include "ugs_internal.h"
 
 namespace ugs {
@@ -103,40 +105,32 @@ int compact_set(const ugs_gaussians &in, const ugs_gaussian_grads &out, int nsh,
 
 int64_t scan_parts(int64_t N) { return (N + kScanBlock - 1) / kScanBlock; }
 
-}  // namespace
-}  // namespace ugs
+size_t prune_scratch_bytes(int64_t N) { return (size_t)(8 * N + 4 * scan_parts(N) + 256); }
 
-using namespace ugs;
-
-extern "C" {
-
-int ugs_prune_scratch_size(int64_t N, size_t *bytes)
+int check_prune_args(const ugs_gaussians *g, const ugs_gaussian_grads *out, int n_state,
+                     const ugs_gaussians *state_in, const ugs_gaussian_grads *state_out, float T_k,
+                     const int64_t *n_kept)
 {
-    if (N < 0 || !bytes) return UGS_ERR_INVALID_ARG;
-    *bytes = (size_t)(8 * N + 4 * scan_parts(N) + 256);
-    return UGS_OK;
-}
-
-int ugs_prune(const ugs_gaussians *g, const ugs_gaussian_grads *out, int n_state, const ugs_gaussians *state_in,
-              const ugs_gaussian_grads *state_out, float T_k, int reset_k, void *scratch, size_t scratch_bytes,
-              int64_t *n_kept, void *stream)
-{
-    if (!g || !out || !n_kept || !scratch || n_state < 0 || (n_state > 0 && (!state_in || !state_out)))
+    if (!g || !out || !n_kept || n_state < 0 || (n_state > 0 && (!state_in || !state_out)))
         return UGS_ERR_INVALID_ARG;
     if (!(T_k >= 0.f) || g->N < 0 || g->N > 0xffffffffll || g->sh_deg < 0 || g->sh_deg > 3 || g->C_o < 0 ||
         g->C_o > UGS_MAX_CHANNELS)
         return UGS_ERR_INVALID_ARG;
-    if (!g->mask_logit || (reinterpret_cast<uintptr_t>(scratch) & 255)) return UGS_ERR_INVALID_ARG;
-    size_t need;
-    ugs_prune_scratch_size(g->N, &need);
-    if (scratch_bytes < need) return UGS_ERR_INVALID_ARG;
-    hipStream_t s = (hipStream_t)stream;
+    if (!g->mask_logit) return UGS_ERR_INVALID_ARG;
+    return UGS_OK;
+}
+
+// The compaction itself, given a device scratch of prune_scratch_bytes(g->N)
+// bytes (256-byte aligned): keep flags, their exclusive scan and the kept count
+// are all written before they are read, so the scratch needs no clearing.
+int prune_impl(const ugs_gaussians *g, const ugs_gaussian_grads *out, int n_state, const ugs_gaussians *state_in,
+               const ugs_gaussian_grads *state_out, float T_k, int reset_k, char *p, int64_t *n_kept, hipStream_t s)
+{
     const int64_t N = g->N;
     if (N == 0) {
         *n_kept = 0;
         return UGS_OK;
     }
-    char *p = (char *)scratch;
     uint32_t *total = (uint32_t *)p;            // 256 B header
     uint32_t *flags = (uint32_t *)(p + 256);
     uint32_t *pos = flags + N;
@@ -162,6 +156,71 @@ int ugs_prune(const ugs_gaussians *g, const ugs_gaussian_grads *out, int n_state
         return UGS_ERR_HIP;
     *n_kept = (int64_t)h;
     return UGS_OK;
+}
+
+// Library-held scratch of ugs_prune_noalloc: one copy per GPU, kept until the
+// process ends.  Host code never passes `scratch` itself to a kernel (in host
+// code the name is a host-side stand-in, not a device address): it passes the
+// device address that hipGetSymbolAddress returns for the current device,
+// looked up once per device on the first call there.
+constexpr size_t kNoAllocScratchBytes = (size_t)8 * UGS_PRUNE_NOALLOC_MAX_N +
+                                        (size_t)4 * ((UGS_PRUNE_NOALLOC_MAX_N + kScanBlock - 1) / kScanBlock) + 256;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+int noalloc_scratch(char **p)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return UGS_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return UGS_ERR_HIP;
+        g_scratch_dev[dev] = ptr;
+    }
+    *p = (char *)g_scratch_dev[dev];
+    return UGS_OK;
+}
+
+}  // namespace
+}  // namespace ugs
+
+using namespace ugs;
+
+extern "C" {
+
+int ugs_prune_scratch_size(int64_t N, size_t *bytes)
+{
+    if (N < 0 || !bytes) return UGS_ERR_INVALID_ARG;
+    *bytes = prune_scratch_bytes(N);
+    return UGS_OK;
+}
+
+int ugs_prune(const ugs_gaussians *g, const ugs_gaussian_grads *out, int n_state, const ugs_gaussians *state_in,
+              const ugs_gaussian_grads *state_out, float T_k, int reset_k, void *scratch_mem, size_t scratch_bytes,
+              int64_t *n_kept, void *stream)
+{
+    int rc = check_prune_args(g, out, n_state, state_in, state_out, T_k, n_kept);
+    if (rc) return rc;
+    if (!scratch_mem || (reinterpret_cast<uintptr_t>(scratch_mem) & 255)) return UGS_ERR_INVALID_ARG;
+    if (scratch_bytes < prune_scratch_bytes(g->N)) return UGS_ERR_INVALID_ARG;
+    return prune_impl(g, out, n_state, state_in, state_out, T_k, reset_k, (char *)scratch_mem, n_kept,
+                      (hipStream_t)stream);
+}
+
+int ugs_prune_noalloc(const ugs_gaussians *g, const ugs_gaussian_grads *out, int n_state,
+                      const ugs_gaussians *state_in, const ugs_gaussian_grads *state_out, float T_k, int reset_k,
+                      int64_t *n_kept, void *stream)
+{
+    int rc = check_prune_args(g, out, n_state, state_in, state_out, T_k, n_kept);
+    if (rc) return rc;
+    if (g->N > UGS_PRUNE_NOALLOC_MAX_N) return UGS_ERR_UNSUPPORTED;
+    char *p = nullptr;
+    if ((rc = noalloc_scratch(&p))) return rc;
+    return prune_impl(g, out, n_state, state_in, state_out, T_k, reset_k, p, n_kept, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -34,8 +34,8 @@ EXPORTS = ["ugs_default_options", "ugs_create", "ugs_destroy", "ugs_set_options"
            "ugs_project", "ugs_bin_sort", "ugs_check_overflow", "ugs_render_fwd", "ugs_render_bwd",
            "ugs_step_capture", "ugs_step_replay", "ugs_autotune", "ugs_pair_count", "ugs_status_string",
            "ugs_last_hip_error", "ugs_enable_counters", "ugs_read_counters", "ugs_debug_buffer", "ugs_time_stage",
-           "ugs_prune_scratch_size", "ugs_prune", "ugs_default_loss_options", "ugs_loss_scratch_size",
-           "ugs_loss"]
+           "ugs_prune_scratch_size", "ugs_prune", "ugs_prune_noalloc", "ugs_default_loss_options",
+           "ugs_loss_scratch_size", "ugs_loss"]
 
 
 class UgsError(RuntimeError):
@@ -131,6 +131,9 @@ def lib():
         L.ugs_prune.argtypes = [C.POINTER(ugs_gaussians), C.POINTER(ugs_gaussian_grads), C.c_int,
                                 C.POINTER(ugs_gaussians), C.POINTER(ugs_gaussian_grads), C.c_float, C.c_int, P,
                                 C.c_size_t, C.POINTER(C.c_int64), P]
+        L.ugs_prune_noalloc.argtypes = [C.POINTER(ugs_gaussians), C.POINTER(ugs_gaussian_grads), C.c_int,
+                                        C.POINTER(ugs_gaussians), C.POINTER(ugs_gaussian_grads), C.c_float, C.c_int,
+                                        C.POINTER(C.c_int64), P]
         L.ugs_default_loss_options.argtypes = [C.POINTER(ugs_loss_options)]
         L.ugs_default_loss_options.restype = None
         L.ugs_loss_scratch_size.argtypes = [C.POINTER(ugs_camera), C.c_int, C.POINTER(C.c_size_t)]
@@ -295,18 +298,24 @@ def zeros_like_params(g):
     return {k: torch.zeros_like(g[k]) for k in PARAM_KEYS}
 
 
-def prune(g, T_k, reset_k=True, states=()):
+UGS_PRUNE_NOALLOC_MAX_N = 1 << 22
+
+
+def prune(g, T_k, reset_k=True, states=(), noalloc=False):
     """Differentiable pruning (ugs_prune): returns (pruned parameter dict,
     list of pruned state dicts, kept count).  `states` are dicts with the
-    parameter keys (None for absent arrays), laid out like the parameters."""
+    parameter keys (None for absent arrays), laid out like the parameters.
+    noalloc=True calls ugs_prune_noalloc (the library's own scratch array,
+    N <= UGS_PRUNE_NOALLOC_MAX_N) instead of allocating a scratch buffer."""
     import torch
     N = int(g["N"])
     out = {k: torch.empty_like(g[k]) for k in PARAM_KEYS}
     outs_state = [{k: (torch.empty_like(st[k]) if st.get(k) is not None else None) for k in PARAM_KEYS}
                   for st in states]
-    nb = C.c_size_t()
-    _chk(lib().ugs_prune_scratch_size(N, C.byref(nb)), "ugs_prune_scratch_size")
-    scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=g["mean"].device)
+    if not noalloc:
+        nb = C.c_size_t()
+        _chk(lib().ugs_prune_scratch_size(N, C.byref(nb)), "ugs_prune_scratch_size")
+        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=g["mean"].device)
     gs = make_gaussians(g)
     os_ = make_grads(out)
     n_state = len(states)
@@ -318,8 +327,12 @@ def prune(g, T_k, reset_k=True, states=()):
             setattr(sin[k_], key, st[key].data_ptr() if st.get(key) is not None else None)
             setattr(sout[k_], key, so[key].data_ptr() if so.get(key) is not None else None)
     nk = C.c_int64()
-    _chk(lib().ugs_prune(C.byref(gs), C.byref(os_), n_state, sin, sout, float(T_k), int(bool(reset_k)),
-                         C.c_void_p(scratch.data_ptr()), int(nb.value), C.byref(nk), _stream()), "ugs_prune")
+    if noalloc:
+        _chk(lib().ugs_prune_noalloc(C.byref(gs), C.byref(os_), n_state, sin, sout, float(T_k), int(bool(reset_k)),
+                                     C.byref(nk), _stream()), "ugs_prune_noalloc")
+    else:
+        _chk(lib().ugs_prune(C.byref(gs), C.byref(os_), n_state, sin, sout, float(T_k), int(bool(reset_k)),
+                             C.c_void_p(scratch.data_ptr()), int(nb.value), C.byref(nk), _stream()), "ugs_prune")
     n = int(nk.value)
 
     def view(key, t):
