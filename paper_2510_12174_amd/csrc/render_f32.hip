@@ -20,9 +20,9 @@
 //    the FP32 matrix instructions share the FP32 datapath with the vector ALU
 //    (they do not co-issue, unlike the bf16 ones), so every matrix product
 //    spent on an idle entry would cost vector time.
-//  * Channel chunks.  A pass covers CCH channels (forward: up to 128, held as
-//    CCH accumulators per lane; backward: 32, whose upstream gradients live in
-//    registers in the two operand layouts the products need).  Wider C_o runs
+//  * Channel chunks.  A pass covers CCH channels (forward: up to 64, held as
+//    CCH accumulators per lane; backward: 32 or 64, whose upstream gradients
+//    live in registers in the two operand layouts the products need).  Wider C_o runs
 //    further passes over the same lists with a channel offset: a forward pass
 //    repeats the walk to recover the weights and adds only its channels; a
 //    backward chunk pass adds the chunk's dO and its share of the alpha
@@ -32,6 +32,7 @@
 #include <algorithm>
 
 #include "render_common.h"
+
 
 
 namespace ugs {
@@ -47,7 +48,6 @@ __device__ __forceinline__ mf4 mma(float a, float b, mf4 c)
 constexpr int kFRows = 4;   // active entries per forward product (the MFMA's K)
 constexpr int kBGrp = 16;   // active entries per backward group (the MFMA's M)
 constexpr int kSW = 68;     // floats per row of the per-wavefront S / w buffer
-constexpr int kBwdCCH = 32; // channels per backward pass
 
 __host__ __device__ constexpr int feat_stride(int CCH) { return CCH + 4; }
 
@@ -114,15 +114,18 @@ __device__ __forceinline__ float frag_adjoint_sem(bool contrib, float4 r0, float
     return w;
 }
 
-// Stages `n` entries [start, start+n): their 64 B records and the CCH feature
-// channels [c0, c0 + CCH) (zero beyond C_o), rows of feat_stride(CCH) floats.
-template <int NT, int CCH>
+// Stages `n` entries [start, start+n): the first NR float4 of their 64 B
+// records (4: all; 2: mean2d, conic factor, opacity, k and z0, all that the
+// alpha test needs) at a stride of 4 float4, and the CCH feature channels
+// [c0, c0 + CCH) (zero beyond C_o), rows of feat_stride(CCH) floats.
+template <int NT, int CCH, int NR = 4>
 __device__ __forceinline__ void stage_mm(float4 *srec, float *sfeat, const uint32_t *vals, uint32_t start, int n,
                                          const float4 *rec, int64_t recbase, const float *sem, int C_o, int c0)
 {
-    for (int q = threadIdx.x; q < n * 4; q += NT) {
-        const uint32_t id = vals[start + (q >> 2)];
-        srec[q] = rec[(recbase + id) * 4 + (q & 3)];
+    for (int q = threadIdx.x; q < n * NR; q += NT) {
+        const int e = q / NR, k = q - e * NR;
+        const uint32_t id = vals[start + e];
+        srec[4 * e + k] = rec[(recbase + id) * 4 + k];
     }
     for (int q = threadIdx.x; q < n * CCH; q += NT) {
         const int e = q / CCH, c = q - e * CCH;
@@ -142,13 +145,13 @@ __device__ __forceinline__ void stage_mm(float4 *srec, float *sfeat, const uint3
 // colour, depth and the gradient factor, write T_final / n_contrib and the
 // counters; other passes (C_o > CCH) only add their channels.
 template <int TW, int TH, int CCH, int DM, bool MAIN>
-__global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH >= 128 ? 2 : 3))) render_fwd_mm_kernel(
+__global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))) render_fwd_mm_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o, int c0,
     ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles,
     const float *__restrict__ hrec, int half_out, uint32_t *__restrict__ amask, int64_t mwords)
 {
-    static_assert(CCH == 16 || CCH == 32 || CCH == 64 || CCH == 128, "forward pass: 16, 32, 64 or 128 channels");
+    static_assert(CCH == 16 || CCH == 32 || CCH == 64, "forward pass: 16, 32 or 64 channels");
     constexpr int NT = TW * TH, NW = NT / 64, FS = feat_stride(CCH), CPL = CCH / 16;
     constexpr bool HIT = DM == 2;
     constexpr float kd = DM == 1 ? 0.f : 1.f;  // depth form fixed per instantiation
@@ -189,7 +192,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
     for (uint32_t start = range.x; start < range.y; start += (uint32_t)batch) {
         if (__syncthreads_count(done) == NT) break;
         const int n = (int)min((uint32_t)batch, range.y - start);
-        stage_mm<NT, CCH>(srec, sfeat, vals, start, n, rec, recbase, sem, C_o, c0);
+        stage_mm<NT, CCH, MAIN ? 4 : 2>(srec, sfeat, vals, start, n, rec, recbase, sem, C_o, c0);
         stage_hits<NT, HIT>(shh, vals, start, n, hrec, recbase);
         __syncthreads();
         if (__all(done)) continue;  // the other wavefronts may still walk this batch
@@ -323,14 +326,14 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
 }
 
 // ------------------------------------------------------------------ backward
-// One pass over CCH = 32 channels [c0, c0 + 32).  The wavefront walks only its
+// One pass over CCH = 32 or 64 channels [c0, c0 + CCH).  The wavefront walks only its
 // active entries (the forward's activity mask), last first, in groups of 16.
 // The upstream semantic gradients G of its 64 pixels for these channels stay
 // in registers in the two B-operand layouts:
-//   GS[ks][pb] = G[pixel 16 pb + lane % 16][channel 8 (lane / 16) + ks]  (S)
+//   GS[ks][pb] = G[pixel 16 pb + lane % 16][channel KS (lane / 16) + ks]  (S)
 //   GD[ks][cb] = G[pixel 16 (lane / 16) + ks][channel 16 cb + lane % 16] (dO)
-// S[f][p] = sum_c o_f[c] G_p[c]: A[m = f][k] = o_{act f}[8 (lane / 16) + ks]
-// (8 consecutive floats of the staged feature row), output rows f = entries,
+// S[f][p] = sum_c o_f[c] G_p[c]: A[m = f][k] = o_{act f}[KS (lane / 16) + ks]
+// (KS = CCH / 4 consecutive floats of the staged feature row), output rows f = entries,
 // columns p = pixels, stored in the wavefront's S / w buffer.  The reverse walk
 // reads its S there and overwrites it with w.  dO[f][c] = sum_p w_f[p] G_p[c]:
 // A[m = f][k] = w_f[16 (lane / 16) + ks], output D[f][c], added to the
@@ -338,8 +341,8 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
 // fragment adjoint and the 16 record slots; chunk passes (c0 > 0) only the
 // semantic share of the alpha gradient, i.e. record slots 0..5 (mean2d, conic,
 // opacity).
-template <int TW, int TH, int DM, bool MAIN>
-__global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))) render_bwd_mm_kernel(
+template <int TW, int TH, int CCH, int DM, bool MAIN>
+__global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH > 32 ? 2 : 4))) render_bwd_mm_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o, int c0,
     const float *__restrict__ T_final, const uint32_t *__restrict__ n_contrib, const float *__restrict__ up_rgb,
@@ -347,7 +350,8 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
     float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, const float *__restrict__ hrec,
     SemSeed seed, const uint32_t *__restrict__ amask, int64_t mwords)
 {
-    constexpr int CCH = kBwdCCH, NT = TW * TH, FS = feat_stride(CCH);
+    static_assert(CCH == 32 || CCH == 64, "backward pass: 32 or 64 channels");
+    constexpr int NT = TW * TH, FS = feat_stride(CCH);
     constexpr int KS = CCH / 4, NCB = CCH / 16;
     constexpr bool HIT = DM == 2;
     constexpr float kd = DM == 1 ? 0.f : 1.f;
@@ -427,7 +431,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
         const uint32_t start = end - range.x > (uint32_t)batch ? end - (uint32_t)batch : range.x;
         const int n = (int)(end - start);
         __syncthreads();
-        stage_mm<NT, CCH>(srec, sfeat, vals, start, n, rec, recbase, sem, C_o, c0);
+        stage_mm<NT, CCH, MAIN ? 4 : 2>(srec, sfeat, vals, start, n, rec, recbase, sem, C_o, c0);
         for (int q = threadIdx.x; q < n; q += NT) sid[q] = vals[start + q];
         stage_hits<NT, HIT>(shh, vals, start, n, hrec, recbase);
         __syncthreads();
@@ -588,7 +592,7 @@ hipError_t fwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayo
     return hipGetLastError();
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int CCH>
 hipError_t bwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
                          const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg, int batch,
                          int final_buf, int c0, hipStream_t s)
@@ -603,12 +607,10 @@ hipError_t bwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayo
     const SemSeed seed{out.sem, up.sem ? nullptr : up.sem_label, up.sem_scale};
     constexpr int NW = TW * TH / 64;
     const bool hit = pb.depth_mode == 2, main_pass = c0 == 0;
-    const int b = std::min(64, fit_batch(batch, 64 * 1024, [&](int x) {
-        return bwd_mm_lds(x, kBwdCCH, NW, hit);
-    }));
-    const size_t lds = bwd_mm_lds(b, kBwdCCH, NW, hit);
+    const int b = std::min(64, fit_batch(batch, 64 * 1024, [&](int x) { return bwd_mm_lds(x, CCH, NW, hit); }));
+    const size_t lds = bwd_mm_lds(b, CCH, NW, hit);
 #define UGS_BWD_MM(DMV, MAINV)                                                                                    \
-    hipLaunchKernelGGL((render_bwd_mm_kernel<TW, TH, DMV, MAINV>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), \
+    hipLaunchKernelGGL((render_bwd_mm_kernel<TW, TH, CCH, DMV, MAINV>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), \
                        lds, s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, c0, out.T_final, out.n_contrib,   \
                        up.rgb, gd, up.kmap, up.sem, grec, dg.sem, b, (uint32_t)pb.total_tiles, hrec, seed,     \
                        (const uint32_t *)(ws + L.amask), L.amask_words)
@@ -624,8 +626,11 @@ hipError_t bwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayo
     return hipGetLastError();
 }
 
-// Channels per forward pass for C_o channels (9..256): one pass up to 128.
-int fwd_pass_channels(int C_o) { return C_o <= 16 ? 16 : C_o <= 32 ? 32 : C_o <= 64 ? 64 : 128; }
+// Channels per forward pass for C_o channels (9..256): at most 64, so that the
+// accumulators (one register per channel) leave room for four wavefronts per
+// SIMD; 128 channels in one pass (two wavefronts per SIMD) measured 38.4 ms
+// against 32.0 ms for two 64-channel passes on the 3M-Gaussian 16-view step.
+int fwd_pass_channels(int C_o) { return C_o <= 16 ? 16 : C_o <= 32 ? 32 : 64; }
 
 template <int TW, int TH>
 hipError_t fwd_mm_tile(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out,
@@ -637,20 +642,27 @@ hipError_t fwd_mm_tile(const ugs_gaussians &g, const Problem &pb, const WsLayout
         switch (cch) {
         case 16: e = fwd_mm_launch<TW, TH, 16>(g, pb, L, ws, out, batch, counters, final_buf, c0, s); break;
         case 32: e = fwd_mm_launch<TW, TH, 32>(g, pb, L, ws, out, batch, counters, final_buf, c0, s); break;
-        case 64: e = fwd_mm_launch<TW, TH, 64>(g, pb, L, ws, out, batch, counters, final_buf, c0, s); break;
-        default: e = fwd_mm_launch<TW, TH, 128>(g, pb, L, ws, out, batch, counters, final_buf, c0, s); break;
+        default: e = fwd_mm_launch<TW, TH, 64>(g, pb, L, ws, out, batch, counters, final_buf, c0, s); break;
         }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
+// Channels per backward pass: 32 up to 32 channels (upstream in 64 registers,
+// four wavefronts per SIMD), else 64 (128 registers, two wavefronts per SIMD):
+// on the 3M-Gaussian 128-channel step two 64-channel passes take 85.8 ms
+// against 87.8 ms for four 32-channel ones.
+int bwd_pass_channels(int C_o) { return C_o <= 32 ? 32 : 64; }
+
 template <int TW, int TH>
 hipError_t bwd_mm_tile(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out,
                        const ugs_upstream &up, const ugs_gaussian_grads &dg, int batch, int final_buf, hipStream_t s)
 {
-    for (int c0 = 0; c0 < pb.C_o; c0 += kBwdCCH) {
-        hipError_t e = bwd_mm_launch<TW, TH>(g, pb, L, ws, out, up, dg, batch, final_buf, c0, s);
+    const int cch = bwd_pass_channels(pb.C_o);
+    for (int c0 = 0; c0 < pb.C_o; c0 += cch) {
+        hipError_t e = cch == 32 ? bwd_mm_launch<TW, TH, 32>(g, pb, L, ws, out, up, dg, batch, final_buf, c0, s)
+                                 : bwd_mm_launch<TW, TH, 64>(g, pb, L, ws, out, up, dg, batch, final_buf, c0, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -6,6 +6,7 @@ WRITE_SIZE counter runs scaled by a plain copy kernel of known size).
   python -m paper_2510_12174_amd.profsum traffic <fetch counter csv> <write counter csv> \
         <kernel substring> <key> <source file> <command>
   python -m paper_2510_12174_amd.profsum valu <counter csv> <kernel substring> <key> <source file> <command>
+  python -m paper_2510_12174_amd.profsum counters <csv>[,<csv>...] <kernel substring> <key> <source file> <command>
 """
 from __future__ import annotations
 
@@ -98,6 +99,50 @@ def valu(pmc_csv, kernel_sub, key, source, command, simds=1024, xcds=8):
     return entry
 
 
+def counters(csv_paths, kernel_sub, key, source, command, simds=1024, xcds=8):
+    """Per-dispatch SQ counters of one kernel from one or more --pmc passes
+    (medians over dispatches) and the fractions derived from them: VALU issue
+    (a wave64 vector instruction holds a 16-lane SIMD for 4 cycles), FP32
+    matrix-pipe busy (SQ_VALU_MFMA_BUSY_CYCLES over the SIMD cycles), LDS bank
+    conflict cycles over LDS active cycles, and the average resident wavefronts
+    per SIMD (SQ_WAVE_CYCLES counts wave-cycles in units of 4 cycles).
+    GRBM_GUI_ACTIVE is summed over the XCDs.  Stored in profiles/counters.json."""
+    med = {}
+    for path in csv_paths:
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if kernel_sub not in r["Kernel_Name"]:
+                continue
+            d = per.setdefault(r.get("Dispatch_Id"), {})
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        names = {c for d in per.values() for c in d}
+        for c in names:
+            vals = sorted(d[c] for d in per.values() if c in d)
+            med[c] = vals[len(vals) // 2]
+        med.setdefault("_dispatches", len(per))
+    cyc = lambda: med.get("GRBM_GUI_ACTIVE", 0.0) / xcds
+    der = {}
+    if cyc() > 0:
+        if "SQ_INSTS_VALU" in med:
+            der["valu_issue_fraction"] = 4.0 * med["SQ_INSTS_VALU"] / (simds * cyc())
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in med:
+            der["mfma_busy_fraction"] = med["SQ_VALU_MFMA_BUSY_CYCLES"] / (simds * cyc())
+        if "SQ_WAVE_CYCLES" in med:
+            der["waves_per_simd"] = 4.0 * med["SQ_WAVE_CYCLES"] / (simds * cyc())
+    if med.get("SQ_ACTIVE_INST_LDS"):
+        der["lds_bank_conflict_fraction"] = med.get("SQ_LDS_BANK_CONFLICT", 0.0) / med["SQ_ACTIVE_INST_LDS"]
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2510_12174_amd", "csrc", source), "rb").read()).hexdigest()[:16]
+    entry = dict(source_sha=sha, counters={k: v for k, v in sorted(med.items()) if not k.startswith("_")},
+                 derived=der, dispatches=med.get("_dispatches"), command=command)
+    if "valu_issue_fraction" in der:
+        entry["valu_issue_fraction"] = der["valu_issue_fraction"]
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    dd = json.load(open(path)) if os.path.exists(path) else {}
+    dd[key] = entry
+    json.dump(dd, open(path, "w"), indent=1, sort_keys=True)
+    return entry
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         sys.stdout.write(stats(sys.argv[2], sys.argv[3]))
@@ -105,3 +150,6 @@ if __name__ == "__main__":
         print(json.dumps(traffic(*sys.argv[2:8]), indent=1))
     elif sys.argv[1] == "valu":
         print(json.dumps(valu(*sys.argv[2:7]), indent=1))
+    elif sys.argv[1] == "counters":
+        # counters <csv>[,<csv>...] <kernel substring> <key> <source file> <command>
+        print(json.dumps(counters(sys.argv[2].split(","), *sys.argv[3:7]), indent=1))

@@ -1,4 +1,5 @@
-"""Parity at the full workload sizes, in the launch configuration the benchmark
+"""Parity at the full workload sizes (the single-view 100k- and 500k-Gaussian
+workloads and the two 16-view ones), in the launch configuration the benchmark
 times (all views in one captured HIP graph, 16x16 tiles): the oracle evaluates
 sampled pixels one by one (brute force over every Gaussian), and gradients are
 checked with upstream weights that are non-zero only on those pixels."""
@@ -62,7 +63,7 @@ def _sampled(O, workload, per_view, seed):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("workload,per_view", [(4, 24), (5, 12)])
+@pytest.mark.parametrize("workload,per_view", [(2, 96), (3, 96), (4, 24), (5, 12)])
 def test_full_size_sampled(O, workload, per_view):
     g, cams, opts, masks, ora, ups, outs, gr = _sampled(O, workload, per_view, seed=31 + workload)
     worst = {}

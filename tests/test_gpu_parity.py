@@ -348,6 +348,14 @@ def test_forward_only_step(O):
         for x, y in zip(outs, eager_out):
             for k in ("rgb", "depth", "kmap", "normal", "sem"):
                 assert np.array_equal(x[k], y[k]), (rep, k)
+    # and against the oracle directly
+    ora = Hn.oracle_forward(O, g, cams, opts)
+    ms = Hn.masks(O, g, cams, opts, ora)
+    err = Hn.image_errors(outs, ora, ms, normals=False)
+    Hn.say(f"[forward-only w4s] image max-abs against the oracle {err}")
+    for k, e in err.items():
+        if k != "T_final":
+            assert e <= Hn.IMG_TOL, (k, e)
     # the backward needs T_final and n_contrib
     r2 = U.Rasterizer(prune_Tk=float(opts.get("prune_Tk", 0.0)))
     o2 = r2.forward(gd, cams, U.alloc_outputs(cams, g["C_o"], state=False))
@@ -384,6 +392,23 @@ def test_half_outputs_forward_only(O, kind):
             assert a.dtype == np.float16 and np.array_equal(a.view(np.uint16), b.view(np.uint16)), (rep, k)
         assert np.array_equal(out["depth"].cpu().numpy(), ref["depth"].cpu().numpy())
     Hn.say(f"[{kind}] half outputs equal the rounded FP32 outputs")
+    # against the oracle directly: within the image tolerance plus the binary16
+    # rounding (half an ulp, 2^-11 relative)
+    ora = Hn.oracle_forward(O, g, cams, opts)
+    ms = Hn.masks(O, g, cams, opts, ora)
+    P = U.pixel_offsets(cams)
+    worst = 0.0
+    for v, (cam, o, m) in enumerate(zip(cams, ora, ms)):
+        ok = ~m["img"]
+        for k, c in (("rgb", 3), ("kmap", 1), ("sem", C_o)):
+            if c == 0:
+                continue
+            a = out[k][c * P[v]:c * P[v + 1]].cpu().numpy().astype(np.float64).reshape(c, cam["H"], cam["W"])
+            b = np.asarray(o[k], np.float64).reshape(c, cam["H"], cam["W"])
+            r = (np.abs(a - b) - 2.0 ** -11 * np.abs(b))[:, ok]
+            worst = max(worst, float(r.max()) if r.size else 0.0)
+    Hn.say(f"[{kind}] half outputs against the oracle: max(|err| - 2^-11 |ref|) = {worst:.3g}")
+    assert worst <= Hn.IMG_TOL
     ups = Hn.stack_upstream(Hn.scenes.upstream(cams, C_o, seed=3), C_o)
     full = U.alloc_outputs(cams, C_o, half=True)
     with pytest.raises(U.UgsError):
