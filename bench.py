@@ -101,6 +101,21 @@ def profile_entry(fname, name, workload):
     return d
 
 
+def tile_balance(clk):
+    """Load balance of one compositing launch from its per-tile workgroup start
+    and end times (100 MHz ticks): the launch span, the tail after the last
+    tile started (the time the hardware dispatch can no longer fill the
+    machine), and the tile-duration distribution."""
+    st, en = clk[:, 0].astype(np.int64), clk[:, 1].astype(np.int64)
+    span = float(en.max() - st.min())
+    tail = float(en.max() - st.max())
+    dur = (en - st).astype(np.float64)
+    return dict(tiles=int(clk.shape[0]), span_ms=round(span / 1e5, 3), tail_ms=round(tail / 1e5, 3),
+                tail_frac=round(tail / span, 4) if span > 0 else None,
+                tile_ms=dict(median=round(pct(dur, 50) / 1e5, 4), p99=round(pct(dur, 99) / 1e5, 4),
+                             max=round(float(dur.max()) / 1e5, 4)))
+
+
 def device_upstream(torch, Px, C_o, seed):
     """Upstream gradients N(0, 1) per output element, drawn on the device."""
     gen = torch.Generator(device="cuda").manual_seed(seed)
@@ -403,15 +418,23 @@ def main():
         tuned = rast.autotune(g, cams, out, up, grads, cache=False)  # always time here
         log(f"[bench] autotune -> {tuned}")
 
-    # counters for the FLOP accounting (one eager forward)
+    # counters for the FLOP accounting (one eager forward) and the per-tile
+    # workgroup times of the compositing kernels (one eager forward + backward)
     P = rast.project_and_sort(g, cams)
     rast.enable_counters(True)
     rast.forward(g, cams, out)
     F_eval, F_contrib = rast.read_counters()
-    rast.enable_counters(False)
     touched = rast.debug_buffer("touched")
     V_rec = int((touched > 0).sum().item())
+    rast.backward(g, out, up, grads)
+    torch.cuda.synchronize()
+    balance = None
+    if C_o > 8 and not (bf16 and C_o <= 32):
+        balance = {k: tile_balance(rast.debug_buffer(b).cpu().numpy())
+                   for k, b in (("render_fwd", "tile_clock_fwd"), ("render_bwd", "tile_clock_bwd"))}
+    rast.enable_counters(False)
     log(f"[bench] pairs P={P} visible records={V_rec} evaluated={F_eval} contributing={F_contrib}")
+    log(f"[bench] tile balance {balance}")
 
     # per-stage durations (one eager step each) to find the dominant kernel
     ev = HipEvents()
@@ -581,6 +604,7 @@ def main():
                forward_only=fwd_only, prune=prune_res, loss=loss_res, depth_modes=depth_modes,
                step_hbm=dict(alg_bytes=int(b_alg), frac=round(b_alg / t_batched / PEAK_HBM, 4)),
                counts=dict(pairs=P, records=V_rec, evaluated=F_eval, contributing=F_contrib),
+               tile_balance=balance,
                stage_ms={k: round(v, 4) for k, v in stage_ms.items()},
                roofline=roof, parity=None, cpu_baseline=None, secondary=None)
     if not args.no_cpu_baseline:

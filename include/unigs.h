@@ -261,7 +261,10 @@ int ugs_time_stage(ugs_ctx *ctx, int stage, void *ev_start, void *ev_stop);
  *   4 sorted values (Gaussian index), uint32[P], bin_sort;
  *   5 tile ranges, uint32[total tiles][2] = [start, end), bin_sort;
  *   6 per-view gradient records, float[V*N][16], render_bwd;
- *   7 depth gradient incl. the normal branch, float[total pixels], render_bwd.
+ *   7 depth gradient incl. the normal branch, float[total pixels], render_bwd;
+ *   8, 9 start and end time of each tile's workgroup in the forward and the
+ *     backward compositing (9..256 channels, counters enabled), uint64[total
+ *     tiles][2], in ticks of the 100 MHz GPU real-time clock.
  * Counts 3 and 4 read the pair count back (synchronises `stream`). */
 int ugs_debug_buffer(ugs_ctx *ctx, void *ws, int which, void *stream, void **dev_ptr, int64_t *count);
 
@@ -271,7 +274,10 @@ const char *ugs_last_hip_error(const ugs_ctx *ctx);
 
 /* Kernel-level counters for roofline accounting: after a render_fwd, the number
  * of (pixel, list entry) evaluations and of contributing fragments over all
- * views (synchronises; counting adds atomics, so it is off unless enabled). */
+ * views (synchronises; counting adds atomics, so it is off unless enabled).
+ * While enabled, the compositing kernels for 9..256 channels (first pass of
+ * the forward and of the backward) also record each (view, tile) workgroup's
+ * start and end time, read back with ugs_debug_buffer 8 and 9. */
 int ugs_enable_counters(ugs_ctx *ctx, int on);
 int ugs_read_counters(ugs_ctx *ctx, void *ws, void *stream, int64_t *evaluated, int64_t *contributing);
 

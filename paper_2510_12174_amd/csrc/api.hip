@@ -259,6 +259,7 @@ WsLayout make_layout(const Problem &pb, int64_t pair_cap)
     L.nadj = take(pix * 12 * 4);
     L.amask_words = (int64_t)(P / 32 + 4);
     L.amask = take((size_t)kMaskPlanes * L.amask_words * 4);
+    L.tclk = take((size_t)pb.total_tiles * 4 * 8);  // forward, backward: start and end per tile
     L.total = o;
     return L;
 }
@@ -488,7 +489,7 @@ int step_stage(ugs_ctx *ctx, const StepArgs &a, int st, hipStream_t s)
         if ((rc = check_bwd(ctx, a.g, a.ws, a.out, a.up, a.dg))) return rc;
         StageTimer tm(ctx, 6, s);
         HIPCHK(ctx, launch_render_bwd(*a.g, ctx->pb, ctx->L, ctx->ws, *a.out, *a.up, *a.dg,
-                                      auto_batch(ctx->opt, a.g->C_o), ctx->final_buf, s));
+                                      auto_batch(ctx->opt, a.g->C_o), ctx->final_buf, ctx->counters, s));
         return UGS_OK;
     }
     case 7: {
@@ -907,6 +908,8 @@ int ugs_debug_buffer(ugs_ctx *ctx, void *ws, int which, void *stream, void **dev
     case 5: *dev_ptr = b + L.ranges; *count = L.total_tiles; return UGS_OK;
     case 6: *dev_ptr = b + L.grec; *count = L.VN; return UGS_OK;
     case 7: *dev_ptr = b + L.gd; *count = L.total_pix; return UGS_OK;
+    case 8: *dev_ptr = b + L.tclk; *count = L.total_tiles; return UGS_OK;
+    case 9: *dev_ptr = b + L.tclk + (size_t)L.total_tiles * 16; *count = L.total_tiles; return UGS_OK;
     default: return UGS_ERR_INVALID_ARG;
     }
 }

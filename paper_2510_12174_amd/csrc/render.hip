@@ -832,10 +832,10 @@ hipError_t launch_render_fwd(const ugs_gaussians &g, const Problem &pb, const Ws
 
 hipError_t launch_render_bwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
                              const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg,
-                             int batch, int final_buf, hipStream_t s)
+                             int batch, int final_buf, bool counters, hipStream_t s)
 {
     if (pb.total_tiles == 0) return hipSuccess;
-    if (use_f32_mm(pb)) return launch_render_bwd_mm(g, pb, L, ws, out, up, dg, batch, final_buf, s);
+    if (use_f32_mm(pb)) return launch_render_bwd_mm(g, pb, L, ws, out, up, dg, batch, final_buf, counters, s);
     int cp = channel_pad(pb.C_o);
     if (pb.tile_w == 8 && pb.tile_h == 8) return bwd_co<8, 8>(cp, g, pb, L, ws, out, up, dg, batch, final_buf, s);
     if (pb.tile_w == 32 && pb.tile_h == 8) return bwd_co<32, 8>(cp, g, pb, L, ws, out, up, dg, batch, final_buf, s);

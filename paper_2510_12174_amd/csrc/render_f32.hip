@@ -149,7 +149,8 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ vals, const float4 *__restrict__ rec, const float *__restrict__ sem, int C_o, int c0,
     ugs_outputs out, int batch, DevCounters *__restrict__ cnt, int count, uint32_t ntiles,
-    const float *__restrict__ hrec, int half_out, uint32_t *__restrict__ amask, int64_t mwords)
+    const float *__restrict__ hrec, int half_out, uint32_t *__restrict__ amask, int64_t mwords,
+    unsigned long long *__restrict__ tclk)
 {
     static_assert(CCH == 16 || CCH == 32 || CCH == 64, "forward pass: 16, 32 or 64 channels");
     constexpr int NT = TW * TH, NW = NT / 64, FS = feat_stride(CCH), CPL = CCH / 16;
@@ -164,6 +165,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
     const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    if (tclk && threadIdx.x == 0) tclk[2 * tile] = __builtin_amdgcn_s_memrealtime();
     const uint2 range = ranges[tile];
     const float fx = (float)ti.px, fy = (float)ti.py;
     const int64_t recbase = (int64_t)ti.v * N;
@@ -310,6 +312,10 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
             }
         }
     }
+    if (tclk) {
+        __syncthreads();
+        if (threadIdx.x == 0) tclk[2 * tile + 1] = __builtin_amdgcn_s_memrealtime();
+    }
     if constexpr (MAIN) {
         if (count) {
             unsigned long long e = n_eval, c = n_con;
@@ -348,7 +354,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
     const float *__restrict__ T_final, const uint32_t *__restrict__ n_contrib, const float *__restrict__ up_rgb,
     const float *__restrict__ gD_img, const float *__restrict__ up_kmap, const float *__restrict__ up_sem,
     float *__restrict__ grec, float *__restrict__ dsem, int batch, uint32_t ntiles, const float *__restrict__ hrec,
-    SemSeed seed, const uint32_t *__restrict__ amask, int64_t mwords)
+    SemSeed seed, const uint32_t *__restrict__ amask, int64_t mwords, unsigned long long *__restrict__ tclk)
 {
     static_assert(CCH == 32 || CCH == 64, "backward pass: 32 or 64 channels");
     constexpr int NT = TW * TH, FS = feat_stride(CCH);
@@ -366,6 +372,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
     const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
     if (tile >= ntiles) return;
     const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    if (tclk && threadIdx.x == 0) tclk[2 * tile] = __builtin_amdgcn_s_memrealtime();
     const uint2 range = ranges[tile];
     const float fx = (float)ti.px, fy = (float)ti.py;
     const int64_t recbase = (int64_t)ti.v * N;
@@ -541,6 +548,10 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
         }
         end = start;
     }
+    if (tclk) {
+        __syncthreads();
+        if (threadIdx.x == 0) tclk[2 * tile + 1] = __builtin_amdgcn_s_memrealtime();
+    }
 }
 
 // Largest batch (a multiple of 16, at most `want`) whose LDS fits `cap` bytes.
@@ -568,6 +579,7 @@ hipError_t fwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayo
     const int b = fit_batch(batch, 64 * 1024, [&](int x) { return fwd_mm_lds(x, CCH, NW, hit); });
     const size_t lds = fwd_mm_lds(b, CCH, NW, hit);
     const bool main_pass = c0 == 0;
+    auto tclk = (counters && main_pass) ? (unsigned long long *)(ws + L.tclk) : nullptr;
     // the activity mask for the backward: written by the first pass of a forward
     // that keeps the backward's state (T_final, n_contrib)
     uint32_t *amask = nullptr;
@@ -579,7 +591,7 @@ hipError_t fwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayo
 #define UGS_FWD_MM(DMV, MAINV)                                                                                  \
     hipLaunchKernelGGL((render_fwd_mm_kernel<TW, TH, CCH, DMV, MAINV>), dim3(xcd_grid(pb.total_tiles)),        \
                        dim3(TW * TH), lds, s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, c0, out, b, cnt, \
-                       (int)counters, (uint32_t)pb.total_tiles, hrec, pb.half_out, amask, L.amask_words)
+                       (int)counters, (uint32_t)pb.total_tiles, hrec, pb.half_out, amask, L.amask_words, tclk)
     if (main_pass) {
         if (pb.depth_mode == 2) UGS_FWD_MM(2, true);
         else if (pb.depth_mode == 1) UGS_FWD_MM(1, true);
@@ -595,7 +607,7 @@ hipError_t fwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayo
 template <int TW, int TH, int CCH>
 hipError_t bwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
                          const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg, int batch,
-                         int final_buf, int c0, hipStream_t s)
+                         int final_buf, int c0, bool counters, hipStream_t s)
 {
     auto cams = (const DevCam *)(ws + L.cams);
     auto ranges = (const uint2 *)(ws + L.ranges);
@@ -607,13 +619,14 @@ hipError_t bwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayo
     const SemSeed seed{out.sem, up.sem ? nullptr : up.sem_label, up.sem_scale};
     constexpr int NW = TW * TH / 64;
     const bool hit = pb.depth_mode == 2, main_pass = c0 == 0;
+    auto tclk = (counters && main_pass) ? (unsigned long long *)(ws + L.tclk + (size_t)pb.total_tiles * 16) : nullptr;
     const int b = std::min(64, fit_batch(batch, 64 * 1024, [&](int x) { return bwd_mm_lds(x, CCH, NW, hit); }));
     const size_t lds = bwd_mm_lds(b, CCH, NW, hit);
 #define UGS_BWD_MM(DMV, MAINV)                                                                                    \
     hipLaunchKernelGGL((render_bwd_mm_kernel<TW, TH, CCH, DMV, MAINV>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), \
                        lds, s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, c0, out.T_final, out.n_contrib,   \
                        up.rgb, gd, up.kmap, up.sem, grec, dg.sem, b, (uint32_t)pb.total_tiles, hrec, seed,     \
-                       (const uint32_t *)(ws + L.amask), L.amask_words)
+                       (const uint32_t *)(ws + L.amask), L.amask_words, tclk)
     if (main_pass) {
         if (pb.depth_mode == 2) UGS_BWD_MM(2, true);
         else if (pb.depth_mode == 1) UGS_BWD_MM(1, true);
@@ -657,12 +670,13 @@ int bwd_pass_channels(int C_o) { return C_o <= 32 ? 32 : 64; }
 
 template <int TW, int TH>
 hipError_t bwd_mm_tile(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out,
-                       const ugs_upstream &up, const ugs_gaussian_grads &dg, int batch, int final_buf, hipStream_t s)
+                       const ugs_upstream &up, const ugs_gaussian_grads &dg, int batch, int final_buf, bool counters,
+                       hipStream_t s)
 {
     const int cch = bwd_pass_channels(pb.C_o);
     for (int c0 = 0; c0 < pb.C_o; c0 += cch) {
-        hipError_t e = cch == 32 ? bwd_mm_launch<TW, TH, 32>(g, pb, L, ws, out, up, dg, batch, final_buf, c0, s)
-                                 : bwd_mm_launch<TW, TH, 64>(g, pb, L, ws, out, up, dg, batch, final_buf, c0, s);
+        hipError_t e = cch == 32 ? bwd_mm_launch<TW, TH, 32>(g, pb, L, ws, out, up, dg, batch, final_buf, c0, counters, s)
+                                 : bwd_mm_launch<TW, TH, 64>(g, pb, L, ws, out, up, dg, batch, final_buf, c0, counters, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -681,12 +695,14 @@ hipError_t launch_render_fwd_mm(const ugs_gaussians &g, const Problem &pb, const
 
 hipError_t launch_render_bwd_mm(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
                                 const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg,
-                                int batch, int final_buf, hipStream_t s)
+                                int batch, int final_buf, bool counters, hipStream_t s)
 {
     if (pb.total_tiles == 0) return hipSuccess;
-    if (pb.tile_w == 8 && pb.tile_h == 8) return bwd_mm_tile<8, 8>(g, pb, L, ws, out, up, dg, batch, final_buf, s);
-    if (pb.tile_w == 32 && pb.tile_h == 8) return bwd_mm_tile<32, 8>(g, pb, L, ws, out, up, dg, batch, final_buf, s);
-    return bwd_mm_tile<16, 16>(g, pb, L, ws, out, up, dg, batch, final_buf, s);
+    if (pb.tile_w == 8 && pb.tile_h == 8)
+        return bwd_mm_tile<8, 8>(g, pb, L, ws, out, up, dg, batch, final_buf, counters, s);
+    if (pb.tile_w == 32 && pb.tile_h == 8)
+        return bwd_mm_tile<32, 8>(g, pb, L, ws, out, up, dg, batch, final_buf, counters, s);
+    return bwd_mm_tile<16, 16>(g, pb, L, ws, out, up, dg, batch, final_buf, counters, s);
 }
 
 }  // namespace ugs

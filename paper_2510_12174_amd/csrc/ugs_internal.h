@@ -64,7 +64,7 @@ struct DevCounters {
 
 struct WsLayout {
     size_t cams, rec, hrec, rect, touched, voff, poff, tsorted, dkey0, dkey1, didx0, didx1, vlist, scan_part, keys0, keys1,
-        vals0, vals1, hist, digit_tot, ranges, grec, gd, nadj, amask, counters, total;
+        vals0, vals1, hist, digit_tot, ranges, grec, gd, nadj, amask, tclk, counters, total;
     int64_t N, VN, total_tiles, total_pix, pair_cap;
     int64_t amask_words;  // 32-bit words per plane of the activity mask
     int V, nb_scan, depth_bits, tile_bits;
@@ -104,13 +104,15 @@ hipError_t launch_render_fwd(const ugs_gaussians &g, const Problem &pb, const Ws
                              const ugs_outputs &out, int batch, bool counters, int final_buf, hipStream_t s);
 hipError_t launch_render_bwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
                              const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg,
-                             int batch, int final_buf, hipStream_t s);
+                             int batch, int final_buf, bool counters, hipStream_t s);
 // 9..256 channels, semantic contractions on the FP32 matrix cores
+// With `counters` set, the first (main) pass of each also writes each tile
+// workgroup's start and end time (s_memrealtime, 100 MHz) to L.tclk.
 hipError_t launch_render_fwd_mm(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
                                 const ugs_outputs &out, int batch, bool counters, int final_buf, hipStream_t s);
 hipError_t launch_render_bwd_mm(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
                                 const ugs_outputs &out, const ugs_upstream &up, const ugs_gaussian_grads &dg,
-                                int batch, int final_buf, hipStream_t s);
+                                int batch, int final_buf, bool counters, hipStream_t s);
 hipError_t launch_normal_fwd(const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out,
                              const ugs_options &opt, hipStream_t s);
 hipError_t launch_normal_bwd(const Problem &pb, const WsLayout &L, char *ws, const ugs_outputs &out,
@@ -123,7 +125,9 @@ hipError_t launch_scan_flags(const uint32_t *flags, int64_t n, uint32_t *part, u
 // Which record-index buffer (0: didx0, 1: didx1) holds the depth-sorted visible
 // records after launch_binsort (the depth sort flips buffers once per 8 bits).
 // L.vlist holds the same records in index order.
-inline int depth_sort_buffer(const WsLayout &L) { return ((L.depth_bits + 7) / 8) & 1; }
+// Passes of the LSD radix sort over `bits` key bits (digits of at most 8 bits).
+inline int radix_passes(int bits) { return (bits + 7) / 8; }
+inline int depth_sort_buffer(const WsLayout &L) { return radix_passes(L.depth_bits) & 1; }
 int channel_pad(int C_o);
 
 // index of the view owning a global tile (V small: linear scan over tile_base)
