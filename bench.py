@@ -36,8 +36,9 @@ METRIC = "fwd+bwd megapixels/sec (all modalities), batched vs per-view, at oracl
 PEAK_FP32 = 157.3e12   # MI355X FP32 vector (and FP32 matrix), FLOP/s
 PEAK_HBM = 8.0e12      # MI355X HBM3E, B/s
 STAGES = ["project", "bin_sort", "render_fwd", "normal_fwd", "normal_bwd", "render_bwd", "project_bwd"]
-KERNEL_SOURCE = {"project": "project.hip", "bin_sort": "binsort.hip", "render_fwd": "render_f32.hip",
-                 "normal_fwd": "normal.hip", "normal_bwd": "normal.hip", "render_bwd": "render_f32.hip",
+RENDER_SOURCES = "render_f32.hip,render_common.h"
+KERNEL_SOURCE = {"project": "project.hip", "bin_sort": "binsort.hip", "render_fwd": RENDER_SOURCES,
+                 "normal_fwd": "normal.hip", "normal_bwd": "normal.hip", "render_bwd": RENDER_SOURCES,
                  "project_bwd": "project.hip"}
 IMG_TOL, GRAD_REL, DELTA = 1e-4, 1e-3, 1e-5
 
@@ -85,8 +86,10 @@ def algorithmic(N, V_rec, P, Px, C_o, sh_deg, F_eval, F_contrib):
 
 
 def source_sha(name):
-    p = os.path.join(ROOT, "paper_2510_12174_amd", "csrc", KERNEL_SOURCE[name])
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCE[name].split(","):
+        h.update(open(os.path.join(ROOT, "paper_2510_12174_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def profile_entry(fname, name, workload):
@@ -99,6 +102,17 @@ def profile_entry(fname, name, workload):
     if not d or d.get("source_sha") != source_sha(name):
         return None
     return d
+
+
+def stage_launches(stage, C_o, bf16):
+    """Kernel launches that make up one compositing stage: the FP32 matrix-core
+    kernels take the semantic channels in passes (forward: up to 64 per pass,
+    backward: 32 when there are at most 32, else 64), the first pass also doing
+    the colour, depth and alpha work."""
+    if stage not in ("render_fwd", "render_bwd") or C_o <= 8 or (bf16 and C_o <= 32):
+        return 1
+    per = 64 if stage == "render_fwd" else (32 if C_o <= 32 else 64)
+    return -(-C_o // per)
 
 
 def tile_balance(clk):
@@ -583,10 +597,11 @@ def main():
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM / 1e9, unit="GB/s",
                     frac=round(achieved * 1e9 / PEAK_HBM, 4))
     tr = profile_entry("traffic.json", dominant, wl)
-    va = profile_entry("valu.json", dominant, wl)
-    roof.update(kernel=dominant, ms=round(k_ms, 4), ms_median=round(float(np.median(kern)), 4),
+    co = profile_entry("counters.json", dominant, wl)
+    roof.update(kernel=dominant, launches=stage_launches(dominant, C_o, bf16),
+                ms=round(k_ms, 4), ms_median=round(float(np.median(kern)), 4),
                 traffic=None if tr is None else tr.get("bytes_per_launch"),
-                valu_issue=None if va is None else round(va["valu_issue_fraction"], 4),
+                counters=None if co is None else {k: round(v, 4) for k, v in co["derived"].items()},
                 flops_per_launch=None if fl is None else float(fl))
 
     res = dict(metric=METRIC, value=round(Px / t_batched / 1e6, 2), unit="MP/s", n_gpus=1, steps=args.steps,

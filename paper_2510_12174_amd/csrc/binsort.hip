@@ -301,10 +301,23 @@ __global__ void __launch_bounds__(256) walk_pairs(const DevCam *__restrict__ cam
     }
 }
 
+// Digit of `width` (<= 8) bits at `shift`.
 template <typename K>
-__device__ __forceinline__ uint32_t digit_of(K key, int shift)
+__device__ __forceinline__ uint32_t digit_of(K key, int shift, int width)
 {
-    return (uint32_t)(key >> shift) & 255u;
+    return (uint32_t)(key >> shift) & ((1u << width) - 1u);
+}
+
+// Lanes of the wavefront whose digit equals this lane's (`valid` lanes only):
+// one ballot per digit bit.  `width` is uniform across the wavefront.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int width)
+{
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < width; ++b) {
+        const uint64_t m = __ballot((d >> b) & 1u);
+        peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    return peers;
 }
 
 // The sort runs with one wavefront per block (kSortThreads = 64) and a fixed
@@ -314,10 +327,13 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift)
 // kSortUnroll groups of 64 keys before using any of them.
 constexpr int kSortUnroll = 8;
 
-// Per-block digit histogram of the block's chunk.
+// Per-block digit histogram of the block's chunk: one LDS atomic per key,
+// except for digits of fewer than 4 bits, where so few counters would
+// serialise the atomics -- there equal digits within a group of 64 keys are
+// counted once per group (by the lowest such lane).
 template <typename K>
 __global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__ keys, const uint32_t *__restrict__ n_dev,
-                                                           int shift, uint32_t *__restrict__ hist)
+                                                           int shift, int width, uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t h[256];
     for (int d = threadIdx.x; d < 256; d += kSortThreads) h[d] = 0;
@@ -332,9 +348,20 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__
             const uint64_t i = tb + u * kSortThreads + threadIdx.x;
             key[u] = i < b1 ? keys[i] : K(0);
         }
+        if (width >= 4) {
 #pragma unroll
-        for (int u = 0; u < kSortUnroll; ++u)
-            if (tb + u * kSortThreads + threadIdx.x < b1) atomicAdd(&h[digit_of(key[u], shift)], 1u);
+            for (int u = 0; u < kSortUnroll; ++u)
+                if (tb + u * kSortThreads + threadIdx.x < b1) atomicAdd(&h[digit_of(key[u], shift, width)], 1u);
+        } else {
+            const uint64_t lt = __lanemask_lt();
+#pragma unroll
+            for (int u = 0; u < kSortUnroll; ++u) {
+                const bool valid = tb + u * kSortThreads + threadIdx.x < b1;
+                const uint32_t d = digit_of(key[u], shift, width);
+                const uint64_t peers = digit_peers(d, valid, width);
+                if (valid && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+            }
+        }
     }
     __syncthreads();
     for (int d = threadIdx.x; d < 256; d += kSortThreads) hist[(size_t)d * kSortBlocks + blockIdx.x] = h[d];
@@ -377,7 +404,7 @@ template <typename K>
 __global__ void __launch_bounds__(kScatThreads) radix_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                               K *__restrict__ kout, uint32_t *__restrict__ vout,
                                                               const uint32_t *__restrict__ n_dev, int shift,
-                                                              const uint32_t *__restrict__ hist,
+                                                              int width, const uint32_t *__restrict__ hist,
                                                               const uint32_t *__restrict__ digit_tot)
 {
     __shared__ uint32_t gbase[256], loff[256], tot[256], lds4[4];
@@ -411,13 +438,8 @@ __global__ void __launch_bounds__(kScatThreads) radix_scatter(const K *__restric
         for (int i = 0; i < kScatRounds; ++i) {
             const uint32_t li = (uint32_t)(wave * kScatQuarter + i * 64 + lane);
             const bool valid = li < nt;
-            const uint32_t d = digit_of(key[i], shift);
-            uint64_t peers = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                uint64_t m = __ballot((d >> b) & 1u);
-                peers &= ((d >> b) & 1u) ? m : ~m;
-            }
+            const uint32_t d = digit_of(key[i], shift, width);
+            const uint64_t peers = digit_peers(d, valid, width);
             const uint32_t rank = __popcll(peers & lt);
             pw[i] = valid ? wcnt[wave][d] + rank : 0u;
             __builtin_amdgcn_wave_barrier();
@@ -442,7 +464,7 @@ __global__ void __launch_bounds__(kScatThreads) radix_scatter(const K *__restric
         for (int i = 0; i < kScatRounds; ++i) {
             const uint32_t li = (uint32_t)(wave * kScatQuarter + i * 64 + lane);
             if (li < nt) {
-                const uint32_t d = digit_of(key[i], shift);
+                const uint32_t d = digit_of(key[i], shift, width);
                 const uint32_t lp = loff[d] + wcnt[wave][d] + pw[i];
                 skey[lp] = key[i];
                 sval[lp] = val[i];
@@ -451,7 +473,7 @@ __global__ void __launch_bounds__(kScatThreads) radix_scatter(const K *__restric
         __syncthreads();
         for (uint32_t i = (uint32_t)t; i < nt; i += kScatThreads) {
             const K k = skey[i];
-            const uint32_t d = digit_of(k, shift);
+            const uint32_t d = digit_of(k, shift, width);
             const uint32_t g = gbase[d] + (i - loff[d]);
             kout[g] = k;
             vout[g] = sval[i];
@@ -503,7 +525,9 @@ void scan(const ScanIn &si, int nb, uint32_t *part, uint32_t *out, int64_t cap, 
 }
 
 // Sorts (keys, vals) in place over bits [0, bits); returns the buffer index
-// (0: k0/v0, 1: k1/v1) holding the result.
+// (0: k0/v0, 1: k1/v1) holding the result.  The passes split the bits evenly
+// (17 bits: 6 + 6 + 5) rather than 8 + 8 + 1: a scatter pass writes one run per
+// digit and LDS tile, and fewer digits per pass make those runs longer.
 template <typename K>
 int radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t *n_dev, int bits, uint32_t *hist,
                uint32_t *dtot, hipStream_t s)
@@ -511,13 +535,16 @@ int radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t *n_dev, 
     K *k[2] = {k0, k1};
     uint32_t *v[2] = {v0, v1};
     int cur = 0;
-    for (int shift = 0; shift < bits; shift += 8) {
+    const int passes = radix_passes(bits);
+    for (int p = 0, shift = 0; p < passes; ++p) {
+        const int width = (bits - shift + (passes - p) - 1) / (passes - p);
         hipLaunchKernelGGL(radix_hist<K>, dim3(kSortBlocks), dim3(kSortThreads), 0, s, (const K *)k[cur], n_dev, shift,
-                           hist);
+                           width, hist);
         hipLaunchKernelGGL(radix_scan_digit, dim3(256), dim3(256), 0, s, hist, dtot);
         hipLaunchKernelGGL(radix_scatter<K>, dim3(kSortBlocks), dim3(kScatThreads), 0, s, (const K *)k[cur],
-                           (const uint32_t *)v[cur], k[cur ^ 1], v[cur ^ 1], n_dev, shift, (const uint32_t *)hist,
-                           (const uint32_t *)dtot);
+                           (const uint32_t *)v[cur], k[cur ^ 1], v[cur ^ 1], n_dev, shift, width,
+                           (const uint32_t *)hist, (const uint32_t *)dtot);
+        shift += width;
         cur ^= 1;
     }
     return cur;

@@ -24,8 +24,10 @@
 //    CCH accumulators per lane; backward: 32 or 64, whose upstream gradients
 //    live in registers in the two operand layouts the products need).  Wider C_o runs
 //    further passes over the same lists with a channel offset: a forward pass
-//    repeats the walk to recover the weights and adds only its channels; a
-//    backward chunk pass adds the chunk's dO and its share of the alpha
+//    recovers the weights and adds only its channels (in a training forward it
+//    visits only the entries of the first pass's activity mask, each pixel up
+//    to its contributor count; otherwise it repeats the walk); a backward
+//    chunk pass adds the chunk's dO and its share of the alpha
 //    gradient (the alpha gradient is linear in the semantic upstream, so the
 //    chunks' shares add up to the full one: dL/dalpha_i = T_i s_i -
 //    A_i / (1 - alpha_i) with s_i and A_i sums over channels).
@@ -191,7 +193,83 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
         mbits = 0;
     };
 
-    for (uint32_t start = range.x; start < range.y; start += (uint32_t)batch) {
+    // the weights' matrix product for the nrow buffered rows (rows past nrow
+    // zeroed first)
+    auto flush_rows = [&](int nrow, int rid) {
+        for (int r = nrow; r < kFRows; ++r) wb[r * 64 + wslot] = 0.f;
+        __builtin_amdgcn_wave_barrier();
+        const float4 bw = *reinterpret_cast<const float4 *>(wb + h16 * 64 + l16 * 4);
+        float a[CPL];
+        lds_row<CPL>(sfeat + rid * FS + CPL * l16, a);
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            acc[q][0] = mma(a[q], bw.x, acc[q][0]);
+            acc[q][1] = mma(a[q], bw.y, acc[q][1]);
+            acc[q][2] = mma(a[q], bw.z, acc[q][2]);
+            acc[q][3] = mma(a[q], bw.w, acc[q][3]);
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+
+    if (!MAIN && amask) {
+        // A further channel pass of a forward that keeps the backward's state:
+        // the first pass has left this wavefront's activity mask and every
+        // pixel's contributor count, so the walk visits only the marked
+        // entries and stops each pixel at its count.  The weights are the
+        // first pass's (same alpha, same FP64 transmittance updates in the
+        // same order); entries no lane takes change no weight.
+        uint32_t lastp = 0;
+        if (ti.inside) {
+            const uint32_t rel = out.n_contrib[ti.off + ti.pix];
+            lastp = rel ? range.x + rel : 0u;
+        }
+        __shared__ uint32_t s_end;
+        if (threadIdx.x == 0) s_end = 0;
+        __syncthreads();
+        if (lastp) atomicMax(&s_end, lastp);
+        __syncthreads();
+        const uint32_t end_all = s_end;
+        for (uint32_t start = range.x; start < end_all; start += (uint32_t)batch) {
+            const int n = (int)min((uint32_t)batch, end_all - start);
+            __syncthreads();
+            stage_mm<NT, CCH, 2>(srec, sfeat, vals, start, n, rec, recbase, sem, C_o, c0);
+            __syncthreads();
+            int nrow = 0, rid = 0;
+            for (int w0 = 0; w0 < n; w0 += 64) {
+                // mask bits of entries start + w0 .. start + w0 + 63
+                const uint32_t e0 = start + (uint32_t)w0;
+                const int64_t wd = e0 >> 5;
+                const int sh = (int)(e0 & 31);
+                const uint64_t lo = ((uint64_t)mplane[wd + 1] << 32) | mplane[wd];
+                uint64_t m = sh ? (lo >> sh) | ((uint64_t)mplane[wd + 2] << (64 - sh)) : lo;
+                if (n - w0 < 64) m &= (1ull << (n - w0)) - 1ull;
+                m = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32) |
+                    __builtin_amdgcn_readfirstlane((uint32_t)m);
+                while (m) {
+                    const int j = w0 + __builtin_ctzll(m);
+                    m &= m - 1ull;
+                    const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
+                    const float dx = fx - r0.x, dy = fy - r0.y;
+                    const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
+                    const float alpha = fminf(kAlphaMax, r1.y * gauss_of(t1, t2));
+                    float wf = 0.f;
+                    if (start + (uint32_t)j < lastp && alpha >= kAlphaMin) {
+                        wf = (float)((double)alpha * T);
+                        T = T * (1.0 - (double)alpha);
+                    }
+                    wb[nrow * 64 + wslot] = wf;
+                    rid = h16 == nrow ? j : rid;
+                    if (++nrow == kFRows) {
+                        flush_rows(nrow, rid);
+                        nrow = 0;
+                    }
+                }
+            }
+            if (nrow) flush_rows(nrow, rid);
+        }
+    }
+
+    for (uint32_t start = range.x; start < range.y && !(!MAIN && amask); start += (uint32_t)batch) {
         if (__syncthreads_count(done) == NT) break;
         const int n = (int)min((uint32_t)batch, range.y - start);
         stage_mm<NT, CCH, MAIN ? 4 : 2>(srec, sfeat, vals, start, n, rec, recbase, sem, C_o, c0);
@@ -247,38 +325,13 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
                 wb[nrow * 64 + wslot] = wf;
                 rid = h16 == nrow ? j : rid;
                 if (++nrow == kFRows) {
-                    __builtin_amdgcn_wave_barrier();
-                    const float4 bw = *reinterpret_cast<const float4 *>(wb + h16 * 64 + l16 * 4);
-                    float a[CPL];
-                    lds_row<CPL>(sfeat + rid * FS + CPL * l16, a);
-#pragma unroll
-                    for (int q = 0; q < CPL; ++q) {
-                        acc[q][0] = mma(a[q], bw.x, acc[q][0]);
-                        acc[q][1] = mma(a[q], bw.y, acc[q][1]);
-                        acc[q][2] = mma(a[q], bw.z, acc[q][2]);
-                        acc[q][3] = mma(a[q], bw.w, acc[q][3]);
-                    }
-                    __builtin_amdgcn_wave_barrier();
+                    flush_rows(nrow, rid);
                     nrow = 0;
                 }
             }
             if (__all(done)) break;
         }
-        if (nrow) {  // the batch's remaining rows, padded with zero weights
-            for (int r = nrow; r < kFRows; ++r) wb[r * 64 + wslot] = 0.f;
-            __builtin_amdgcn_wave_barrier();
-            const float4 bw = *reinterpret_cast<const float4 *>(wb + h16 * 64 + l16 * 4);
-            float a[CPL];
-            lds_row<CPL>(sfeat + rid * FS + CPL * l16, a);
-#pragma unroll
-            for (int q = 0; q < CPL; ++q) {
-                acc[q][0] = mma(a[q], bw.x, acc[q][0]);
-                acc[q][1] = mma(a[q], bw.y, acc[q][1]);
-                acc[q][2] = mma(a[q], bw.z, acc[q][2]);
-                acc[q][3] = mma(a[q], bw.w, acc[q][3]);
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
+        if (nrow) flush_rows(nrow, rid);  // the batch's remaining rows, padded with zero weights
     }
     if constexpr (MAIN) {
         if (mplane) mflush();
@@ -580,13 +633,16 @@ hipError_t fwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayo
     const size_t lds = fwd_mm_lds(b, CCH, NW, hit);
     const bool main_pass = c0 == 0;
     auto tclk = (counters && main_pass) ? (unsigned long long *)(ws + L.tclk) : nullptr;
-    // the activity mask for the backward: written by the first pass of a forward
-    // that keeps the backward's state (T_final, n_contrib)
+    // the activity mask: written by the first pass of a forward that keeps the
+    // backward's state (T_final, n_contrib), read by its further channel passes
+    // and by the backward
     uint32_t *amask = nullptr;
-    if (main_pass && out.T_final && out.n_contrib) {
+    if (out.T_final && out.n_contrib) {
         amask = (uint32_t *)(ws + L.amask);
-        hipError_t e = launch_fill_u32(amask, 0u, (int64_t)kMaskPlanes * L.amask_words, s);
-        if (e != hipSuccess) return e;
+        if (main_pass) {
+            hipError_t e = launch_fill_u32(amask, 0u, (int64_t)kMaskPlanes * L.amask_words, s);
+            if (e != hipSuccess) return e;
+        }
     }
 #define UGS_FWD_MM(DMV, MAINV)                                                                                  \
     hipLaunchKernelGGL((render_fwd_mm_kernel<TW, TH, CCH, DMV, MAINV>), dim3(xcd_grid(pb.total_tiles)),        \

@@ -4,8 +4,7 @@ WRITE_SIZE counter runs scaled by a plain copy kernel of known size).
 
   python -m paper_2510_12174_amd.profsum stats <kernel_stats.csv> <command>
   python -m paper_2510_12174_amd.profsum traffic <fetch counter csv> <write counter csv> \
-        <kernel substring> <key> <source file> <command>
-  python -m paper_2510_12174_amd.profsum valu <counter csv> <kernel substring> <key> <source file> <command>
+        <kernel substring> <key> <source files> <command>
   python -m paper_2510_12174_amd.profsum counters <csv>[,<csv>...] <kernel substring> <key> <source file> <command>
 """
 from __future__ import annotations
@@ -18,6 +17,14 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 1 << 30  # the calibration copy moves 1 GiB each way
+
+
+def _sha(sources):
+    """Hash of the kernel's source files (comma-separated, under csrc/)."""
+    h = hashlib.sha256()
+    for f in sources.split(","):
+        h.update(open(os.path.join(ROOT, "paper_2510_12174_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def _short(name, n=90):
@@ -56,46 +63,24 @@ def traffic(fetch_csv, write_csv, kernel_sub, key, source, command):
     cw = max((big(w, k) for k in copy_k if k in w), default=0.0)
     fs = COPY_BYTES / (cf * 1024) if cf else 1.0
     ws = COPY_BYTES / (cw * 1024) if cw else 1.0
-    ks = [k for k in f if kernel_sub in k]
-    fk = [x for k in ks for x in f[k]]
-    wk = [x for k in ks for x in w.get(k, [])]
-    fb = sum(fk) / len(fk) * 1024 * fs if fk else None
-    wb = sum(wk) / len(wk) * 1024 * ws if wk else None
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2510_12174_amd", "csrc", source), "rb").read()).hexdigest()[:16]
+    # a stage may be several kernels (a first pass and channel-chunk passes),
+    # each launched once per step: mean per kernel over its dispatches, summed
+    # over the stage's kernels
+    ks = sorted(k for k in f if kernel_sub in k)
+    mean = lambda xs: sum(xs) / len(xs)
+    fb = sum(mean(f[k]) for k in ks) * 1024 * fs if ks else None
+    wb = sum(mean(w[k]) for k in ks if w.get(k)) * 1024 * ws if any(w.get(k) for k in ks) else None
+    per = {_short(k, 70): dict(fetch_bytes=mean(f[k]) * 1024 * fs,
+                               write_bytes=mean(w[k]) * 1024 * ws if w.get(k) else None, dispatches=len(f[k]))
+           for k in ks}
+    sha = _sha(source)
     entry = dict(source_sha=sha, fetch_bytes=fb, write_bytes=wb,
                  bytes_per_launch=(fb or 0) + (wb or 0), copy_scale=dict(fetch=fs, write=ws),
-                 dispatches=len(fk), command=command)
+                 kernels=per, command=command)
     path = os.path.join(ROOT, "profiles", "traffic.json")
     d = json.load(open(path)) if os.path.exists(path) else {}
     d[key] = entry
     json.dump(d, open(path, "w"), indent=1, sort_keys=True)
-    return entry
-
-
-def valu(pmc_csv, kernel_sub, key, source, command, simds=1024, xcds=8):
-    """VALU issue fraction of one kernel from a pass with SQ_INSTS_VALU,
-    SQ_INSTS_MFMA and GRBM_GUI_ACTIVE: a wave64 VALU instruction occupies a
-    16-lane SIMD for 4 cycles, GRBM_GUI_ACTIVE is summed over the XCDs."""
-    per = {}
-    for r in csv.DictReader(open(pmc_csv)):
-        if kernel_sub not in r["Kernel_Name"]:
-            continue
-        d = per.setdefault(r.get("Dispatch_Id"), {})
-        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
-    fr, mf = [], []
-    for d in per.values():
-        cyc = d.get("GRBM_GUI_ACTIVE", 0.0) / xcds
-        if cyc > 0:
-            fr.append(4.0 * d.get("SQ_INSTS_VALU", 0.0) / (simds * cyc))
-            mf.append(d.get("SQ_INSTS_MFMA", 0.0))
-    fr.sort()
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2510_12174_amd", "csrc", source), "rb").read()).hexdigest()[:16]
-    entry = dict(source_sha=sha, valu_issue_fraction=fr[len(fr) // 2] if fr else None,
-                 mfma_insts=sorted(mf)[len(mf) // 2] if mf else None, dispatches=len(fr), command=command)
-    path = os.path.join(ROOT, "profiles", "valu.json")
-    dd = json.load(open(path)) if os.path.exists(path) else {}
-    dd[key] = entry
-    json.dump(dd, open(path, "w"), indent=1, sort_keys=True)
     return entry
 
 
@@ -107,33 +92,43 @@ def counters(csv_paths, kernel_sub, key, source, command, simds=1024, xcds=8):
     conflict cycles over LDS active cycles, and the average resident wavefronts
     per SIMD (SQ_WAVE_CYCLES counts wave-cycles in units of 4 cycles).
     GRBM_GUI_ACTIVE is summed over the XCDs.  Stored in profiles/counters.json."""
-    med = {}
+    per_k = {}
     for path in csv_paths:
-        per = {}
         for r in csv.DictReader(open(path)):
             if kernel_sub not in r["Kernel_Name"]:
                 continue
-            d = per.setdefault(r.get("Dispatch_Id"), {})
+            d = per_k.setdefault(r["Kernel_Name"], {}).setdefault((path, r.get("Dispatch_Id")), {})
             d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
-        names = {c for d in per.values() for c in d}
-        for c in names:
-            vals = sorted(d[c] for d in per.values() if c in d)
-            med[c] = vals[len(vals) // 2]
-        med.setdefault("_dispatches", len(per))
-    cyc = lambda: med.get("GRBM_GUI_ACTIVE", 0.0) / xcds
-    der = {}
-    if cyc() > 0:
-        if "SQ_INSTS_VALU" in med:
-            der["valu_issue_fraction"] = 4.0 * med["SQ_INSTS_VALU"] / (simds * cyc())
-        if "SQ_VALU_MFMA_BUSY_CYCLES" in med:
-            der["mfma_busy_fraction"] = med["SQ_VALU_MFMA_BUSY_CYCLES"] / (simds * cyc())
-        if "SQ_WAVE_CYCLES" in med:
-            der["waves_per_simd"] = 4.0 * med["SQ_WAVE_CYCLES"] / (simds * cyc())
-    if med.get("SQ_ACTIVE_INST_LDS"):
-        der["lds_bank_conflict_fraction"] = med.get("SQ_LDS_BANK_CONFLICT", 0.0) / med["SQ_ACTIVE_INST_LDS"]
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2510_12174_amd", "csrc", source), "rb").read()).hexdigest()[:16]
-    entry = dict(source_sha=sha, counters={k: v for k, v in sorted(med.items()) if not k.startswith("_")},
-                 derived=der, dispatches=med.get("_dispatches"), command=command)
+    # median over dispatches per kernel and counter; a stage of several kernels
+    # (each launched once per step) sums them
+    kmed = {}
+    for k, disp in per_k.items():
+        names = {c for d in disp.values() for c in d}
+        kmed[k] = {c: sorted(d[c] for d in disp.values() if c in d)[len([1 for d in disp.values() if c in d]) // 2]
+                   for c in names}
+    med = {}
+    for m in kmed.values():
+        for c, v in m.items():
+            med[c] = med.get(c, 0.0) + v
+
+    def derive(m):
+        cyc = m.get("GRBM_GUI_ACTIVE", 0.0) / xcds
+        der = {}
+        if cyc > 0:
+            if "SQ_INSTS_VALU" in m:
+                der["valu_issue_fraction"] = 4.0 * m["SQ_INSTS_VALU"] / (simds * cyc)
+            if "SQ_VALU_MFMA_BUSY_CYCLES" in m:
+                der["mfma_busy_fraction"] = m["SQ_VALU_MFMA_BUSY_CYCLES"] / (simds * cyc)
+            if "SQ_WAVE_CYCLES" in m:
+                der["waves_per_simd"] = 4.0 * m["SQ_WAVE_CYCLES"] / (simds * cyc)
+        if m.get("SQ_ACTIVE_INST_LDS"):
+            der["lds_bank_conflict_fraction"] = m.get("SQ_LDS_BANK_CONFLICT", 0.0) / m["SQ_ACTIVE_INST_LDS"]
+        return der
+
+    der = derive(med)
+    kernels = {_short(k, 70): dict(derived=derive(m), dispatches=len(per_k[k])) for k, m in kmed.items()}
+    sha = _sha(source)
+    entry = dict(source_sha=sha, counters=dict(sorted(med.items())), derived=der, kernels=kernels, command=command)
     if "valu_issue_fraction" in der:
         entry["valu_issue_fraction"] = der["valu_issue_fraction"]
     path = os.path.join(ROOT, "profiles", "counters.json")
@@ -148,8 +143,6 @@ if __name__ == "__main__":
         sys.stdout.write(stats(sys.argv[2], sys.argv[3]))
     elif sys.argv[1] == "traffic":
         print(json.dumps(traffic(*sys.argv[2:8]), indent=1))
-    elif sys.argv[1] == "valu":
-        print(json.dumps(valu(*sys.argv[2:7]), indent=1))
     elif sys.argv[1] == "counters":
         # counters <csv>[,<csv>...] <kernel substring> <key> <source file> <command>
         print(json.dumps(counters(sys.argv[2].split(","), *sys.argv[3:7]), indent=1))
