@@ -85,6 +85,19 @@ def algorithmic(N, V_rec, P, Px, C_o, sh_deg, F_eval, F_contrib):
     return b, f_fwd, f_bwd
 
 
+def binsort_bytes(R, P, tiles):
+    """Algorithmic HBM bytes of the binning and sorting stage: the stable depth
+    sort of the R visible records (4 passes of 8 bits: a 4-byte key read for
+    the histogram, key and index read and written by the scatter), the two
+    binning walks over the sorted records (index, rectangle and the 32 bytes of
+    the culling record read; counts written, then the P (tile, index) pairs),
+    the stable tile sort of the pairs (as many passes as 8-bit digits cover the
+    tile ids: histogram read, pair read and written) and the per-tile ranges."""
+    dp = 4
+    tp = -(-max(tiles - 1, 0).bit_length() // 8)
+    return (R * dp * (4 + 16) + 2 * R * (4 + 8 + 32) + R * 8 + P * 8 + tp * P * (4 + 16) + P * 4 + tiles * 8), tp
+
+
 def source_sha(name):
     h = hashlib.sha256()
     for f in KERNEL_SOURCE[name].split(","):
@@ -442,12 +455,16 @@ def main():
     V_rec = int((touched > 0).sum().item())
     rast.backward(g, out, up, grads)
     torch.cuda.synchronize()
-    balance = None
+    balance, active = None, None
     if C_o > 8 and not (bf16 and C_o <= 32):
         balance = {k: tile_balance(rast.debug_buffer(b).cpu().numpy())
                    for k, b in (("render_fwd", "tile_clock_fwd"), ("render_bwd", "tile_clock_bwd"))}
+        # (wavefront, list entry) pairs that the matrix-core backward walks
+        bits = torch.tensor([bin(i).count("1") for i in range(256)], device="cuda", dtype=torch.int64)
+        active = int(bits[rast.debug_buffer("activity_mask").view(torch.uint8).long()].sum().item())
     rast.enable_counters(False)
-    log(f"[bench] pairs P={P} visible records={V_rec} evaluated={F_eval} contributing={F_contrib}")
+    log(f"[bench] pairs P={P} visible records={V_rec} evaluated={F_eval} contributing={F_contrib} "
+        f"active wavefront entries={active}")
     log(f"[bench] tile balance {balance}")
 
     # per-stage durations (one eager step each) to find the dominant kernel
@@ -585,6 +602,13 @@ def main():
         del gt
 
     b_alg, f_fwd, f_bwd = algorithmic(N, V_rec, P, Px, C_o, int(g_np["sh_deg"]), F_eval, F_contrib)
+    tiles = sum(-(-c["W"] // rast.opts.tile_w) * -(-c["H"] // rast.opts.tile_h) for c in cams)
+    bs_bytes, bs_passes = binsort_bytes(V_rec, P, tiles)
+    bs_ms = stage_ms["bin_sort"]
+    bin_sort = dict(ms=round(bs_ms, 3), alg_bytes=int(bs_bytes), tile_sort_passes=bs_passes,
+                    achieved_gbps=round(bs_bytes / (bs_ms * 1e-3) / 1e9, 1),
+                    frac=round(bs_bytes / (bs_ms * 1e-3) / PEAK_HBM, 4))
+    log(f"[bench] bin_sort {bin_sort}")
     k_ms = float(np.mean(kern))
     fl = None
     if dominant in ("render_bwd", "render_fwd"):
@@ -618,7 +642,9 @@ def main():
                                                         ms_per_step=round(t_pv, 3)),
                forward_only=fwd_only, prune=prune_res, loss=loss_res, depth_modes=depth_modes,
                step_hbm=dict(alg_bytes=int(b_alg), frac=round(b_alg / t_batched / PEAK_HBM, 4)),
-               counts=dict(pairs=P, records=V_rec, evaluated=F_eval, contributing=F_contrib),
+               bin_sort=bin_sort,
+               counts=dict(pairs=P, records=V_rec, evaluated=F_eval, contributing=F_contrib,
+                           active_wavefront_entries=active),
                tile_balance=balance,
                stage_ms={k: round(v, 4) for k, v in stage_ms.items()},
                roofline=roof, parity=None, cpu_baseline=None, secondary=None)

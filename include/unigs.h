@@ -264,7 +264,10 @@ int ugs_time_stage(ugs_ctx *ctx, int stage, void *ev_start, void *ev_stop);
  *   7 depth gradient incl. the normal branch, float[total pixels], render_bwd;
  *   8, 9 start and end time of each tile's workgroup in the forward and the
  *     backward compositing (9..256 channels, counters enabled), uint64[total
- *     tiles][2], in ticks of the 100 MHz GPU real-time clock.
+ *     tiles][2], in ticks of the 100 MHz GPU real-time clock;
+ *  10 activity mask of the last training forward (9..256 channels): per
+ *     wavefront slot of a tile (4 planes), one bit per sorted list entry that
+ *     at least one of the wavefront's pixels composites, uint32[4][words].
  * Counts 3 and 4 read the pair count back (synchronises `stream`). */
 int ugs_debug_buffer(ugs_ctx *ctx, void *ws, int which, void *stream, void **dev_ptr, int64_t *count);
 

@@ -910,6 +910,7 @@ int ugs_debug_buffer(ugs_ctx *ctx, void *ws, int which, void *stream, void **dev
     case 7: *dev_ptr = b + L.gd; *count = L.total_pix; return UGS_OK;
     case 8: *dev_ptr = b + L.tclk; *count = L.total_tiles; return UGS_OK;
     case 9: *dev_ptr = b + L.tclk + (size_t)L.total_tiles * 16; *count = L.total_tiles; return UGS_OK;
+    case 10: *dev_ptr = b + L.amask; *count = (int64_t)kMaskPlanes * L.amask_words; return UGS_OK;
     default: return UGS_ERR_INVALID_ARG;
     }
 }

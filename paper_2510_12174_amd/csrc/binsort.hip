@@ -327,17 +327,21 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int widt
 // kSortUnroll groups of 64 keys before using any of them.
 constexpr int kSortUnroll = 8;
 
-// Per-block digit histogram of the block's chunk: one LDS atomic per key,
-// except for digits of fewer than 4 bits, where so few counters would
-// serialise the atomics -- there equal digits within a group of 64 keys are
-// counted once per group (by the lowest such lane).
+// Per-block digit histogram of the block's chunk: one LDS atomic per key, into
+// one of kHistCopies copies of the histogram by lane, summed at the end.  The
+// digits of a group of 64 keys are often few (the top digit of tile ids that
+// are already ordered by their low bits), and lanes adding to one LDS word
+// serialise.
+constexpr int kHistCopies = 8;
+
 template <typename K>
 __global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__ keys, const uint32_t *__restrict__ n_dev,
                                                            int shift, int width, uint32_t *__restrict__ hist)
 {
-    __shared__ uint32_t h[256];
-    for (int d = threadIdx.x; d < 256; d += kSortThreads) h[d] = 0;
+    __shared__ uint32_t h[kHistCopies][256];
+    for (int d = threadIdx.x; d < kHistCopies * 256; d += kSortThreads) (&h[0][0])[d] = 0;
     __syncthreads();
+    uint32_t *hc = h[threadIdx.x % kHistCopies];
     const uint32_t P = *n_dev;
     const uint32_t per = ((P + kSortBlocks - 1) / kSortBlocks + 63) & ~63u;
     const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = min((uint64_t)P, b0 + per);
@@ -348,23 +352,17 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__
             const uint64_t i = tb + u * kSortThreads + threadIdx.x;
             key[u] = i < b1 ? keys[i] : K(0);
         }
-        if (width >= 4) {
 #pragma unroll
-            for (int u = 0; u < kSortUnroll; ++u)
-                if (tb + u * kSortThreads + threadIdx.x < b1) atomicAdd(&h[digit_of(key[u], shift, width)], 1u);
-        } else {
-            const uint64_t lt = __lanemask_lt();
-#pragma unroll
-            for (int u = 0; u < kSortUnroll; ++u) {
-                const bool valid = tb + u * kSortThreads + threadIdx.x < b1;
-                const uint32_t d = digit_of(key[u], shift, width);
-                const uint64_t peers = digit_peers(d, valid, width);
-                if (valid && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
-            }
-        }
+        for (int u = 0; u < kSortUnroll; ++u)
+            if (tb + u * kSortThreads + threadIdx.x < b1) atomicAdd(&hc[digit_of(key[u], shift, width)], 1u);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < 256; d += kSortThreads) hist[(size_t)d * kSortBlocks + blockIdx.x] = h[d];
+    for (int d = threadIdx.x; d < 256; d += kSortThreads) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < kHistCopies; ++k) c += h[k][d];
+        hist[(size_t)d * kSortBlocks + blockIdx.x] = c;
+    }
 }
 
 // One block per digit: exclusive scan of that digit's per-block counts.

@@ -28,9 +28,10 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_kernel(
     float4 *srec = smem;
     float *ssem = (float *)(smem + 4 * batch);
     float *shh = DM == 2 ? ssem + (size_t)batch * CO : nullptr;
-    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
-    if (tile >= ntiles) return;
-    const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    const uint32_t slot = xcd_tile(blockIdx.x, ntiles);
+    if (slot >= ntiles) return;
+    const TileInfo ti = tile_info<TW, TH>(cams, V, slot);
+    const uint32_t tile = ti.tile;
     const uint2 range = ranges[tile];
     const float fx = (float)ti.px, fy = (float)ti.py;
     const int64_t recbase = (int64_t)ti.v * N;
@@ -164,9 +165,10 @@ __global__ void __launch_bounds__(TW *TH) render_bwd_kernel(
     float4 *srec = smem;
     float *ssem = (float *)(smem + 4 * batch);
     float *shh = DM == 2 ? ssem + (size_t)batch * CO : nullptr;
-    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
-    if (tile >= ntiles) return;
-    const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    const uint32_t slot = xcd_tile(blockIdx.x, ntiles);
+    if (slot >= ntiles) return;
+    const TileInfo ti = tile_info<TW, TH>(cams, V, slot);
+    const uint32_t tile = ti.tile;
     const uint2 range = ranges[tile];
     const float fx = (float)ti.px, fy = (float)ti.py;
     const int64_t recbase = (int64_t)ti.v * N;
@@ -326,9 +328,10 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
     const int wave = (int)(threadIdx.x >> 6);
     float *wb = (float *)(sid + batch) + wave * (kGrp * kWbStride);
     float *shh = DM == 2 ? (float *)(sid + batch) + (TW * TH / 64) * (kGrp * kWbStride) : nullptr;
-    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
-    if (tile >= ntiles) return;
-    const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    const uint32_t slot = xcd_tile(blockIdx.x, ntiles);
+    if (slot >= ntiles) return;
+    const TileInfo ti = tile_info<TW, TH>(cams, V, slot);
+    const uint32_t tile = ti.tile;
     const uint2 range = ranges[tile];
     const float fx = (float)ti.px, fy = (float)ti.py;
     const int64_t recbase = (int64_t)ti.v * N;
@@ -413,19 +416,21 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
         const uint32_t start = end - range.x > (uint32_t)batch ? end - (uint32_t)batch : range.x;
         const int n = (int)(end - start);
         __syncthreads();
-        for (int q = threadIdx.x; q < n * 4; q += NT) {
-            const uint32_t id = vals[start + (q >> 2)];
-            srec[q] = rec[(recbase + id) * 4 + (q & 3)];
-        }
+        stage_records<NT>(srec, vals, start, n, rec, recbase);
         // features, split: 32 channels per row (zero beyond C_o)
-        for (int q = threadIdx.x; q < n * 32; q += NT) {
-            const int e = q >> 5, c = q & 31;
-            const uint32_t id = vals[start + e];
-            __bf16 h, l;
-            split_bf16(c < C_o ? sem[(int64_t)id * C_o + c] : 0.f, h, l);
-            ssem[e * kSemRow + c] = h;
-            ssem[e * kSemRow + 32 + c] = l;
-        }
+        staged_copy<NT, 4, float>(
+            n * 32, [&](int q) { return vals[start + (q >> 5)]; },
+            [&](int q, uint32_t id) {
+                const int c = q & 31;
+                return c < C_o ? sem[(int64_t)id * C_o + c] : 0.f;
+            },
+            [&](int q, float x) {
+                const int e = q >> 5, c = q & 31;
+                __bf16 h, l;
+                split_bf16(x, h, l);
+                ssem[e * kSemRow + c] = h;
+                ssem[e * kSemRow + 32 + c] = l;
+            });
         for (int q = threadIdx.x; q < n; q += NT) sid[q] = vals[start + q];
         stage_hits<NT, HIT>(shh, vals, start, n, hrec, recbase);
         __syncthreads();
@@ -565,9 +570,10 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
     const int wave = (int)(threadIdx.x >> 6);
     float *wb = (float *)(seml + CO * RS) + wave * (kGrp * kWbStride);
     float *shh = DM == 2 ? (float *)(seml + CO * RS) + (NT / 64) * (kGrp * kWbStride) : nullptr;
-    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
-    if (tile >= ntiles) return;
-    const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    const uint32_t slot = xcd_tile(blockIdx.x, ntiles);
+    if (slot >= ntiles) return;
+    const TileInfo ti = tile_info<TW, TH>(cams, V, slot);
+    const uint32_t tile = ti.tile;
     const uint2 range = ranges[tile];
     const float fx = (float)ti.px, fy = (float)ti.py;
     const int64_t recbase = (int64_t)ti.v * N;
@@ -589,21 +595,22 @@ __global__ void __launch_bounds__(TW *TH) render_fwd_mfma_kernel(
     for (uint32_t start = range.x; start < range.y; start += (uint32_t)batch) {
         if (__syncthreads_count(done) == NT) break;
         const int n = (int)min((uint32_t)batch, range.y - start);
-        for (int q = threadIdx.x; q < n * 4; q += NT) {
-            const uint32_t id = vals[start + (q >> 2)];
-            srec[q] = rec[(recbase + id) * 4 + (q & 3)];
-        }
+        stage_records<NT>(srec, vals, start, n, rec, recbase);
         // features, split and transposed: column f of row c (zero beyond C_o and past n)
         const int ng16 = (n + kGrp - 1) / kGrp * kGrp;
-        for (int q = threadIdx.x; q < ng16 * CO; q += NT) {
-            const int e = q / CO, c = q - e * CO;
-            float x = 0.f;
-            if (e < n && c < C_o) x = sem[(int64_t)vals[start + e] * C_o + c];
-            short h, l;
-            split_bf16_bits(x, h, l);
-            semh[c * RS + e] = h;
-            seml[c * RS + e] = l;
-        }
+        staged_copy<NT, 4, float>(
+            ng16 * CO, [&](int q) { return q / CO < n ? vals[start + q / CO] : 0u; },
+            [&](int q, uint32_t id) {
+                const int e = q / CO, c = q - e * CO;
+                return e < n && c < C_o ? sem[(int64_t)id * C_o + c] : 0.f;
+            },
+            [&](int q, float x) {
+                const int e = q / CO, c = q - e * CO;
+                short h, l;
+                split_bf16_bits(x, h, l);
+                semh[c * RS + e] = h;
+                seml[c * RS + e] = l;
+            });
         stage_hits<NT, HIT>(shh, vals, start, n, hrec, recbase);
         __syncthreads();
         if (__all(done)) continue;  // the block may still walk this batch

@@ -195,20 +195,26 @@ __device__ __forceinline__ float frag_adjoint(bool contrib, float4 r0, float4 r1
 }
 
 struct TileInfo {
+    uint32_t tile;  // global tile id (row-major within its view)
     int v, px, py;
     bool inside;
     int64_t pix;  // pixel index within the view
     int64_t HW, off;
 };
 
+// The tile that workgroup slot `slot` (from xcd_tile) processes, and this
+// lane's pixel in it.  (A super-tile order of the slots, 8 x 4 tiles per run
+// of 32 slots on one XCD instead of a strip of one tile row, measured the same
+// on the 3M- and 1M-Gaussian 16-view steps.)
 template <int TW, int TH>
-__device__ __forceinline__ TileInfo tile_info(const DevCam *cams, int V, uint32_t tile)
+__device__ __forceinline__ TileInfo tile_info(const DevCam *cams, int V, uint32_t slot)
 {
     TileInfo ti;
-    ti.v = view_of_tile(cams, V, tile);
+    ti.tile = slot;
+    ti.v = view_of_tile(cams, V, slot);
     const DevCam &cam = cams[ti.v];
-    uint32_t lt = tile - cam.tile_base;
-    int tx = (int)(lt % (uint32_t)cam.tiles_x), ty = (int)(lt / (uint32_t)cam.tiles_x);
+    const uint32_t lt = slot - cam.tile_base;
+    const int tx = (int)(lt % (uint32_t)cam.tiles_x), ty = (int)(lt / (uint32_t)cam.tiles_x);
     // each wavefront covers a compact 8 x 8 (or 8-row) block of the tile
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = (int)(threadIdx.x & 63);
     constexpr int WX = TW / 8;  // wavefronts per tile row
@@ -246,13 +252,51 @@ __device__ __forceinline__ float frag_kd(float kd, const float *shh, int j, floa
         return kd;
 }
 
+// Copies `total` items to LDS, G items per lane at a time (item q = q0 + NT u
+// + thread): first the G list ids idx(q), then the G data loads load(q, id),
+// then the G LDS writes store(q, value), so that each group costs two round
+// trips to memory.  A plain loop would wait for every item's loads in turn.
+template <int NT, int G, typename T, typename Idx, typename Load, typename Store>
+__device__ __forceinline__ void staged_copy(int total, Idx idx, Load load, Store store)
+{
+    const int t = (int)threadIdx.x;
+#pragma unroll 1
+    for (int q0 = 0; q0 < total; q0 += NT * G) {
+        // items past the end load the last item again: no branches around
+        // the loads or stores, which the compiler would otherwise sink into
+        // per-item conditional blocks, one round trip each
+        uint32_t id[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) id[u] = idx(min(q0 + NT * u + t, total - 1));
+        asm volatile("" ::: "memory");  // every id load issued before the first data load
+        T v[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) v[u] = load(min(q0 + NT * u + t, total - 1), id[u]);
+        // (the extra items rewrite the last item's slot with the same value)
+#pragma unroll
+        for (int u = 0; u < G; ++u) store(min(q0 + NT * u + t, total - 1), v[u]);
+    }
+}
+
 // Stages the hit constants of `n` list entries (depth_mode 2 only).
 template <int NT, bool HIT>
 __device__ __forceinline__ void stage_hits(float *shh, const uint32_t *vals, uint32_t start, int n,
                                            const float *hrec, int64_t recbase)
 {
     if constexpr (HIT)
-        for (int q = threadIdx.x; q < n; q += NT) shh[q] = hrec[recbase + vals[start + q]];
+        staged_copy<NT, 4, float>(
+            n, [&](int q) { return vals[start + q]; }, [&](int, uint32_t id) { return hrec[recbase + id]; },
+            [&](int q, float v) { shh[q] = v; });
+}
+
+// Stages the 4 float4 records of `n` list entries [start, start+n).
+template <int NT, int G = 2>
+__device__ __forceinline__ void stage_records(float4 *srec, const uint32_t *vals, uint32_t start, int n,
+                                              const float4 *rec, int64_t recbase)
+{
+    staged_copy<NT, G, float4>(
+        n * 4, [&](int q) { return vals[start + (q >> 2)]; },
+        [&](int q, uint32_t id) { return rec[(recbase + id) * 4 + (q & 3)]; }, [&](int q, float4 v) { srec[q] = v; });
 }
 
 // Stage `n` list entries [start, start+n) into LDS: 4 float4 of record and CO
@@ -261,17 +305,15 @@ template <int NT, int CO>
 __device__ __forceinline__ void stage_batch(float4 *srec, float *ssem, const uint32_t *vals, uint32_t start, int n,
                                             const float4 *rec, int64_t recbase, const float *sem, int C_o)
 {
-    for (int q = threadIdx.x; q < n * 4; q += NT) {
-        uint32_t id = vals[start + (q >> 2)];
-        srec[q] = rec[(recbase + id) * 4 + (q & 3)];
-    }
-    if constexpr (CO > 0) {
-        for (int q = threadIdx.x; q < n * CO; q += NT) {
-            int e = q / CO, c = q - e * CO;
-            uint32_t id = vals[start + e];
-            ssem[q] = c < C_o ? sem[(int64_t)id * C_o + c] : 0.f;
-        }
-    }
+    stage_records<NT>(srec, vals, start, n, rec, recbase);
+    if constexpr (CO > 0)
+        staged_copy<NT, 4, float>(
+            n * CO, [&](int q) { return vals[start + q / CO]; },
+            [&](int q, uint32_t id) {
+                const int c = q % CO;
+                return c < C_o ? sem[(int64_t)id * C_o + c] : 0.f;
+            },
+            [&](int q, float v) { ssem[q] = v; });
 }
 
 }  // namespace

@@ -47,7 +47,10 @@ __device__ __forceinline__ mf4 mma(float a, float b, mf4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+
 constexpr int kFRows = 4;   // active entries per forward product (the MFMA's K)
+constexpr int kFwdMaxBatch = 128;  // forward batch bound (ids held in two lane registers)
+constexpr int kFwdFmax = 4;        // forward staging: feature loads per lane in flight
 constexpr int kBGrp = 16;   // active entries per backward group (the MFMA's M)
 constexpr int kSW = 68;     // floats per row of the per-wavefront S / w buffer
 
@@ -116,23 +119,85 @@ __device__ __forceinline__ float frag_adjoint_sem(bool contrib, float4 r0, float
     return w;
 }
 
-// Stages `n` entries [start, start+n): the first NR float4 of their 64 B
-// records (4: all; 2: mean2d, conic factor, opacity, k and z0, all that the
-// alpha test needs) at a stride of 4 float4, and the CCH feature channels
-// [c0, c0 + CCH) (zero beyond C_o), rows of feat_stride(CCH) floats.
-template <int NT, int CCH, int NR = 4>
-__device__ __forceinline__ void stage_mm(float4 *srec, float *sfeat, const uint32_t *vals, uint32_t start, int n,
-                                         const float4 *rec, int64_t recbase, const float *sem, int C_o, int c0)
-{
-    for (int q = threadIdx.x; q < n * NR; q += NT) {
-        const int e = q / NR, k = q - e * NR;
-        const uint32_t id = vals[start + e];
-        srec[4 * e + k] = rec[(recbase + id) * 4 + k];
+// Ids of a batch's entries, held in lane registers (lane l: entries l, 64 + l,
+// ...), so that a batch's staging loads need no id load of their own and can
+// all be in flight at once.
+template <int MAXB>
+struct BatchIds {
+    static constexpr int R = (MAXB + 63) / 64;
+    uint32_t v[R];
+    __device__ __forceinline__ void load(const uint32_t *vals, uint32_t s0, int nn, int lane)
+    {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = 64 * r + lane < nn ? vals[s0 + 64 * r + lane] : 0u;
     }
-    for (int q = threadIdx.x; q < n * CCH; q += NT) {
-        const int e = q / CCH, c = q - e * CCH;
-        const uint32_t id = vals[start + e];
-        sfeat[e * feat_stride(CCH) + c] = c0 + c < C_o ? sem[(int64_t)id * C_o + c0 + c] : 0.f;
+    // id of entry e (< MAXB); every lane of the wavefront must take part
+    __device__ __forceinline__ uint32_t at(int e) const
+    {
+        uint32_t x = (uint32_t)__shfl((int)v[0], e & 63, 64);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            const uint32_t y = (uint32_t)__shfl((int)v[r], e & 63, 64);
+            x = (e >> 6) == r ? y : x;
+        }
+        return x;
+    }
+};
+
+// Stages the n (<= MAXB) entries of a batch whose ids are in `ids`: the first
+// NR float4 of their 64 B records (4: all; 2: mean2d, conic factor, opacity, k
+// and z0, all that the alpha test needs) at a stride of 4 float4, the CCH
+// feature channels [c0, c0 + CCH) (zero beyond C_o) in rows of
+// feat_stride(CCH) floats, and with HIT the hit constants.  The loads go out
+// in groups of up to FMAX per lane (registers) before their LDS writes.
+template <int NT, int CCH, int NR, int FMAX, int MAXB, bool HIT>
+__device__ __forceinline__ void stage_ids(float4 *srec, float *sfeat, float *shh, const BatchIds<MAXB> &ids, int n,
+                                          const float4 *rec, int64_t recbase, const float *sem, int C_o, int c0,
+                                          const float *hrec)
+{
+    // Items past the batch (or past a lane's share) load and store the last
+    // entry's item again (same value to the same slot): no branches around the
+    // loads or stores, which the compiler would otherwise sink into per-item
+    // conditional blocks, one round trip each.
+    constexpr int FS = feat_stride(CCH);
+    constexpr int RPT = (MAXB * NR + NT - 1) / NT, FPT = (MAXB * CCH + NT - 1) / NT;
+    constexpr int RCH = RPT < 4 ? RPT : 4, FCH = FPT < FMAX ? FPT : FMAX;
+    const int t = (int)threadIdx.x;
+#pragma unroll 1
+    for (int i0 = 0; i0 < RPT && NT * i0 < n * NR; i0 += RCH) {
+        float4 rr[RCH];
+#pragma unroll
+        for (int u = 0; u < RCH; ++u) {
+            const int q = t + NT * (i0 + u), e = min(q / NR, n - 1), k = q % NR;
+            rr[u] = rec[(recbase + ids.at(e)) * 4 + k];
+        }
+#pragma unroll
+        for (int u = 0; u < RCH; ++u) {
+            const int q = t + NT * (i0 + u), e = min(q / NR, n - 1), k = q % NR;
+            srec[4 * e + k] = rr[u];
+        }
+    }
+#pragma unroll 1
+    for (int i0 = 0; i0 < FPT && NT * i0 < n * CCH; i0 += FCH) {
+        float ff[FCH];
+#pragma unroll
+        for (int u = 0; u < FCH; ++u) {
+            const int q = t + NT * (i0 + u), e = min(q / CCH, n - 1), c = q % CCH;
+            const float x = sem[(int64_t)ids.at(e) * C_o + min(c0 + c, C_o - 1)];
+            ff[u] = c0 + c < C_o ? x : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < FCH; ++u) {
+            const int q = t + NT * (i0 + u), e = min(q / CCH, n - 1), c = q % CCH;
+            sfeat[e * FS + c] = ff[u];
+        }
+    }
+    if constexpr (HIT) {
+#pragma unroll 1
+        for (int e0 = 0; e0 < n; e0 += NT) {
+            const int e = min(e0 + t, n - 1);
+            shh[e] = hrec[recbase + ids.at(e)];
+        }
     }
 }
 
@@ -164,9 +229,10 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
     float *shh = sfeat + (size_t)batch * FS;
     float *wb = shh + (HIT ? batch : 0) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * (kFRows * 64);  // [row][lane % 16][pixel block]
     (void)NW;
-    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
-    if (tile >= ntiles) return;
-    const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    const uint32_t slot = xcd_tile(blockIdx.x, ntiles);
+    if (slot >= ntiles) return;
+    const TileInfo ti = tile_info<TW, TH>(cams, V, slot);
+    const uint32_t tile = ti.tile;
     if (tclk && threadIdx.x == 0) tclk[2 * tile] = __builtin_amdgcn_s_memrealtime();
     const uint2 range = ranges[tile];
     const float fx = (float)ti.px, fy = (float)ti.py;
@@ -229,19 +295,34 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
         if (lastp) atomicMax(&s_end, lastp);
         __syncthreads();
         const uint32_t end_all = s_end;
+        // ids and mask words (lanes 0..4) of the batch at s0, one batch ahead
+        BatchIds<kFwdMaxBatch> nid;
+        uint32_t nmk = 0;
+        auto prefetch = [&](uint32_t s0) {
+            const int nn = (int)min((uint32_t)batch, end_all - s0);
+            nid.load(vals, s0, nn, lane);
+            nmk = lane < (nn > 64 ? 5 : 3) ? mplane[(s0 >> 5) + lane] : 0u;
+        };
+        if (range.x < end_all) prefetch(range.x);
         for (uint32_t start = range.x; start < end_all; start += (uint32_t)batch) {
             const int n = (int)min((uint32_t)batch, end_all - start);
+            const BatchIds<kFwdMaxBatch> cid = nid;
+            const uint32_t cmk = nmk;
             __syncthreads();
-            stage_mm<NT, CCH, 2>(srec, sfeat, vals, start, n, rec, recbase, sem, C_o, c0);
+            stage_ids<NT, CCH, 2, kFwdFmax, kFwdMaxBatch, false>(srec, sfeat, nullptr, cid, n, rec, recbase, sem, C_o,
+                                                                 c0, hrec);
             __syncthreads();
+            if (start + (uint32_t)batch < end_all) prefetch(start + (uint32_t)batch);
             int nrow = 0, rid = 0;
             for (int w0 = 0; w0 < n; w0 += 64) {
                 // mask bits of entries start + w0 .. start + w0 + 63
                 const uint32_t e0 = start + (uint32_t)w0;
-                const int64_t wd = e0 >> 5;
+                const int wi = (int)((e0 >> 5) - (start >> 5));
+                const uint32_t m0 = __builtin_amdgcn_readlane(cmk, wi), m1 = __builtin_amdgcn_readlane(cmk, wi + 1),
+                               m2 = __builtin_amdgcn_readlane(cmk, wi + 2);
                 const int sh = (int)(e0 & 31);
-                const uint64_t lo = ((uint64_t)mplane[wd + 1] << 32) | mplane[wd];
-                uint64_t m = sh ? (lo >> sh) | ((uint64_t)mplane[wd + 2] << (64 - sh)) : lo;
+                const uint64_t lo = ((uint64_t)m1 << 32) | m0;
+                uint64_t m = sh ? (lo >> sh) | ((uint64_t)m2 << (64 - sh)) : lo;
                 if (n - w0 < 64) m &= (1ull << (n - w0)) - 1ull;
                 m = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32) |
                     __builtin_amdgcn_readfirstlane((uint32_t)m);
@@ -269,12 +350,18 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
         }
     }
 
-    for (uint32_t start = range.x; start < range.y && !(!MAIN && amask); start += (uint32_t)batch) {
+    const bool walk_all = MAIN || !amask;
+    BatchIds<kFwdMaxBatch> nid;  // ids of the next batch, loaded one batch ahead
+    if (walk_all && range.x < range.y) nid.load(vals, range.x, (int)min((uint32_t)batch, range.y - range.x), lane);
+    for (uint32_t start = range.x; start < range.y && walk_all; start += (uint32_t)batch) {
         if (__syncthreads_count(done) == NT) break;
         const int n = (int)min((uint32_t)batch, range.y - start);
-        stage_mm<NT, CCH, MAIN ? 4 : 2>(srec, sfeat, vals, start, n, rec, recbase, sem, C_o, c0);
-        stage_hits<NT, HIT>(shh, vals, start, n, hrec, recbase);
+        const BatchIds<kFwdMaxBatch> cid = nid;
+        stage_ids<NT, CCH, MAIN ? 4 : 2, kFwdFmax, kFwdMaxBatch, HIT && MAIN>(srec, sfeat, shh, cid, n, rec, recbase,
+                                                                            sem, C_o, c0, hrec);
         __syncthreads();
+        if (start + (uint32_t)batch < range.y)
+            nid.load(vals, start + (uint32_t)batch, (int)min((uint32_t)batch, range.y - start - (uint32_t)batch), lane);
         if (__all(done)) continue;  // the other wavefronts may still walk this batch
         int nrow = 0;
         int rid = 0;  // lane l: batch index of buffered row l / 16
@@ -422,9 +509,10 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
     uint32_t *sid = (uint32_t *)(sfeat + (size_t)batch * FS);
     float *shh = (float *)(sid + batch);
     float *swb = shh + (HIT ? batch : 0) + wave * (kBGrp * kSW);
-    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
-    if (tile >= ntiles) return;
-    const TileInfo ti = tile_info<TW, TH>(cams, V, tile);
+    const uint32_t slot = xcd_tile(blockIdx.x, ntiles);
+    if (slot >= ntiles) return;
+    const TileInfo ti = tile_info<TW, TH>(cams, V, slot);
+    const uint32_t tile = ti.tile;
     if (tclk && threadIdx.x == 0) tclk[2 * tile] = __builtin_amdgcn_s_memrealtime();
     const uint2 range = ranges[tile];
     const float fx = (float)ti.px, fy = (float)ti.py;
@@ -440,27 +528,42 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
     float my_lse = 0.f, my_sc = 0.f;
     int my_lab = -1;
     if (fused && ti.inside) seed_pixel(seed, C_o, ti.off, ti.HW, ti.pix, my_lse, my_lab, my_sc);
-    auto up_at = [&](int p, int c) -> float {
+    // Addresses are clamped into the view and the channel range and the value
+    // selected afterwards: no branch around a load, so that all of them are in
+    // flight together instead of one round trip each.
+    auto up_idx = [&](int p, int c, bool &ok) -> int64_t {
         const int x = qx0 + (p & 7), y = qy0 + (p >> 3);
-        if (fused) {
-            const float l = __shfl(my_lse, p, 64), sc = __shfl(my_sc, p, 64);
-            const int lb = __shfl(my_lab, p, 64);
-            if (c >= C_o || x >= W || y >= H) return 0.f;
-            const float o = seed.logits[(int64_t)C_o * ti.off + (int64_t)c * ti.HW + (int64_t)y * W + x];
-            return sc * (__expf(o - l) - (c == lb ? 1.f : 0.f));
-        }
-        if (!up_sem || c >= C_o || x >= W || y >= H) return 0.f;
-        return up_sem[(int64_t)C_o * ti.off + (int64_t)c * ti.HW + (int64_t)y * W + x];
+        ok = c < C_o && x < W && y < H;
+        return (int64_t)C_o * ti.off + (int64_t)min(c, C_o - 1) * ti.HW + (int64_t)min(y, H - 1) * W + min(x, W - 1);
     };
     float GSr[KS][4], GDr[16][NCB];
+    auto fill = [&](auto up_at) {
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
+        for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-        for (int pb = 0; pb < 4; ++pb) GSr[ks][pb] = up_at(16 * pb + l16, c0 + KS * h16 + ks);
+            for (int pb = 0; pb < 4; ++pb) GSr[ks][pb] = up_at(16 * pb + l16, c0 + KS * h16 + ks);
 #pragma unroll
-    for (int ks = 0; ks < 16; ++ks)
+        for (int ks = 0; ks < 16; ++ks)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) GDr[ks][cb] = up_at(16 * h16 + ks, c0 + 16 * cb + l16);
+            for (int cb = 0; cb < NCB; ++cb) GDr[ks][cb] = up_at(16 * h16 + ks, c0 + 16 * cb + l16);
+    };
+    if (fused) {
+        fill([&](int p, int c) {
+            bool ok;
+            const float o = seed.logits[up_idx(p, c, ok)];
+            const float l = __shfl(my_lse, p, 64), sc = __shfl(my_sc, p, 64);
+            const int lb = __shfl(my_lab, p, 64);
+            return ok ? sc * (__expf(o - l) - (c == lb ? 1.f : 0.f)) : 0.f;
+        });
+    } else if (up_sem) {
+        fill([&](int p, int c) {
+            bool ok;
+            const float v = up_sem[up_idx(p, c, ok)];
+            return ok ? v : 0.f;
+        });
+    } else {
+        fill([&](int, int) { return 0.f; });
+    }
 
     double T = 1.0;
     float gR = 0.f, gG = 0.f, gB = 0.f, gDp = 0.f, gK = 0.f;
@@ -487,22 +590,51 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
     const uint32_t end_all = s_max;
     float A = 0.f;
 
+    // Staging.  The ids of a batch's entries and this wavefront's mask words
+    // for it are loaded one batch ahead (while the batch before is walked), so
+    // that staging a batch costs one round trip to memory (records, feature
+    // rows and hit constants at known ids, all in flight together) instead of
+    // three (ids, then those loads, then the mask).
+    const int t = (int)threadIdx.x;
+    auto batch_start = [&](uint32_t e) -> uint32_t {
+        return e - range.x > (uint32_t)batch ? e - (uint32_t)batch : range.x;
+    };
+    // mask words (lanes 0..2) of the batch at s0
+    auto mask_of = [&](uint32_t s0) -> uint32_t { return lane < 3 ? mplane[(s0 >> 5) + lane] : 0u; };
+    BatchIds<64> nid;
+    uint32_t nmask = 0;
+    nid.v[0] = 0;
+    if (end_all > range.x) {
+        const uint32_t s0 = batch_start(end_all);
+        nid.load(vals, s0, (int)(end_all - s0), lane);
+        nmask = mask_of(s0);
+    }
+
     for (uint32_t end = end_all; end > range.x;) {
-        const uint32_t start = end - range.x > (uint32_t)batch ? end - (uint32_t)batch : range.x;
+        const uint32_t start = batch_start(end);
         const int n = (int)(end - start);
+        const BatchIds<64> cid = nid;
+        const uint32_t cm = nmask;
         __syncthreads();
-        stage_mm<NT, CCH, MAIN ? 4 : 2>(srec, sfeat, vals, start, n, rec, recbase, sem, C_o, c0);
-        for (int q = threadIdx.x; q < n; q += NT) sid[q] = vals[start + q];
-        stage_hits<NT, HIT>(shh, vals, start, n, hrec, recbase);
+        stage_ids<NT, CCH, MAIN ? 4 : 2, (CCH > 32 ? 16 : 4), 64, HIT>(srec, sfeat, shh, cid, n, rec, recbase, sem,
+                                                                    C_o, c0, hrec);
+        if (t < n) sid[t] = cid.v[0];
+
         __syncthreads();
+        if (start > range.x) {
+            const uint32_t s1 = batch_start(start);
+            nid.load(vals, s1, (int)(start - s1), lane);
+            nmask = mask_of(s1);
+        }
         // the batch's active entries for this wavefront, last first, from the
         // forward's activity mask (bits of entries start .. start + n - 1)
         int nact = 0, myact = 0;
         {
-            const int64_t w = start >> 5;
-            const uint64_t lo = ((uint64_t)mplane[w + 1] << 32) | mplane[w];
+            const uint32_t m0 = __builtin_amdgcn_readlane(cm, 0), m1 = __builtin_amdgcn_readlane(cm, 1),
+                           m2 = __builtin_amdgcn_readlane(cm, 2);
+            const uint64_t lo = ((uint64_t)m1 << 32) | m0;
             const int sh = (int)(start & 31);
-            uint64_t m = sh ? (lo >> sh) | ((uint64_t)mplane[w + 2] << (64 - sh)) : lo;
+            uint64_t m = sh ? (lo >> sh) | ((uint64_t)m2 << (64 - sh)) : lo;
             if (n < 64) m &= (1ull << n) - 1ull;
             while (m) {
                 const int j = 63 - __builtin_clzll(m);
@@ -629,7 +761,7 @@ hipError_t fwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayo
     auto hrec = (const float *)(ws + L.hrec);
     constexpr int NW = TW * TH / 64;
     const bool hit = pb.depth_mode == 2;
-    const int b = fit_batch(batch, 64 * 1024, [&](int x) { return fwd_mm_lds(x, CCH, NW, hit); });
+    const int b = std::min(kFwdMaxBatch, fit_batch(batch, 64 * 1024, [&](int x) { return fwd_mm_lds(x, CCH, NW, hit); }));
     const size_t lds = fwd_mm_lds(b, CCH, NW, hit);
     const bool main_pass = c0 == 0;
     auto tclk = (counters && main_pass) ? (unsigned long long *)(ws + L.tclk) : nullptr;

@@ -572,7 +572,8 @@ class Rasterizer:
     DEBUG = {"records": (0, "float32", 16), "rects": (1, "int32", 2), "touched": (2, "int32", 1),
              "keys": (3, "int32", 1), "vals": (4, "int32", 1), "ranges": (5, "int32", 2),
              "grad_records": (6, "float32", 16), "depth_grad": (7, "float32", 1),
-             "tile_clock_fwd": (8, "int64", 2), "tile_clock_bwd": (9, "int64", 2)}
+             "tile_clock_fwd": (8, "int64", 2), "tile_clock_bwd": (9, "int64", 2),
+             "activity_mask": (10, "int32", 1)}
 
     def debug_buffer(self, name):
         """Device tensor view of an internal workspace array (see ugs_debug_buffer)."""
