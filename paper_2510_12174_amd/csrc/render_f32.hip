@@ -666,7 +666,85 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
             __builtin_amdgcn_wave_barrier();
             // reverse walk over the group
             const int ng = min(kBGrp, nact - g0);
-            for (int f = 0; f < kBGrp; ++f) {
+            if constexpr (!MAIN) {
+                // chunk passes take the entries in pairs: the second entry's
+                // alpha arithmetic overlaps the first's, and one 16-value
+                // reduction and one atomic carry both entries' six slots
+                auto entry_sem = [&](int f, bool valid, float (&u)[8], uint32_t &id) -> float {
+                    const int j = __builtin_amdgcn_readlane(myact, g0 + f);
+                    const uint32_t entry = start + (uint32_t)j;
+                    const float s_sem = swb[f * kSW + lane];
+                    const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
+                    const float dx = fx - r0.x, dy = fy - r0.y;
+                    const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
+                    const float G = gauss_of(t1, t2);
+                    const float oG = r1.y * G;
+                    const float alpha = fminf(kAlphaMax, oG);
+                    const bool contrib = valid && entry < last && alpha >= kAlphaMin;
+                    id = sid[j];
+                    return frag_adjoint_sem(contrib, r0, r1, dx, dy, t1, t2, G, oG, alpha, s_sem, T, A, u);
+                };
+                for (int f = 0; f < ng; f += 2) {
+                    const bool has1 = f + 1 < ng;
+                    float u0[8], u1[8], u[16];
+                    uint32_t id0, id1;
+                    const float w0 = entry_sem(f, true, u0, id0);
+                    const float w1 = entry_sem(has1 ? f + 1 : f, has1, u1, id1);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        u[k] = u0[k];
+                        u[8 + k] = u1[k];
+                    }
+                    const float tot = reduce_scatter<16>(u);
+                    const int slot = lane >> 2, e1 = slot >> 3, k = slot & 7;
+                    if ((lane & 3) == 0 && k < 6 && (e1 == 0 || has1))
+                        unsafeAtomicAdd(&grec[(recbase + (e1 ? id1 : id0)) * kRecFloats + k], tot);
+                    swb[f * kSW + lane] = w0;
+                    if (has1) swb[(f + 1) * kSW + lane] = w1;
+                }
+                for (int f = ng; f < kBGrp; ++f) swb[f * kSW + lane] = 0.f;
+            }
+            constexpr bool PAIR_MAIN = MAIN && CCH > 32;  // (the 32-channel form has no registers to spare)
+            if constexpr (PAIR_MAIN) {
+                // a 64-channel first pass pairs its entries the same way (16
+                // slots each, one 32-value reduction)
+                auto entry_all = [&](int f, bool valid, float (&v)[16], uint32_t &id) -> float {
+                    const int j = __builtin_amdgcn_readlane(myact, g0 + f);
+                    const uint32_t entry = start + (uint32_t)j;
+                    const float s_sem = swb[f * kSW + lane];
+                    const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
+                    const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
+                    const float dx = fx - r0.x, dy = fy - r0.y;
+                    const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
+                    const float G = gauss_of(t1, t2);
+                    const float oG = r1.y * G;
+                    const float alpha = fminf(kAlphaMax, oG);
+                    const bool contrib = valid && entry < last && alpha >= kAlphaMin;
+                    id = sid[j];
+                    return frag_adjoint(contrib, r0, r1, r2, r3, dx, dy, t1, t2, G, oG, alpha, s_sem, gR, gG, gB, gDp,
+                                        gK, frag_kd<HIT>(kd, shh, j, r2, r3, dx, dy), T, A, v);
+                };
+                for (int f = 0; f < ng; f += 2) {
+                    const bool has1 = f + 1 < ng;
+                    float v0[16], v1[16], v[32];
+                    uint32_t id0, id1;
+                    const float w0 = entry_all(f, true, v0, id0);
+                    const float w1 = entry_all(has1 ? f + 1 : f, has1, v1, id1);
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        v[k] = v0[k];
+                        v[16 + k] = v1[k];
+                    }
+                    const float tot = reduce_scatter<32>(v);
+                    const int slot = lane >> 1, e1 = slot >> 4, k = slot & 15;
+                    if ((lane & 1) == 0 && (e1 == 0 || has1))
+                        unsafeAtomicAdd(&grec[(recbase + (e1 ? id1 : id0)) * kRecFloats + k], tot);
+                    swb[f * kSW + lane] = w0;
+                    if (has1) swb[(f + 1) * kSW + lane] = w1;
+                }
+                for (int f = ng; f < kBGrp; ++f) swb[f * kSW + lane] = 0.f;
+            }
+            for (int f = 0; f < kBGrp && MAIN && !PAIR_MAIN; ++f) {
                 float w = 0.f;
                 if (f < ng) {
                     const int j = __builtin_amdgcn_readlane(myact, g0 + f);
@@ -687,12 +765,6 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
                                          gDp, gK, frag_kd<HIT>(kd, shh, j, r2, r3, dx, dy), T, A, v);
                         const float tot = reduce_scatter<16>(v);
                         if ((lane & 3) == 0) unsafeAtomicAdd(&gr[lane >> 2], tot);
-                    } else {
-                        // the semantic share only: no colour, depth or K terms
-                        float u[8];
-                        w = frag_adjoint_sem(contrib, r0, r1, dx, dy, t1, t2, G, oG, alpha, s_sem, T, A, u);
-                        const float tot = reduce_scatter<8>(u);
-                        if ((lane & 7) == 0 && (lane >> 3) < 6) unsafeAtomicAdd(&gr[lane >> 3], tot);
                     }
                 }
                 swb[f * kSW + lane] = w;
