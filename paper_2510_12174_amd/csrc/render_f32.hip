@@ -47,6 +47,12 @@ __device__ __forceinline__ mf4 mma(float a, float b, mf4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Float add to an LDS word (no return value needed).
+__device__ __forceinline__ void lds_add(float *p, float v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 
 constexpr int kFRows = 4;   // active entries per forward product (the MFMA's K)
 constexpr int kFwdMaxBatch = 128;  // forward batch bound (ids held in two lane registers)
@@ -66,7 +72,7 @@ __host__ __device__ constexpr size_t fwd_mm_lds(int batch, int CCH, int NW, bool
 // LDS bytes of the backward kernel.
 __host__ __device__ constexpr size_t bwd_mm_lds(int batch, int CCH, int NW, bool hit)
 {
-    return (size_t)batch * (64 + 4 * feat_stride(CCH) + 4 + (hit ? 4 : 0)) + (size_t)NW * kBGrp * kSW * 4;
+    return (size_t)batch * (64 + 4 * feat_stride(CCH) + 8 + (hit ? 4 : 0) + 64) + (size_t)NW * kBGrp * kSW * 4;
 }
 
 // Loads n floats from LDS (n = 1, 2, 4 or 8; 4-float aligned when n >= 4).
@@ -486,7 +492,10 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
 // semantic gradient of entry f.  MAIN passes (c0 = 0) carry every term of the
 // fragment adjoint and the 16 record slots; chunk passes (c0 > 0) only the
 // semantic share of the alpha gradient, i.e. record slots 0..5 (mean2d, conic,
-// opacity).
+// opacity).  The record-slot sums of the tile's wavefronts meet in LDS (one
+// row of 16 per batch entry) and go to the gradient records with one atomic
+// per entry and slot when the next batch is staged; the dO rows (CCH floats
+// per entry) go straight from the matrix layout to the semantic gradients.
 template <int TW, int TH, int CCH, int DM, bool MAIN>
 __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH > 32 ? 2 : 4))) render_bwd_mm_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,
@@ -506,9 +515,11 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     float4 *srec = smem;
     float *sfeat = (float *)(smem + 4 * batch);
-    uint32_t *sid = (uint32_t *)(sfeat + (size_t)batch * FS);
-    float *shh = (float *)(sid + batch);
-    float *swb = shh + (HIT ? batch : 0) + wave * (kBGrp * kSW);
+    uint32_t *sid = (uint32_t *)(sfeat + (size_t)batch * FS);  // two buffers of `batch` ids
+    float *shh = (float *)(sid + 2 * batch);
+    float *sgr = shh + (HIT ? batch : 0);  // [batch][16] record-slot sums of the tile's wavefronts
+    float *swb = sgr + (size_t)batch * 16 + wave * (kBGrp * kSW);
+    for (int q = threadIdx.x; q < batch * 16; q += NT) sgr[q] = 0.f;
     const uint32_t slot = xcd_tile(blockIdx.x, ntiles);
     if (slot >= ntiles) return;
     const TileInfo ti = tile_info<TW, TH>(cams, V, slot);
@@ -610,15 +621,29 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
         nmask = mask_of(s0);
     }
 
-    for (uint32_t end = end_all; end > range.x;) {
+    // the record-slot sums of the previous batch (ids in sidp) to the
+    // gradient records: one atomic per entry and slot for the whole tile
+    auto flush = [&](int nn, const uint32_t *sidp) {
+        for (int q = t; q < nn * 16; q += NT) {
+            const float x = sgr[q];
+            if (x != 0.f) {
+                unsafeAtomicAdd(&grec[(recbase + sidp[q >> 4]) * kRecFloats + (q & 15)], x);
+                sgr[q] = 0.f;
+            }
+        }
+    };
+    int kb = 0, n_prev = 0;
+    for (uint32_t end = end_all; end > range.x; ++kb) {
         const uint32_t start = batch_start(end);
         const int n = (int)(end - start);
         const BatchIds<64> cid = nid;
         const uint32_t cm = nmask;
+        uint32_t *sidc = sid + (kb & 1) * batch;
         __syncthreads();
         stage_ids<NT, CCH, MAIN ? 4 : 2, (CCH > 32 ? 16 : 4), 64, HIT>(srec, sfeat, shh, cid, n, rec, recbase, sem,
                                                                     C_o, c0, hrec);
-        if (t < n) sid[t] = cid.v[0];
+        if (t < n) sidc[t] = cid.v[0];
+        if (kb) flush(n_prev, sid + ((kb - 1) & 1) * batch);
 
         __syncthreads();
         if (start > range.x) {
@@ -670,7 +695,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
                 // chunk passes take the entries in pairs: the second entry's
                 // alpha arithmetic overlaps the first's, and one 16-value
                 // reduction and one atomic carry both entries' six slots
-                auto entry_sem = [&](int f, bool valid, float (&u)[8], uint32_t &id) -> float {
+                auto entry_sem = [&](int f, bool valid, float (&u)[8], int &jo) -> float {
                     const int j = __builtin_amdgcn_readlane(myact, g0 + f);
                     const uint32_t entry = start + (uint32_t)j;
                     const float s_sem = swb[f * kSW + lane];
@@ -681,13 +706,13 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
                     const float oG = r1.y * G;
                     const float alpha = fminf(kAlphaMax, oG);
                     const bool contrib = valid && entry < last && alpha >= kAlphaMin;
-                    id = sid[j];
+                    jo = j;
                     return frag_adjoint_sem(contrib, r0, r1, dx, dy, t1, t2, G, oG, alpha, s_sem, T, A, u);
                 };
                 for (int f = 0; f < ng; f += 2) {
                     const bool has1 = f + 1 < ng;
                     float u0[8], u1[8], u[16];
-                    uint32_t id0, id1;
+                    int id0, id1;
                     const float w0 = entry_sem(f, true, u0, id0);
                     const float w1 = entry_sem(has1 ? f + 1 : f, has1, u1, id1);
 #pragma unroll
@@ -697,8 +722,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
                     }
                     const float tot = reduce_scatter<16>(u);
                     const int slot = lane >> 2, e1 = slot >> 3, k = slot & 7;
-                    if ((lane & 3) == 0 && k < 6 && (e1 == 0 || has1))
-                        unsafeAtomicAdd(&grec[(recbase + (e1 ? id1 : id0)) * kRecFloats + k], tot);
+                    if ((lane & 3) == 0 && k < 6 && (e1 == 0 || has1)) lds_add(&sgr[(e1 ? id1 : id0) * 16 + k], tot);
                     swb[f * kSW + lane] = w0;
                     if (has1) swb[(f + 1) * kSW + lane] = w1;
                 }
@@ -708,7 +732,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
             if constexpr (PAIR_MAIN) {
                 // a 64-channel first pass pairs its entries the same way (16
                 // slots each, one 32-value reduction)
-                auto entry_all = [&](int f, bool valid, float (&v)[16], uint32_t &id) -> float {
+                auto entry_all = [&](int f, bool valid, float (&v)[16], int &jo) -> float {
                     const int j = __builtin_amdgcn_readlane(myact, g0 + f);
                     const uint32_t entry = start + (uint32_t)j;
                     const float s_sem = swb[f * kSW + lane];
@@ -720,14 +744,14 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
                     const float oG = r1.y * G;
                     const float alpha = fminf(kAlphaMax, oG);
                     const bool contrib = valid && entry < last && alpha >= kAlphaMin;
-                    id = sid[j];
+                    jo = j;
                     return frag_adjoint(contrib, r0, r1, r2, r3, dx, dy, t1, t2, G, oG, alpha, s_sem, gR, gG, gB, gDp,
                                         gK, frag_kd<HIT>(kd, shh, j, r2, r3, dx, dy), T, A, v);
                 };
                 for (int f = 0; f < ng; f += 2) {
                     const bool has1 = f + 1 < ng;
                     float v0[16], v1[16], v[32];
-                    uint32_t id0, id1;
+                    int id0, id1;
                     const float w0 = entry_all(f, true, v0, id0);
                     const float w1 = entry_all(has1 ? f + 1 : f, has1, v1, id1);
 #pragma unroll
@@ -737,8 +761,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
                     }
                     const float tot = reduce_scatter<32>(v);
                     const int slot = lane >> 1, e1 = slot >> 4, k = slot & 15;
-                    if ((lane & 1) == 0 && (e1 == 0 || has1))
-                        unsafeAtomicAdd(&grec[(recbase + (e1 ? id1 : id0)) * kRecFloats + k], tot);
+                    if ((lane & 1) == 0 && (e1 == 0 || has1)) lds_add(&sgr[(e1 ? id1 : id0) * 16 + k], tot);
                     swb[f * kSW + lane] = w0;
                     if (has1) swb[(f + 1) * kSW + lane] = w1;
                 }
@@ -757,14 +780,14 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
                     const float oG = r1.y * G;
                     const float alpha = fminf(kAlphaMax, oG);
                     const bool contrib = entry < last && alpha >= kAlphaMin;
-                    float *gr = grec + (recbase + sid[j]) * kRecFloats;
+                    float *gr = sgr + j * 16;
                     if constexpr (MAIN) {
                         float v[16];
                         const float4 r2 = srec[4 * j + 2], r3 = srec[4 * j + 3];
                         w = frag_adjoint(contrib, r0, r1, r2, r3, dx, dy, t1, t2, G, oG, alpha, s_sem, gR, gG, gB,
                                          gDp, gK, frag_kd<HIT>(kd, shh, j, r2, r3, dx, dy), T, A, v);
                         const float tot = reduce_scatter<16>(v);
-                        if ((lane & 3) == 0) unsafeAtomicAdd(&gr[lane >> 2], tot);
+                        if ((lane & 3) == 0) lds_add(&gr[lane >> 2], tot);
                     }
                 }
                 swb[f * kSW + lane] = w;
@@ -792,7 +815,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
                     const int f = 4 * h16 + r;
                     const int jf = __shfl(myact, min(g0 + f, nact - 1), 64);
                     if (f < ng) {
-                        const int64_t row = (int64_t)sid[jf] * C_o + c0;
+                        const int64_t row = (int64_t)sidc[jf] * C_o + c0;
 #pragma unroll
                         for (int cb = 0; cb < NCB; ++cb) {
                             const float x = d4[cb][r];
@@ -803,7 +826,12 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
             }
             __builtin_amdgcn_wave_barrier();
         }
+        n_prev = n;
         end = start;
+    }
+    if (kb) {
+        __syncthreads();
+        flush(n_prev, sid + ((kb - 1) & 1) * batch);
     }
     if (tclk) {
         __syncthreads();
