@@ -810,16 +810,37 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
                         d4[cb] = mma(a.w, GDr[4 * k4 + 3][cb], d4[cb]);
                     }
                 }
+                if constexpr (CCH <= 32) {
+                    // 32 channels: D to LDS rows (the wavefront's w buffer,
+                    // free after the products), then one atomic instruction per
+                    // two entries, each a whole 128-byte row (12.85 -> 12.34 ms
+                    // on the 1M-Gaussian 16-view step; slower at 64 channels)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int f = 4 * h16 + r;
-                    const int jf = __shfl(myact, min(g0 + f, nact - 1), 64);
-                    if (f < ng) {
-                        const int64_t row = (int64_t)sidc[jf] * C_o + c0;
+                    for (int r = 0; r < 4; ++r)
 #pragma unroll
-                        for (int cb = 0; cb < NCB; ++cb) {
-                            const float x = d4[cb][r];
-                            if (x != 0.f && c0 + 16 * cb + l16 < C_o) unsafeAtomicAdd(&dsem[row + 16 * cb + l16], x);
+                        for (int cb = 0; cb < NCB; ++cb) swb[(4 * h16 + r) * kSW + 16 * cb + l16] = d4[cb][r];
+                    __builtin_amdgcn_wave_barrier();
+                    const int fl = lane >> 5, cl = lane & 31;
+                    for (int f0 = 0; f0 < ng; f0 += 2) {
+                        const int f = f0 + fl;
+                        const int jf = __shfl(myact, min(g0 + f, nact - 1), 64);
+                        const float x = swb[f * kSW + cl];
+                        if (f < ng && x != 0.f && c0 + cl < C_o)
+                            unsafeAtomicAdd(&dsem[(int64_t)sidc[jf] * C_o + c0 + cl], x);
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int f = 4 * h16 + r;
+                        const int jf = __shfl(myact, min(g0 + f, nact - 1), 64);
+                        if (f < ng) {
+                            const int64_t row = (int64_t)sidc[jf] * C_o + c0;
+#pragma unroll
+                            for (int cb = 0; cb < NCB; ++cb) {
+                                const float x = d4[cb][r];
+                                if (x != 0.f && c0 + 16 * cb + l16 < C_o)
+                                    unsafeAtomicAdd(&dsem[row + 16 * cb + l16], x);
+                            }
                         }
                     }
                 }
