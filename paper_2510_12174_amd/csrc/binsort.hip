@@ -142,8 +142,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_down(ScanIn si, const uint3
 __global__ void __launch_bounds__(256) compact_visible(int64_t N, int64_t VN, const uint32_t *__restrict__ touched,
                                                        const uint32_t *__restrict__ voff,
                                                        const uint32_t *__restrict__ zbits,
-                                                       uint32_t *__restrict__ dkey, uint32_t *__restrict__ didx,
-                                                       uint32_t *__restrict__ vlist)
+                                                       uint32_t *__restrict__ dkey, uint32_t *__restrict__ didx)
 {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= VN || touched[idx] == 0) return;
@@ -153,7 +152,30 @@ __global__ void __launch_bounds__(256) compact_visible(int64_t N, int64_t VN, co
     // is stable)
     dkey[r] = zbits[idx];
     didx[r] = (uint32_t)idx;
-    vlist[r] = (uint32_t)idx;
+}
+
+// Visible views of each Gaussian (reads of neighbouring threads coalesce per
+// view), and their records in (Gaussian, view) order at the scanned offsets.
+__global__ void __launch_bounds__(256) gauss_views(int64_t N, int V, const uint32_t *__restrict__ touched,
+                                                   uint32_t *__restrict__ count)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    uint32_t c = 0;
+    for (int v = 0; v < V; ++v) c += touched[(int64_t)v * N + i] > 0u ? 1u : 0u;
+    count[i] = c;
+}
+
+__global__ void __launch_bounds__(256) gauss_emit(int64_t N, int V, const uint32_t *__restrict__ touched,
+                                                  const uint32_t *__restrict__ off, uint32_t *__restrict__ list)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    uint32_t o = off[i];
+    for (int v = 0; v < V; ++v) {
+        const int64_t idx = (int64_t)v * N + i;
+        if (touched[idx] > 0u) list[o++] = (uint32_t)idx;
+    }
 }
 
 // Tile counts in depth order (grid-stride up to the device count R).
@@ -595,7 +617,7 @@ hipError_t launch_binsort(const Problem &pb, const WsLayout &L, char *ws, hipStr
     scan(ScanIn{touched, VN, nullptr, 1}, L.nb_scan, part, voff, -1, &cnt->R, nullptr, nullptr, cnt, s);
     if (VN > 0)
         hipLaunchKernelGGL(compact_visible, dim3(vn_blocks), dim3(256), 0, s, L.N, VN, (const uint32_t *)touched,
-                           (const uint32_t *)voff, (const uint32_t *)dk1, dk0, di0, (uint32_t *)(ws + L.vlist));
+                           (const uint32_t *)voff, (const uint32_t *)dk1, dk0, di0);
     // 2. sort by depth
     const int dcur = radix_sort<uint32_t>(dk0, di0, dk1, di1, &cnt->R, L.depth_bits, hist, dtot, s);
     uint32_t *didx = dcur ? di1 : di0;
@@ -615,6 +637,24 @@ hipError_t launch_binsort(const Problem &pb, const WsLayout &L, char *ws, hipStr
     hipLaunchKernelGGL(tile_ranges, dim3(4096), dim3(256), 0, s, (const uint32_t *)(cur ? k1 : k0),
                        (const uint32_t *)&cnt->P_eff, ranges);
     *final_buf = cur;
+    return hipGetLastError();
+}
+
+hipError_t launch_gauss_major_list(const WsLayout &L, char *ws, int V, hipStream_t s)
+{
+    const int64_t N = L.N;
+    if (N <= 0) return hipSuccess;
+    auto touched = (const uint32_t *)(ws + L.touched);
+    auto count = (uint32_t *)(ws + L.tsorted);
+    auto off = (uint32_t *)(ws + L.poff);
+    auto part = (uint32_t *)(ws + L.scan_part);
+    auto cnt = (DevCounters *)(ws + L.counters);
+    const unsigned blocks = (unsigned)((N + 255) / 256);
+    const int nb = (int)((N + kScanBlock - 1) / kScanBlock);  // <= L.nb_scan (N <= V N)
+    hipLaunchKernelGGL(gauss_views, dim3(blocks), dim3(256), 0, s, N, V, touched, count);
+    scan(ScanIn{count, N, nullptr, 0}, nb, part, off, -1, &cnt->R_gauss, nullptr, nullptr, nullptr, s);
+    hipLaunchKernelGGL(gauss_emit, dim3(blocks), dim3(256), 0, s, N, V, touched, (const uint32_t *)off,
+                       (uint32_t *)(ws + L.vlist));
     return hipGetLastError();
 }
 

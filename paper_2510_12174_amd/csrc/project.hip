@@ -318,9 +318,9 @@ __global__ void __launch_bounds__(kProjThreads) project_fwd_kernel(ugs_gaussians
 
 // Backward of the per-view records into the Gaussian parameters, in two
 // passes.  The first runs the whole chain rule once per visible (view,
-// Gaussian) record -- one thread per record of the index-ordered visible list,
-// so no lane idles on views where its Gaussian is not visible and neighbouring
-// lanes read neighbouring parameters -- and writes the
+// Gaussian) record -- one thread per record of the (Gaussian, view)-ordered
+// visible list, so no lane idles on views where its Gaussian is not visible and
+// neighbouring lanes read the same or neighbouring parameters -- and writes the
 // record's contributions to the parameter gradients back into its gradient
 // record: mean 0-2, quaternion 3-6, log-scale 7-9, opacity logit 10, mask logit
 // 11 and the clamped colour gradient 12-14 (the SH coefficients' share is
@@ -337,7 +337,10 @@ __global__ void __launch_bounds__(kProjThreads) project_bwd_rec_kernel(ugs_gauss
     const int64_t N = g.N;
     constexpr int NC = (DEG + 1) * (DEG + 1);
     using D = double;  // the chain rule runs in FP64: its terms scale like 1/s^2 and cancel
-    const uint32_t Rn = cnt->R;
+    // the list holds the records still touched after the binning walk, which
+    // sets a record's count to its kept tiles (0 when the ellipse cull drops
+    // them all): R_gauss <= R
+    const uint32_t Rn = cnt->R_gauss;
     for (uint64_t rr = (uint64_t)blockIdx.x * kProjThreads + threadIdx.x; rr < Rn;
          rr += (uint64_t)gridDim.x * kProjThreads) {
         const uint32_t idx = didx[rr];
@@ -610,7 +613,13 @@ hipError_t launch_project_bwd(const ugs_gaussians &g, const Problem &pb, const W
     auto touched = (const uint32_t *)(ws + L.touched);
     auto grec = (float4 *)(ws + L.grec);
     auto cnt = (const DevCounters *)(ws + L.counters);
-    auto didx = (const uint32_t *)(ws + L.vlist);  // visible records in index order: coalesced parameter loads
+    // visible records in (Gaussian, view) order: a wavefront's records belong
+    // to a few consecutive Gaussians, so the parameter loads coalesce (in
+    // index order, a view's visible Gaussians are sparse and every parameter
+    // row read pulled in several cache lines per wavefront)
+    hipError_t e = launch_gauss_major_list(L, ws, pb.V, s);
+    if (e != hipSuccess) return e;
+    auto didx = (const uint32_t *)(ws + L.vlist);
     const int64_t VN = L.VN;
     const unsigned rec_blocks = (unsigned)std::min<int64_t>(std::max<int64_t>((VN + kProjThreads - 1) / kProjThreads, 1), 8192);
     dim3 grid((unsigned)((g.N + kProjThreads - 1) / kProjThreads));

@@ -60,6 +60,7 @@ struct DevCounters {
     uint32_t R;          // visible (view, Gaussian) records
     uint32_t P_eff;      // pairs emitted and sorted (0 on overflow)
     unsigned long long n_eval, n_contrib;
+    uint32_t R_gauss, pad;  // records still touched after the binning walk (<= R), listed per Gaussian
 };
 
 struct WsLayout {
@@ -100,6 +101,10 @@ hipError_t launch_project_fwd(const ugs_gaussians &g, const Problem &pb, const W
 hipError_t launch_project_bwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
                               const ugs_gaussian_grads &dg, hipStream_t s);
 hipError_t launch_binsort(const Problem &pb, const WsLayout &L, char *ws, hipStream_t s, int *final_buf);
+// The records still touched after the binning (a kept tile) in (Gaussian,
+// view) order into L.vlist, their count into DevCounters::R_gauss (after the
+// binning; uses L.tsorted and L.poff, free by then, as scratch).
+hipError_t launch_gauss_major_list(const WsLayout &L, char *ws, int V, hipStream_t s);
 hipError_t launch_render_fwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
                              const ugs_outputs &out, int batch, bool counters, int final_buf, hipStream_t s);
 hipError_t launch_render_bwd(const ugs_gaussians &g, const Problem &pb, const WsLayout &L, char *ws,
@@ -124,7 +129,8 @@ hipError_t launch_scan_flags(const uint32_t *flags, int64_t n, uint32_t *part, u
                              hipStream_t s);
 // Which record-index buffer (0: didx0, 1: didx1) holds the depth-sorted visible
 // records after launch_binsort (the depth sort flips buffers once per 8 bits).
-// L.vlist holds the same records in index order.
+// L.vlist holds the records that kept a tile, in (Gaussian, view) order, once
+// launch_gauss_major_list has run.
 // Passes of the LSD radix sort over `bits` key bits (digits of at most 8 bits).
 inline int radix_passes(int bits) { return (bits + 7) / 8; }
 inline int depth_sort_buffer(const WsLayout &L) { return radix_passes(L.depth_bits) & 1; }
