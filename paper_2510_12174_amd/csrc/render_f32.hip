@@ -330,8 +330,10 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
                 const uint64_t lo = ((uint64_t)m1 << 32) | m0;
                 uint64_t m = sh ? (lo >> sh) | ((uint64_t)m2 << (64 - sh)) : lo;
                 if (n - w0 < 64) m &= (1ull << (n - w0)) - 1ull;
-                m = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32) |
-                    __builtin_amdgcn_readfirstlane((uint32_t)m);
+                // (readfirstlane returns int: widen through uint32_t, or bit 31
+                // would be sign-extended into phantom entries 32..63)
+                m = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32) |
+                    (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)m);
                 while (m) {
                     const int j = w0 + __builtin_ctzll(m);
                     m &= m - 1ull;

@@ -595,6 +595,7 @@ class Rasterizer:
         up and grads both None, the forward-only step."""
         P = self.project_and_sort(g, cams)
         self.ensure_workspace(g, cams, max(int(P * margin) + 4096, self.pair_cap))
+        self._cap_args = (g, cams, out, up, grads)
         fwd_only = up is None and grads is None
         self._keep = [make_gaussians(g), make_cameras(cams), make_outputs(out),
                       None if fwd_only else make_upstream(up), None if fwd_only else make_grads(grads)]
@@ -616,6 +617,23 @@ class Rasterizer:
         _chk(lib().ugs_step_replay(self.ctx, _stream()), "ugs_step_replay", self.ctx)
         self.generation += 1  # the captured step projects again
         self.bwd_consumed = True
+
+    def replay_checked(self, margin=1.5):
+        """Replays the captured step, then synchronises and checks that its
+        pair count fitted the workspace (ugs_check_overflow).  If it did not (the
+        step's outputs and gradients are then zero), captures the step again
+        with room for the required pairs x margin, on the same tensors, and
+        replays it.  Returns True when it re-captured."""
+        self.replay()
+        P = C.c_int64()
+        rc = lib().ugs_check_overflow(self.ctx, self.ws_ptr, _stream(), C.byref(P))
+        if rc != UGS_ERR_CAPACITY:
+            _chk(rc, "ugs_check_overflow", self.ctx)
+            return False
+        self.pair_cap = max(self.pair_cap, int(P.value * margin) + 4096)
+        self.capture_step(*self._cap_args, margin=margin)
+        self.replay()
+        return True
 
     def autotune(self, g, cams, out, up, grads, cache=None):
         """ugs_autotune, with its choice cached in a JSON file keyed by

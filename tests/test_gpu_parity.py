@@ -458,6 +458,37 @@ def test_pair_capacity_overflow():
     assert e.value.code == U.UGS_ERR_CAPACITY
 
 
+def test_replay_checked_recaptures(O):
+    """Rasterizer.replay_checked: a captured step whose Gaussians grow past the
+    pair capacity is captured again with room for them and replayed, so the
+    outputs are those of the grown scene (equal to its eager forward, which
+    matches the oracle elsewhere), not the zero outputs of the overflowing
+    replay."""
+    import torch
+    from paper_2510_12174_amd import unigs as U
+    g, cams, opts = Hn.small_workload("w4s")
+    C_o = int(g["C_o"])
+    gd = U.to_device(g)
+    out = U.alloc_outputs(cams, C_o)
+    up = Hn.stack_upstream(Hn.scenes.upstream(cams, C_o, seed=2), C_o)
+    grads = U.zeros_like_params(gd)
+    rast = U.Rasterizer()
+    rast.capture_step(gd, cams, out, up, grads, margin=1.0)
+    assert rast.replay_checked() is False
+    cap = rast.pair_cap
+    gd["log_scale"].add_(2.0)  # 7x larger splats: more pairs than the capacity
+    Hn.say(f"[replay_checked] capacity {cap}; Gaussians grown")
+    assert rast.replay_checked() is True
+    torch.cuda.synchronize()
+    Hn.say(f"[replay_checked] re-captured with capacity {rast.pair_cap}")
+    assert rast.pair_cap > cap
+    ref = U.Rasterizer().forward(gd, cams)
+    torch.cuda.synchronize()
+    for k in ("rgb", "depth", "kmap", "T_final", "n_contrib"):
+        assert torch.equal(out[k], ref[k]), k
+    assert float(sum(float(v.abs().sum()) for v in grads.values())) > 0
+
+
 def test_autotune_and_cache(tmp_path):
     """ugs_autotune picks one of its candidates and leaves the forward outputs
     unchanged (bit for bit except the semantic map, to rounding); the binding
@@ -513,12 +544,15 @@ def test_maximum_view_count(O):
         Hn.gpu_run(g, cams + cams[:1], opts)
 
 
-@pytest.mark.parametrize("kind,batch", [("w4s", 24), ("w3s", 10), ("w1", 200)])
+@pytest.mark.parametrize("kind,batch", [("w4s", 24), ("w3s", 10), ("w1", 200), ("w5s", 32), ("w5s", 48),
+                                        ("w2c200", 96)])
 def test_odd_batch_sizes(O, kind, batch):
     """User-chosen LDS batch sizes that are not multiples of the matrix-core
     group (rounded up there) or exceed the tile's pixel count: forward outputs
     equal the default batch's (the semantic map to rounding), gradients agree
-    to float-atomic reordering."""
+    to float-atomic reordering.  The 128- and 200-channel cases run further
+    channel passes that walk the first pass's activity mask, in windows that
+    end inside a batch."""
     g, cams, opts = Hn.small_workload(kind)
     ups = Hn.scenes.upstream(cams, g["C_o"], seed=5)
     a, ga, _ = Hn.gpu_run(g, cams, opts, ups=ups)
