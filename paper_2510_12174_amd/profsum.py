@@ -57,10 +57,17 @@ def _per_kernel(path, counter):
 def traffic(fetch_csv, write_csv, kernel_sub, key, source, command):
     f = _per_kernel(fetch_csv, "FETCH_SIZE")
     w = _per_kernel(write_csv, "WRITE_SIZE")
-    copy_k = [k for k in f if "copy" in k.lower() or "elementwise" in k.lower()]
+    # the reference is the runtime's plain buffer copy of 1 GiB (its largest
+    # dispatch): other large torch kernels of the run (an index gather, a
+    # fill) move different byte counts and must not stand in for it
+    copy_k = [k for k in f if "copyBuffer" in k]
+    if not copy_k:
+        raise SystemExit("no plain copy kernel in the FETCH_SIZE run: was it made with --calibrate-copy?")
     big = lambda d, k: max(d.get(k, [0.0]))
-    cf = max((big(f, k) for k in copy_k), default=0.0)       # KiB read by the 1 GiB copy
+    cf = max(big(f, k) for k in copy_k)                      # KiB read by the 1 GiB copy
     cw = max((big(w, k) for k in copy_k if k in w), default=0.0)
+    if not (0.25 * COPY_BYTES <= cf * 1024 <= 4 * COPY_BYTES and 0.25 * COPY_BYTES <= cw * 1024 <= 4 * COPY_BYTES):
+        raise SystemExit(f"copy kernel counters {cf} / {cw} KiB do not look like a 1 GiB copy")
     fs = COPY_BYTES / (cf * 1024) if cf else 1.0
     ws = COPY_BYTES / (cw * 1024) if cw else 1.0
     # a stage may be several kernels (a first pass and channel-chunk passes),
