@@ -675,19 +675,33 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
             {
                 const int fa = __shfl(myact, min(g0 + l16, nact - 1), 64);
                 const float *arow = sfeat + fa * FS + KS * h16;
+                // 64 channels: four independent accumulators (one per 16-pixel
+                // block), so that each feature value is read from LDS once and
+                // the products issue back to back instead of as four dependent
+                // chains
+                // (the 32-channel form keeps one chain at a time: its 128
+                // registers have no room for the other three accumulators)
+                constexpr int PBI = CCH > 32 ? 4 : 1;
+                mf4 s4[4];
 #pragma unroll
-                for (int pb = 0; pb < 4; ++pb) {
-                    mf4 s4 = mf4{0.f, 0.f, 0.f, 0.f};
+                for (int pb = 0; pb < 4; ++pb) s4[pb] = mf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int pb0 = 0; pb0 < 4; pb0 += PBI) {
 #pragma unroll
                     for (int k4 = 0; k4 < KS / 4; ++k4) {
                         const float4 a = reinterpret_cast<const float4 *>(arow)[k4];
-                        s4 = mma(a.x, GSr[4 * k4][pb], s4);
-                        s4 = mma(a.y, GSr[4 * k4 + 1][pb], s4);
-                        s4 = mma(a.z, GSr[4 * k4 + 2][pb], s4);
-                        s4 = mma(a.w, GSr[4 * k4 + 3][pb], s4);
+#pragma unroll
+                        for (int pb = pb0; pb < pb0 + PBI; ++pb) {
+                            s4[pb] = mma(a.x, GSr[4 * k4][pb], s4[pb]);
+                            s4[pb] = mma(a.y, GSr[4 * k4 + 1][pb], s4[pb]);
+                            s4[pb] = mma(a.z, GSr[4 * k4 + 2][pb], s4[pb]);
+                            s4[pb] = mma(a.w, GSr[4 * k4 + 3][pb], s4[pb]);
+                        }
                     }
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) swb[(4 * h16 + r) * kSW + 16 * pb + l16] = s4[r];
+                    for (int pb = pb0; pb < pb0 + PBI; ++pb)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) swb[(4 * h16 + r) * kSW + 16 * pb + l16] = s4[pb][r];
                 }
             }
             __builtin_amdgcn_wave_barrier();
