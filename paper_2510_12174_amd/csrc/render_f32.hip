@@ -442,23 +442,30 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
         }
     }
     {
+        // value (q, r) of a lane is channel cl + CPL r + q: one base address
+        // per pixel block advanced by the (wavefront-uniform) plane size per
+        // channel, and the output type chosen once for all the stores
         const int W = cams[ti.v].W, H = cams[ti.v].H;
         const int qx0 = ti.px - (lane & 7), qy0 = ti.py - (lane >> 3);
+        const int cl = c0 + CPL * 4 * h16, nc = C_o - cl;
+        const int64_t HW = ti.HW;
+        auto store_all = [&](auto *dst) {
 #pragma unroll
-        for (int pb = 0; pb < 4; ++pb) {
-            const int pp = 16 * pb + l16;
-            const int x = qx0 + (pp & 7), y = qy0 + (pp >> 3);
-            if (x < W && y < H) {
-                const int64_t base = (int64_t)C_o * ti.off + (int64_t)y * W + x;
+            for (int pb = 0; pb < 4; ++pb) {
+                const int pp = 16 * pb + l16;
+                const int x = qx0 + (pp & 7), y = qy0 + (pp >> 3);
+                if (x < W && y < H) {
+                    auto *b = dst + ((int64_t)C_o * ti.off + (int64_t)cl * HW + (int64_t)y * W + x);
 #pragma unroll
-                for (int q = 0; q < CPL; ++q)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int c = c0 + CPL * (4 * h16 + r) + q;
-                        if (c < C_o) put_out(out.sem, base + (int64_t)c * ti.HW, acc[q][pb][r], half_out);
-                    }
+                    for (int k = 0; k < 4 * CPL; ++k, b += HW)  // channel cl + k
+                        if (k < nc) *b = acc[k % CPL][pb][k / CPL];
+                }
             }
-        }
+        };
+        if (half_out)
+            store_all(reinterpret_cast<_Float16 *>(out.sem));
+        else
+            store_all(out.sem);
     }
     if (tclk) {
         __syncthreads();
@@ -671,9 +678,15 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
             }
         }
         for (int g0 = 0; g0 < nact; g0 += kBGrp) {
+            // 64 channels: the Gaussian id of group row lane % 16, read now
+            // (beside the S products) so that the dO atomics below need one
+            // shuffle per row instead of a shuffle and a dependent LDS read
+            // (the 32-channel form has no register to hold it)
+            uint32_t gid_row = 0;
             // S for the group's 16 entries (rows past nact repeat an active entry; their w is 0)
             {
                 const int fa = __shfl(myact, min(g0 + l16, nact - 1), 64);
+                if constexpr (CCH > 32) gid_row = sidc[fa];
                 const float *arow = sfeat + fa * FS + KS * h16;
                 // 64 channels: four independent accumulators (one per 16-pixel
                 // block), so that each feature value is read from LDS once and
@@ -845,12 +858,14 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
                             unsafeAtomicAdd(&dsem[(int64_t)sidc[jf] * C_o + c0 + cl], x);
                     }
                 } else {
+                    uint32_t idr[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) idr[r] = (uint32_t)__shfl((int)gid_row, 4 * h16 + r, 64);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int f = 4 * h16 + r;
-                        const int jf = __shfl(myact, min(g0 + f, nact - 1), 64);
                         if (f < ng) {
-                            const int64_t row = (int64_t)sidc[jf] * C_o + c0;
+                            const int64_t row = (int64_t)idr[r] * C_o + c0;
 #pragma unroll
                             for (int cb = 0; cb < NCB; ++cb) {
                                 const float x = d4[cb][r];
