@@ -334,10 +334,18 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
                 // would be sign-extended into phantom entries 32..63)
                 m = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32) |
                     (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)m);
+                // the next marked entry's record is read while this one is
+                // used (an empty mask names the batch's last entry instead)
+                auto next_of = [&](uint64_t mm) { return min(w0 + (int)__builtin_ctzll(mm | (1ull << 63)), n - 1); };
+                int jn = next_of(m);
+                float4 n0 = srec[4 * jn], n1 = srec[4 * jn + 1];
                 while (m) {
-                    const int j = w0 + __builtin_ctzll(m);
+                    const int j = jn;
+                    const float4 r0 = n0, r1 = n1;
                     m &= m - 1ull;
-                    const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
+                    jn = next_of(m);
+                    n0 = srec[4 * jn];
+                    n1 = srec[4 * jn + 1];
                     const float dx = fx - r0.x, dy = fy - r0.y;
                     const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
                     const float alpha = fminf(kAlphaMax, r1.y * gauss_of(t1, t2));
@@ -724,26 +732,43 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
                 // chunk passes take the entries in pairs: the second entry's
                 // alpha arithmetic overlaps the first's, and one 16-value
                 // reduction and one atomic carry both entries' six slots
-                auto entry_sem = [&](int f, bool valid, float (&u)[8], int &jo) -> float {
-                    const int j = __builtin_amdgcn_readlane(myact, g0 + f);
-                    const uint32_t entry = start + (uint32_t)j;
-                    const float s_sem = swb[f * kSW + lane];
-                    const float4 r0 = srec[4 * j], r1 = srec[4 * j + 1];
+                // An entry's LDS operands (its S value and the alpha-test half
+                // of its record) are read one pair ahead, so that a pair's
+                // arithmetic does not start with a wait for them.
+                struct EntIn {
+                    int j;
+                    float s;
+                    float4 r0, r1;
+                };
+                auto entry_load = [&](int f) -> EntIn {
+                    EntIn e;
+                    e.j = __builtin_amdgcn_readlane(myact, g0 + f);
+                    e.s = swb[f * kSW + lane];
+                    e.r0 = srec[4 * e.j];
+                    e.r1 = srec[4 * e.j + 1];
+                    return e;
+                };
+                auto entry_sem = [&](const EntIn &e, bool valid, float (&u)[8]) -> float {
+                    const uint32_t entry = start + (uint32_t)e.j;
+                    const float4 r0 = e.r0, r1 = e.r1;
                     const float dx = fx - r0.x, dy = fy - r0.y;
                     const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
                     const float G = gauss_of(t1, t2);
                     const float oG = r1.y * G;
                     const float alpha = fminf(kAlphaMax, oG);
                     const bool contrib = valid && entry < last && alpha >= kAlphaMin;
-                    jo = j;
-                    return frag_adjoint_sem(contrib, r0, r1, dx, dy, t1, t2, G, oG, alpha, s_sem, T, A, u);
+                    return frag_adjoint_sem(contrib, r0, r1, dx, dy, t1, t2, G, oG, alpha, e.s, T, A, u);
                 };
+                EntIn ea = entry_load(0), eb = entry_load(min(1, ng - 1));
                 for (int f = 0; f < ng; f += 2) {
                     const bool has1 = f + 1 < ng;
                     float u0[8], u1[8], u[16];
-                    int id0, id1;
-                    const float w0 = entry_sem(f, true, u0, id0);
-                    const float w1 = entry_sem(has1 ? f + 1 : f, has1, u1, id1);
+                    const int id0 = ea.j, id1 = eb.j;
+                    const float w0 = entry_sem(ea, true, u0);
+                    const float w1 = entry_sem(eb, has1, u1);
+                    // (rows past ng reload the last entry; the loop ends before using them)
+                    ea = entry_load(min(f + 2, ng - 1));
+                    eb = entry_load(min(f + 3, ng - 1));
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
                         u[k] = u0[k];
@@ -971,9 +996,11 @@ hipError_t bwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayo
         if (pb.depth_mode == 2) UGS_BWD_MM(2, true);
         else if (pb.depth_mode == 1) UGS_BWD_MM(1, true);
         else UGS_BWD_MM(0, true);
-    } else {
+    } else if constexpr (CCH > 32) {
         if (pb.depth_mode == 2) UGS_BWD_MM(2, false);
         else UGS_BWD_MM(0, false);
+    } else {
+        return hipErrorInvalidValue;  // channel passes after the first are 64 wide
     }
 #undef UGS_BWD_MM
     return hipGetLastError();
