@@ -69,10 +69,12 @@ __host__ __device__ constexpr size_t fwd_mm_lds(int batch, int CCH, int NW, bool
     return (size_t)batch * (64 + 4 * feat_stride(CCH) + (hit ? 4 : 0)) + (size_t)NW * kFRows * 64 * 4;
 }
 
-// LDS bytes of the backward kernel.
-__host__ __device__ constexpr size_t bwd_mm_lds(int batch, int CCH, int NW, bool hit)
+// LDS bytes of the backward kernel (channel passes after the first hold a
+// second per-wavefront row buffer, for dpow and the moments).
+__host__ __device__ constexpr size_t bwd_mm_lds(int batch, int CCH, int NW, bool hit, bool main)
 {
-    return (size_t)batch * (64 + 4 * feat_stride(CCH) + 8 + (hit ? 4 : 0) + 64) + (size_t)NW * kBGrp * kSW * 4;
+    return (size_t)batch * (64 + 4 * feat_stride(CCH) + 8 + (hit ? 4 : 0) + 64) +
+           (size_t)(main ? 1 : 2) * NW * kBGrp * kSW * 4;
 }
 
 // Loads n floats from LDS (n = 1, 2, 4 or 8; 4-float aligned when n >= 4).
@@ -97,14 +99,15 @@ __device__ __forceinline__ void lds_row(const float *p, float (&x)[NF])
     }
 }
 
-// The semantic share of one reverse step (backward chunk passes): the same T
-// restoration and weight as frag_adjoint, s_i = s_sem (the chunk's part of the
-// dot product of the upstream gradients with the fragment's values), A the
-// chunk's running sum, and the record slots that depend on alpha only:
-// v[0..1] mean2d, v[2..4] Cholesky conic, v[5] opacity.
-__device__ __forceinline__ float frag_adjoint_sem(bool contrib, float4 r0, float4 r1, float dx, float dy, float t1,
-                                                  float t2, float G, float oG, float alpha, float s_sem, double &T,
-                                                  float &A, float (&v)[8])
+// The semantic share of one reverse step (backward channel passes after the
+// first): the same T restoration and weight as frag_adjoint, s_i = s_sem (this
+// pass's part of the dot product of the upstream gradients with the
+// fragment's values) and A this pass's running sum.  Returns the weight w and
+// sets dpow = dL/d(o G) of this share (zero through the 0.99 clamp): every
+// record slot it reaches (mean2d, Cholesky conic, opacity) is dpow times a
+// polynomial of degree <= 2 in the pixel offset.
+__device__ __forceinline__ float frag_weight_sem(bool contrib, float alpha, float oG, float s_sem, double &T,
+                                                 float &A, float &dpow)
 {
     const float rom = rcp_nr(1.f - alpha);
     const double Tn = contrib ? T * rcp64(1.0 - (double)alpha) : T;
@@ -112,16 +115,7 @@ __device__ __forceinline__ float frag_adjoint_sem(bool contrib, float4 r0, float
     const float dalpha = contrib ? (float)Tn * s_sem - A * rom : 0.f;
     A += w * s_sem;
     T = Tn;
-    const bool free_ = oG < kAlphaMax;  // no gradient through the 0.99 clamp
-    const float dpow = free_ ? dalpha * oG : 0.f;
-    v[5] = free_ ? dalpha * G : 0.f;
-    v[2] = -t1 * dx * dpow;
-    v[3] = -t1 * dy * dpow;
-    v[4] = -t2 * dy * dpow;
-    v[0] = t1 * r0.z * dpow;
-    v[1] = (t1 * r0.w + t2 * r1.x) * dpow;
-    v[6] = 0.f;
-    v[7] = 0.f;
+    dpow = oG < kAlphaMax ? dalpha * oG : 0.f;
     return w;
 }
 
@@ -536,6 +530,7 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
     float *shh = (float *)(sid + 2 * batch);
     float *sgr = shh + (HIT ? batch : 0);  // [batch][16] record-slot sums of the tile's wavefronts
     float *swb = sgr + (size_t)batch * 16 + wave * (kBGrp * kSW);
+    float *sdp = sgr + (size_t)batch * 16 + (NT / 64 + wave) * (kBGrp * kSW);  // channel passes: dpow, then moments
     for (int q = threadIdx.x; q < batch * 16; q += NT) sgr[q] = 0.f;
     const uint32_t slot = xcd_tile(blockIdx.x, ntiles);
     if (slot >= ntiles) return;
@@ -593,6 +588,24 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
         fill([&](int, int) { return 0.f; });
     }
 
+    // Channel passes: the B operand of the dpow moments, column n = lane % 16
+    // of phi = (1, x, y, x^2, x y, y^2) (zero past 5) at pixel 16 (lane / 16) + ks
+    // of the wavefront's 8 x 8 block, where x = ks % 8 and y = 2 (lane / 16) +
+    // ks / 8.  As a polynomial in x: phi = pa[ks / 8] + pb[ks / 8] x + pc x^2.
+    const float bx0 = (float)qx0, by0 = (float)qy0;  // the block's origin pixel
+    float pa[2], pb[2], pc;
+    {
+        const float y0 = (float)(2 * h16), y1 = y0 + 1.f;
+        pa[0] = l16 == 0 ? 1.f : l16 == 2 ? y0 : l16 == 5 ? y0 * y0 : 0.f;
+        pa[1] = l16 == 0 ? 1.f : l16 == 2 ? y1 : l16 == 5 ? y1 * y1 : 0.f;
+        pb[0] = l16 == 1 ? 1.f : l16 == 4 ? y0 : 0.f;
+        pb[1] = l16 == 1 ? 1.f : l16 == 4 ? y1 : 0.f;
+        pc = l16 == 3 ? 1.f : 0.f;
+    }
+    auto phi = [&](int ks) -> float {
+        const float x = (float)(ks & 7);
+        return pa[ks >> 3] + (pb[ks >> 3] + pc * x) * x;
+    };
     double T = 1.0;
     float gR = 0.f, gG = 0.f, gB = 0.f, gDp = 0.f, gK = 0.f;
     uint32_t last = 0;
@@ -729,12 +742,13 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
             // reverse walk over the group
             const int ng = min(kBGrp, nact - g0);
             if constexpr (!MAIN) {
-                // chunk passes take the entries in pairs: the second entry's
-                // alpha arithmetic overlaps the first's, and one 16-value
-                // reduction and one atomic carry both entries' six slots
-                // An entry's LDS operands (its S value and the alpha-test half
-                // of its record) are read one pair ahead, so that a pair's
-                // arithmetic does not start with a wait for them.
+                // Channel passes after the first: per entry only w (for the dO
+                // product below) and dpow, both to LDS rows; the record slots
+                // follow from moments of dpow after the walk.  Entries go in
+                // pairs (two independent alpha evaluations), and an entry's LDS
+                // operands (its S value and the alpha-test half of its record)
+                // are read one pair ahead, so that a pair's arithmetic does not
+                // start with a wait for them.
                 struct EntIn {
                     int j;
                     float s;
@@ -748,38 +762,34 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
                     e.r1 = srec[4 * e.j + 1];
                     return e;
                 };
-                auto entry_sem = [&](const EntIn &e, bool valid, float (&u)[8]) -> float {
+                auto entry_w = [&](const EntIn &e, bool valid, float &dp) -> float {
                     const uint32_t entry = start + (uint32_t)e.j;
                     const float4 r0 = e.r0, r1 = e.r1;
                     const float dx = fx - r0.x, dy = fy - r0.y;
                     const float t1 = r0.z * dx + r0.w * dy, t2 = r1.x * dy;
-                    const float G = gauss_of(t1, t2);
-                    const float oG = r1.y * G;
+                    const float oG = r1.y * gauss_of(t1, t2);
                     const float alpha = fminf(kAlphaMax, oG);
                     const bool contrib = valid && entry < last && alpha >= kAlphaMin;
-                    return frag_adjoint_sem(contrib, r0, r1, dx, dy, t1, t2, G, oG, alpha, e.s, T, A, u);
+                    return frag_weight_sem(contrib, alpha, oG, e.s, T, A, dp);
                 };
                 EntIn ea = entry_load(0), eb = entry_load(min(1, ng - 1));
                 for (int f = 0; f < ng; f += 2) {
                     const bool has1 = f + 1 < ng;
-                    float u0[8], u1[8], u[16];
-                    const int id0 = ea.j, id1 = eb.j;
-                    const float w0 = entry_sem(ea, true, u0);
-                    const float w1 = entry_sem(eb, has1, u1);
+                    float d0, d1;
+                    const float w0 = entry_w(ea, true, d0);
+                    const float w1 = entry_w(eb, has1, d1);
                     // (rows past ng reload the last entry; the loop ends before using them)
                     ea = entry_load(min(f + 2, ng - 1));
                     eb = entry_load(min(f + 3, ng - 1));
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        u[k] = u0[k];
-                        u[8 + k] = u1[k];
-                    }
-                    const float tot = reduce_scatter<16>(u);
-                    const int slot = lane >> 2, e1 = slot >> 3, k = slot & 7;
-                    if ((lane & 3) == 0 && k < 6 && (e1 == 0 || has1)) lds_add(&sgr[(e1 ? id1 : id0) * 16 + k], tot);
                     swb[f * kSW + lane] = w0;
-                    if (has1) swb[(f + 1) * kSW + lane] = w1;
+                    sdp[f * kSW + lane] = d0;
+                    if (has1) {
+                        swb[(f + 1) * kSW + lane] = w1;
+                        sdp[(f + 1) * kSW + lane] = d1;
+                    }
                 }
+                // (dpow rows past ng are left as they are: a product row
+                // depends only on its own A row, and those rows are not used)
                 for (int f = ng; f < kBGrp; ++f) swb[f * kSW + lane] = 0.f;
             }
             constexpr bool PAIR_MAIN = MAIN && CCH > 32;  // (the 32-channel form has no registers to spare)
@@ -901,6 +911,49 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH
                     }
                 }
             }
+            if constexpr (!MAIN) {
+                // M[f][n] = sum_p dpow_f[p] phi_n(p): B[k][n] = phi_n(pixel
+                // 16 (lane / 16) + ks) for step ks, output M[4 (lane / 16) + r][lane % 16]
+                mf4 m4 = mf4{0.f, 0.f, 0.f, 0.f};
+                const float *drow = sdp + l16 * kSW + 16 * h16;
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    const float4 a = reinterpret_cast<const float4 *>(drow)[k4];
+                    m4 = mma(a.x, phi(4 * k4), m4);
+                    m4 = mma(a.y, phi(4 * k4 + 1), m4);
+                    m4 = mma(a.z, phi(4 * k4 + 2), m4);
+                    m4 = mma(a.w, phi(4 * k4 + 3), m4);
+                }
+                const int jrow = __shfl(myact, min(g0 + lane, nact - 1), 64);  // entry of row `lane` (< 16)
+                if (l16 < 6) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) sdp[(4 * h16 + r) * kSW + l16] = m4[r];
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (lane < ng) {
+                    // the six record slots of entry row `lane` from its moments
+                    // about the block origin, re-centred on the entry's mean
+                    const float4 mq = *reinterpret_cast<const float4 *>(sdp + lane * kSW);
+                    const float2 mr = *reinterpret_cast<const float2 *>(sdp + lane * kSW + 4);
+                    const float M0 = mq.x, Mx = mq.y, My = mq.z, Mxx = mq.w, Mxy = mr.x, Myy = mr.y;
+                    const float4 r0 = srec[4 * jrow], r1 = srec[4 * jrow + 1];
+                    const float mx = r0.x - bx0, my = r0.y - by0;
+                    const float l11 = r0.z, l21 = r0.w, l22 = r1.x;
+                    // centred moments: sums of dpow (dx, dy, dx^2, dx dy, dy^2), d = pixel - mean
+                    const float Sx = Mx - mx * M0, Sy = My - my * M0;
+                    const float Sxx = (Mxx - mx * Mx) - mx * Sx;
+                    const float Sxy = (Mxy - my * Mx) - mx * Sy;
+                    const float Syy = (Myy - my * My) - my * Sy;
+                    const float St1 = l11 * Sx + l21 * Sy;  // sum of dpow t1
+                    float *gr = sgr + jrow * 16;
+                    lds_add(&gr[0], l11 * St1);
+                    lds_add(&gr[1], l21 * St1 + l22 * l22 * Sy);
+                    lds_add(&gr[2], -(l11 * Sxx + l21 * Sxy));
+                    lds_add(&gr[3], -(l11 * Sxy + l21 * Syy));
+                    lds_add(&gr[4], -l22 * Syy);
+                    lds_add(&gr[5], r1.y > 0.f ? M0 / r1.y : 0.f);  // sum of dalpha G = sum of dpow / o
+                }
+            }
             __builtin_amdgcn_wave_barrier();
         }
         n_prev = n;
@@ -985,8 +1038,9 @@ hipError_t bwd_mm_launch(const ugs_gaussians &g, const Problem &pb, const WsLayo
     constexpr int NW = TW * TH / 64;
     const bool hit = pb.depth_mode == 2, main_pass = c0 == 0;
     auto tclk = (counters && main_pass) ? (unsigned long long *)(ws + L.tclk + (size_t)pb.total_tiles * 16) : nullptr;
-    const int b = std::min(64, fit_batch(batch, 64 * 1024, [&](int x) { return bwd_mm_lds(x, CCH, NW, hit); }));
-    const size_t lds = bwd_mm_lds(b, CCH, NW, hit);
+    const int b =
+        std::min(64, fit_batch(batch, 64 * 1024, [&](int x) { return bwd_mm_lds(x, CCH, NW, hit, main_pass); }));
+    const size_t lds = bwd_mm_lds(b, CCH, NW, hit, main_pass);
 #define UGS_BWD_MM(DMV, MAINV)                                                                                    \
     hipLaunchKernelGGL((render_bwd_mm_kernel<TW, TH, CCH, DMV, MAINV>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), \
                        lds, s, cams, pb.V, pb.N, ranges, vals, rec, g.sem, pb.C_o, c0, out.T_final, out.n_contrib,   \
