@@ -85,6 +85,26 @@ def algorithmic(N, V_rec, P, Px, C_o, sh_deg, F_eval, F_contrib):
     return b, f_fwd, f_bwd
 
 
+def measured_copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (bytes read + written per second, median of
+    `reps` copies of `nbytes`): the attainable-bandwidth reference beside the
+    8 TB/s specification."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / float(np.median(ts))
+
+
 def binsort_bytes(R, P, tiles):
     """Algorithmic HBM bytes of the binning and sorting stage: the stable depth
     sort of the R visible records (4 passes of 8 bits: a 4-byte key read for
@@ -388,8 +408,8 @@ def cpu_baseline(torch, U, g_np, cams, opts, rast, out, budget_s=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", type=int, default=5)
     ap.add_argument("--secondary", type=int, default=4, help="second workload reported (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -430,6 +450,11 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    copy_bw = measured_copy_bandwidth(torch)
+    log(f"[bench] device-to-device copy of 1 GiB: {copy_bw / 1e9:.1f} GB/s (read + write)")
+    hbm = lambda nbytes, sec: dict(achieved_gbps=round(nbytes / sec / 1e9, 1), peak_gbps=PEAK_HBM / 1e9,
+                                   frac=round(nbytes / sec / PEAK_HBM, 4),
+                                   frac_of_copy=round(nbytes / sec / copy_bw, 4))
     g = U.to_device(g_np)
     up = device_upstream(torch, Px, C_o, 1000 * wl)
     out = U.alloc_outputs(cams, C_o)
@@ -560,9 +585,8 @@ def main():
         t_pr = (time.perf_counter() - t0) / reps
         floats = sum(int(g[k].numel()) for k in U.PARAM_KEYS) // N
         b_pr = 3 * 4 * floats * (N + n_kept) + 4 * N
-        prune_res = dict(ms=round(t_pr * 1e3, 3), kept=int(n_kept), gaussians=N, state_sets=2,
-                         achieved_gbps=round(b_pr / t_pr / 1e9, 1), peak_gbps=PEAK_HBM / 1e9,
-                         frac=round(b_pr / t_pr / PEAK_HBM, 4), note="includes the host read-back of the count")
+        prune_res = dict(ms=round(t_pr * 1e3, 3), kept=int(n_kept), gaussians=N, state_sets=2, **hbm(b_pr, t_pr),
+                         note="includes the host read-back of the count")
         log(f"[bench] prune {prune_res}")
         del moments
 
@@ -596,8 +620,7 @@ def main():
             del lossf
         b_l = (96 + 8 * C_o) * Px  # every input map read once, every gradient map written once
         loss_res = dict(ms=round(times["ms"], 3), fused_seeds_ms=round(times["fused_seeds_ms"], 3), alg_bytes=int(b_l),
-                        achieved_gbps=round(b_l / times["ms"] / 1e6, 1), peak_gbps=PEAK_HBM / 1e9,
-                        frac=round(b_l / (times["ms"] * 1e-3) / PEAK_HBM, 4), values=values)
+                        **hbm(b_l, times["ms"] * 1e-3), values=values)
         log(f"[bench] loss {loss_res}")
         del gt
 
@@ -606,8 +629,7 @@ def main():
     bs_bytes, bs_passes = binsort_bytes(V_rec, P, tiles)
     bs_ms = stage_ms["bin_sort"]
     bin_sort = dict(ms=round(bs_ms, 3), alg_bytes=int(bs_bytes), tile_sort_passes=bs_passes,
-                    achieved_gbps=round(bs_bytes / (bs_ms * 1e-3) / 1e9, 1),
-                    frac=round(bs_bytes / (bs_ms * 1e-3) / PEAK_HBM, 4))
+                    **hbm(bs_bytes, bs_ms * 1e-3))
     log(f"[bench] bin_sort {bin_sort}")
     k_ms = float(np.mean(kern))
     fl = None
@@ -641,7 +663,8 @@ def main():
                per_view=None if t_pv is None else dict(value=round(Px / t_pv / 1e3, 2), unit="MP/s",
                                                         ms_per_step=round(t_pv, 3)),
                forward_only=fwd_only, prune=prune_res, loss=loss_res, depth_modes=depth_modes,
-               step_hbm=dict(alg_bytes=int(b_alg), frac=round(b_alg / t_batched / PEAK_HBM, 4)),
+               step_hbm=dict(alg_bytes=int(b_alg), **hbm(b_alg, t_batched)),
+               copy_gbps=round(copy_bw / 1e9, 1),
                bin_sort=bin_sort,
                counts=dict(pairs=P, records=V_rec, evaluated=F_eval, contributing=F_contrib,
                            active_wavefront_entries=active),

@@ -69,6 +69,19 @@ def small_workload(kind, seed=0):
             c.update(W=W, H=H, fx=c["fx"] * s, fy=c["fy"] * s, cx=W / 2.0, cy=H / 2.0)
             small.append(c)
         return g, small, o
+    if kind == "wbig":
+        # ten large Gaussians (sigma 25-50 px, centres up to 25 px outside the
+        # view) with 128 channels: pixel offsets of up to ~180 px from the mean
+        # inside one 8 x 8 block, through a first pass and a channel pass
+        g, cams, o = scenes.tiny_scene(n=10, seed=11, W=160, H=120, C_o=128, sh_deg=1, f=120.0)
+        rng = np.random.Generator(np.random.PCG64(4411 + seed))
+        g = dict(g)
+        mean = np.array(g["mean"], copy=True)
+        mean[0] = rng.uniform(-2.2, 2.2, g["N"])
+        mean[1] = rng.uniform(-1.7, 1.7, g["N"])
+        g["mean"] = np.ascontiguousarray(mean, dtype=np.float32)
+        g["log_scale"] = np.ascontiguousarray(np.asarray(g["log_scale"]) + 1.3, dtype=np.float32)
+        return g, cams, o
     raise ValueError(kind)
 
 

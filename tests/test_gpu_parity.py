@@ -70,7 +70,7 @@ def _check_forward(O, kind, tile=(16, 16), normals_e2e=False, extra=None):
     return g, cams, opts, outs, ora, ms, rast
 
 
-@pytest.mark.parametrize("kind", ["w1", "w2s", "w2c12", "w2c200", "w3s", "w4s", "w5s"])
+@pytest.mark.parametrize("kind", ["w1", "w2s", "w2c12", "w2c200", "w3s", "w4s", "w5s", "wbig"])
 def test_forward_parity(O, kind):
     _check_forward(O, kind, normals_e2e=(kind == "w1"))
 
@@ -201,7 +201,7 @@ def _check_backward(O, kind, tile=(16, 16), per_view=False, with_normals=True, e
     return err, gr, ref
 
 
-@pytest.mark.parametrize("kind", ["w1", "w2s", "w2c12", "w2c200", "w3s", "w4s", "w5s"])
+@pytest.mark.parametrize("kind", ["w1", "w2s", "w2c12", "w2c200", "w3s", "w4s", "w5s", "wbig"])
 def test_backward_parity(O, kind):
     """Gradients of a random-weighted sum of all outputs (RGB, depth, gradient
     factor, semantics; normals only where the forward normal is end-to-end
