@@ -111,10 +111,10 @@ def binsort_bytes(R, P, tiles):
     the histogram, key and index read and written by the scatter), the two
     binning walks over the sorted records (index, rectangle and the 32 bytes of
     the culling record read; counts written, then the P (tile, index) pairs),
-    the stable tile sort of the pairs (as many passes as 8-bit digits cover the
+    the stable tile sort of the pairs (as many passes as 9-bit digits cover the
     tile ids: histogram read, pair read and written) and the per-tile ranges."""
     dp = 4
-    tp = -(-max(tiles - 1, 0).bit_length() // 8)
+    tp = -(-max(tiles - 1, 0).bit_length() // 9)
     return (R * dp * (4 + 16) + 2 * R * (4 + 8 + 32) + R * 8 + P * 8 + tp * P * (4 + 16) + P * 4 + tiles * 8), tp
 
 

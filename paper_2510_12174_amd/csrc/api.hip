@@ -252,8 +252,8 @@ WsLayout make_layout(const Problem &pb, int64_t pair_cap)
     L.keys1 = take(P * 4);
     L.vals0 = take(P * 4);
     L.vals1 = take(P * 4);
-    L.hist = take((size_t)256 * kSortBlocks * 4);
-    L.digit_tot = take(256 * 4);
+    L.hist = take((size_t)512 * kSortBlocks * 4);  // one row per digit of a 9-bit sort pass
+    L.digit_tot = take(512 * 4);
     L.ranges = take((size_t)pb.total_tiles * 8);
     L.gd = take(pix * 4);
     L.nadj = take(pix * 12 * 4);

@@ -9,7 +9,8 @@
 //      ellipse reaches, scan the counts and emit one (tile, index) pair per
 //      kept tile: pairs come out in (depth, index) order;
 //   4. stable LSD radix sort of the pairs by global tile id (32-bit keys, only
-//      the bits in use: two 8-bit passes up to 65,536 tiles);
+//      the bits in use, in passes of at most 9 bits: two passes up to 262,144
+//      tiles);
 //   5. per-tile [start, end) ranges.
 // Because every sort pass is stable and the compaction keeps index order, each
 // tile's list ends up in the unique (depth bits, index) order.  The pair count
@@ -323,7 +324,10 @@ __global__ void __launch_bounds__(256) walk_pairs(const DevCam *__restrict__ cam
     }
 }
 
-// Digit of `width` (<= 8) bits at `shift`.
+// Digits of a sort pass: at most kRadixBits bits, kRadix values.
+constexpr int kRadixBits = 9, kRadix = 1 << kRadixBits;
+
+// Digit of `width` (<= kRadixBits) bits at `shift`.
 template <typename K>
 __device__ __forceinline__ uint32_t digit_of(K key, int shift, int width)
 {
@@ -354,14 +358,14 @@ constexpr int kSortUnroll = 8;
 // digits of a group of 64 keys are often few (the top digit of tile ids that
 // are already ordered by their low bits), and lanes adding to one LDS word
 // serialise.
-constexpr int kHistCopies = 8;
+constexpr int kHistCopies = 4;
 
 template <typename K>
 __global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__ keys, const uint32_t *__restrict__ n_dev,
                                                            int shift, int width, uint32_t *__restrict__ hist)
 {
-    __shared__ uint32_t h[kHistCopies][256];
-    for (int d = threadIdx.x; d < kHistCopies * 256; d += kSortThreads) (&h[0][0])[d] = 0;
+    __shared__ uint32_t h[kHistCopies][kRadix];
+    for (int d = threadIdx.x; d < kHistCopies * kRadix; d += kSortThreads) (&h[0][0])[d] = 0;
     __syncthreads();
     uint32_t *hc = h[threadIdx.x % kHistCopies];
     const uint32_t P = *n_dev;
@@ -379,7 +383,9 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__
             if (tb + u * kSortThreads + threadIdx.x < b1) atomicAdd(&hc[digit_of(key[u], shift, width)], 1u);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < 256; d += kSortThreads) {
+    // all kRadix rows (zero past 2^width), so that no row keeps a count of an
+    // earlier, wider pass
+    for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
         uint32_t c = 0;
 #pragma unroll
         for (int k = 0; k < kHistCopies; ++k) c += h[k][d];
@@ -407,36 +413,49 @@ __global__ void __launch_bounds__(256) radix_scan_digit(uint32_t *__restrict__ h
     if (threadIdx.x == 0) digit_tot[blockIdx.x] = tot;
 }
 
-// Stable scatter of one block's chunk, in tiles of kScatTile keys.  Each of
+// Stable scatter of one block's chunk, in tiles of 256 ROUNDS keys.  Each of
 // the four wavefronts ranks its quarter of the tile 64 keys at a time (a key's
-// rank among equal digits below it in the wavefront comes from eight ballots,
-// plus the wavefront's running per-digit count in LDS); the per-digit counts
-// of the four wavefronts and of the tile are then scanned, every key is placed
-// at its digit-sorted position in an LDS copy of the tile, and the tile is
-// written out in that order, so each digit's run of keys leaves as consecutive
-// addresses instead of as scattered single words.
+// rank among equal digits below it in the wavefront comes from one ballot per
+// digit bit, plus the wavefront's running per-digit count in LDS); the
+// per-digit counts of the four wavefronts and of the tile are then scanned
+// (thread t owns digits 2t and 2t + 1), every key is placed at its
+// digit-sorted position in an LDS copy of the tile, and the tile is written out
+// in that order, so each digit's run of keys leaves as consecutive addresses
+// instead of as scattered single words.
 constexpr int kScatThreads = 256;
-constexpr int kScatRounds = 16;                          // 64-key rounds per wavefront and tile
-constexpr int kScatTile = kScatThreads * kScatRounds;    // keys per tile
-constexpr int kScatQuarter = kScatTile / 4;              // keys per wavefront and tile
+static_assert(kRadix == 2 * kScatThreads, "two digits per scatter thread");
 
-template <typename K>
-__global__ void __launch_bounds__(kScatThreads) radix_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
-                                                              K *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                              const uint32_t *__restrict__ n_dev, int shift,
-                                                              int width, const uint32_t *__restrict__ hist,
-                                                              const uint32_t *__restrict__ digit_tot)
+// ROUNDS: 64-key rounds per wavefront and tile (tile = 256 ROUNDS keys).  16
+// (4096 keys, four blocks per CU) in general; 32 (8192 keys, two blocks per
+// CU) for the first pass of the tile sort, whose digits arrive in random
+// order: twice the keys per tile double each digit's output run (2.8 against
+// 3.1 ms over 409M pairs; the second pass, whose input is ordered by the low
+// digit, is faster with the smaller tile: 2.4 against 2.8 ms).
+template <typename K, int ROUNDS>
+__global__ void __launch_bounds__(kScatThreads) __attribute__((amdgpu_waves_per_eu(ROUNDS > 16 ? 2 : 4)))
+radix_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
+              uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, int shift, int width,
+              const uint32_t *__restrict__ hist, const uint32_t *__restrict__ digit_tot)
 {
-    __shared__ uint32_t gbase[256], loff[256], tot[256], lds4[4];
-    __shared__ uint32_t wcnt[4][256];
+    constexpr int kScatRounds = ROUNDS;
+    constexpr int kScatTile = kScatThreads * kScatRounds;  // keys per tile
+    constexpr int kScatQuarter = kScatTile / 4;            // keys per wavefront and tile
+    // (counts and offsets within a tile fit 16 bits; a digit's tile total is
+    // the difference of neighbouring offsets: 39,952 bytes in all at 16
+    // rounds, four blocks per CU)
+    __shared__ uint32_t gbase[kRadix], lds4[4];
+    __shared__ uint16_t loff[kRadix], wcnt[4][kRadix];
     __shared__ K skey[kScatTile];
     __shared__ uint32_t sval[kScatTile];
     const int t = threadIdx.x, lane = __lane_id(), wave = t >> 6;
+    const int d0 = 2 * t, d1 = 2 * t + 1;
     {
         // global start of each digit's run for this block
         uint32_t total;
-        const uint32_t ex = block_excl_scan256(digit_tot[t], lds4, total);
-        gbase[t] = ex + hist[(size_t)t * kSortBlocks + blockIdx.x];
+        const uint32_t a0 = digit_tot[d0], a1 = digit_tot[d1];
+        const uint32_t ex = block_excl_scan256(a0 + a1, lds4, total);
+        gbase[d0] = ex + hist[(size_t)d0 * kSortBlocks + blockIdx.x];
+        gbase[d1] = ex + a0 + hist[(size_t)d1 * kSortBlocks + blockIdx.x];
     }
     const uint32_t P = *n_dev;
     const uint32_t per = ((P + kSortBlocks - 1) / kSortBlocks + 63) & ~63u;
@@ -444,7 +463,7 @@ __global__ void __launch_bounds__(kScatThreads) radix_scatter(const K *__restric
     const uint64_t lt = __lanemask_lt();
     for (uint64_t ts = b0; ts < b1; ts += kScatTile) {
         const uint32_t nt = (uint32_t)min((uint64_t)kScatTile, b1 - ts);
-        for (int d = lane; d < 256; d += 64) wcnt[wave][d] = 0;
+        for (int d = lane; d < kRadix; d += 64) wcnt[wave][d] = 0;
         K key[kScatRounds];
         uint32_t val[kScatRounds], pw[kScatRounds];
 #pragma unroll
@@ -461,23 +480,29 @@ __global__ void __launch_bounds__(kScatThreads) radix_scatter(const K *__restric
             const uint32_t d = digit_of(key[i], shift, width);
             const uint64_t peers = digit_peers(d, valid, width);
             const uint32_t rank = __popcll(peers & lt);
-            pw[i] = valid ? wcnt[wave][d] + rank : 0u;
+            pw[i] = valid ? (uint32_t)wcnt[wave][d] + rank : 0u;
             __builtin_amdgcn_wave_barrier();
-            if (valid && rank == 0) wcnt[wave][d] += __popcll(peers);
+            if (valid && rank == 0) wcnt[wave][d] = (uint16_t)(wcnt[wave][d] + __popcll(peers));
             __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
         {
             // per digit: offsets of the four wavefronts' keys, tile total, local start
-            const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
-            wcnt[0][t] = 0;
-            wcnt[1][t] = c0;
-            wcnt[2][t] = c0 + c1;
-            wcnt[3][t] = c0 + c1 + c2;
-            const uint32_t td = c0 + c1 + c2 + c3;
-            tot[t] = td;
+            uint32_t td[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int d = d0 + k;
+                const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
+                wcnt[0][d] = 0;
+                wcnt[1][d] = (uint16_t)c0;
+                wcnt[2][d] = (uint16_t)(c0 + c1);
+                wcnt[3][d] = (uint16_t)(c0 + c1 + c2);
+                td[k] = c0 + c1 + c2 + c3;
+            }
             uint32_t total;
-            loff[t] = block_excl_scan256(td, lds4, total);
+            const uint32_t ex = block_excl_scan256(td[0] + td[1], lds4, total);
+            loff[d0] = (uint16_t)ex;
+            loff[d1] = (uint16_t)(ex + td[0]);
         }
         __syncthreads();
 #pragma unroll
@@ -485,7 +510,7 @@ __global__ void __launch_bounds__(kScatThreads) radix_scatter(const K *__restric
             const uint32_t li = (uint32_t)(wave * kScatQuarter + i * 64 + lane);
             if (li < nt) {
                 const uint32_t d = digit_of(key[i], shift, width);
-                const uint32_t lp = loff[d] + wcnt[wave][d] + pw[i];
+                const uint32_t lp = (uint32_t)loff[d] + wcnt[wave][d] + pw[i];
                 skey[lp] = key[i];
                 sval[lp] = val[i];
             }
@@ -494,12 +519,14 @@ __global__ void __launch_bounds__(kScatThreads) radix_scatter(const K *__restric
         for (uint32_t i = (uint32_t)t; i < nt; i += kScatThreads) {
             const K k = skey[i];
             const uint32_t d = digit_of(k, shift, width);
-            const uint32_t g = gbase[d] + (i - loff[d]);
+            const uint32_t g = gbase[d] + (i - (uint32_t)loff[d]);
             kout[g] = k;
             vout[g] = sval[i];
         }
         __syncthreads();
-        gbase[t] += tot[t];
+        const uint32_t o0 = loff[d0], o1 = loff[d1], o2 = d1 + 1 < kRadix ? (uint32_t)loff[d1 + 1] : nt;
+        gbase[d0] += o1 - o0;
+        gbase[d1] += o2 - o1;
         __syncthreads();
     }
 }
@@ -550,18 +577,22 @@ void scan(const ScanIn &si, int nb, uint32_t *part, uint32_t *out, int64_t cap, 
 // digit and LDS tile, and fewer digits per pass make those runs longer.
 template <typename K>
 int radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t *n_dev, int bits, uint32_t *hist,
-               uint32_t *dtot, hipStream_t s)
+               uint32_t *dtot, bool wide_first, hipStream_t s)
 {
     K *k[2] = {k0, k1};
     uint32_t *v[2] = {v0, v1};
     int cur = 0;
     const int passes = radix_passes(bits);
     for (int p = 0, shift = 0; p < passes; ++p) {
-        const int width = (bits - shift + (passes - p) - 1) / (passes - p);
+        // even split, the wider digits last: the first pass sees digits in
+        // random order (its output runs are shortest), the last only the few
+        // top-digit values that the key range reaches
+        const int width = (bits - shift) / (passes - p);
         hipLaunchKernelGGL(radix_hist<K>, dim3(kSortBlocks), dim3(kSortThreads), 0, s, (const K *)k[cur], n_dev, shift,
                            width, hist);
-        hipLaunchKernelGGL(radix_scan_digit, dim3(256), dim3(256), 0, s, hist, dtot);
-        hipLaunchKernelGGL(radix_scatter<K>, dim3(kSortBlocks), dim3(kScatThreads), 0, s, (const K *)k[cur],
+        hipLaunchKernelGGL(radix_scan_digit, dim3(kRadix), dim3(256), 0, s, hist, dtot);
+        auto scat = wide_first && p == 0 ? radix_scatter<K, 32> : radix_scatter<K, 16>;
+        hipLaunchKernelGGL(scat, dim3(kSortBlocks), dim3(kScatThreads), 0, s, (const K *)k[cur],
                            (const uint32_t *)v[cur], k[cur ^ 1], v[cur ^ 1], n_dev, shift, width,
                            (const uint32_t *)hist, (const uint32_t *)dtot);
         shift += width;
@@ -619,7 +650,7 @@ hipError_t launch_binsort(const Problem &pb, const WsLayout &L, char *ws, hipStr
         hipLaunchKernelGGL(compact_visible, dim3(vn_blocks), dim3(256), 0, s, L.N, VN, (const uint32_t *)touched,
                            (const uint32_t *)voff, (const uint32_t *)dk1, dk0, di0);
     // 2. sort by depth
-    const int dcur = radix_sort<uint32_t>(dk0, di0, dk1, di1, &cnt->R, L.depth_bits, hist, dtot, s);
+    const int dcur = radix_sort<uint32_t>(dk0, di0, dk1, di1, &cnt->R, L.depth_bits, hist, dtot, false, s);
     uint32_t *didx = dcur ? di1 : di0;
     // 3. tile counts in depth order, pair offsets, emission
     hipLaunchKernelGGL(walk_pairs<false>, dim3(gs_blocks), dim3(256), 0, s, cams, L.N, (const uint32_t *)didx, rect,
@@ -631,7 +662,7 @@ hipError_t launch_binsort(const Problem &pb, const WsLayout &L, char *ws, hipStr
                        rec, pb.tile_w, pb.tile_h, (const DevCounters *)cnt, tsorted, touched, (const uint32_t *)poff,
                        L.pair_cap, k0, v0);
     // 4. stable sort of the pairs by tile
-    const int cur = radix_sort<uint32_t>(k0, v0, k1, v1, &cnt->P_eff, L.tile_bits, hist, dtot, s);
+    const int cur = radix_sort<uint32_t>(k0, v0, k1, v1, &cnt->P_eff, L.tile_bits, hist, dtot, true, s);
     // 5. ranges
     if ((e = launch_fill_u32((uint32_t *)ranges, 0u, 2 * L.total_tiles, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(tile_ranges, dim3(4096), dim3(256), 0, s, (const uint32_t *)(cur ? k1 : k0),

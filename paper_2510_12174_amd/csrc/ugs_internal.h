@@ -132,7 +132,8 @@ hipError_t launch_scan_flags(const uint32_t *flags, int64_t n, uint32_t *part, u
 // L.vlist holds the records that kept a tile, in (Gaussian, view) order, once
 // launch_gauss_major_list has run.
 // Passes of the LSD radix sort over `bits` key bits (digits of at most 8 bits).
-inline int radix_passes(int bits) { return (bits + 7) / 8; }
+// passes of the LSD radix sorts: digits of at most 9 bits, split evenly
+inline int radix_passes(int bits) { return (bits + 8) / 9; }
 inline int depth_sort_buffer(const WsLayout &L) { return radix_passes(L.depth_bits) & 1; }
 int channel_pad(int C_o);
 

@@ -565,8 +565,11 @@ def test_odd_batch_sizes(O, kind, batch):
     for k in Hn.PARAMS:
         u, w = ga[k], gb[k]
         if u.size:
+            # the order of the float atomics that sum an element is not fixed,
+            # so an element may round differently by a few of its own ulps
+            # (2^-20 relative: 16 ulps) beside the rms-scaled bound
             rms = np.sqrt(np.mean(u * u)) + 1e-30
-            assert np.abs(u - w).max() <= 1e-4 * rms, k
+            assert np.all(np.abs(u - w) <= 1e-4 * rms + 2.0 ** -20 * np.abs(u)), k
 
 
 def test_autograd_function_matches_oracle(O):
