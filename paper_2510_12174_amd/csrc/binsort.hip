@@ -572,9 +572,10 @@ void scan(const ScanIn &si, int nb, uint32_t *part, uint32_t *out, int64_t cap, 
 }
 
 // Sorts (keys, vals) in place over bits [0, bits); returns the buffer index
-// (0: k0/v0, 1: k1/v1) holding the result.  The passes split the bits evenly
-// (17 bits: 6 + 6 + 5) rather than 8 + 8 + 1: a scatter pass writes one run per
-// digit and LDS tile, and fewer digits per pass make those runs longer.
+// (0: k0/v0, 1: k1/v1) holding the result.  Passes of at most 9 bits, split
+// evenly (17 bits: 8 + 9, not 9 + 8): a scatter pass writes one run per digit
+// and LDS tile, so the first pass, whose digits come in random order, gets the
+// narrower digit and (with wide_first) the larger tile.
 template <typename K>
 int radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, const uint32_t *n_dev, int bits, uint32_t *hist,
                uint32_t *dtot, bool wide_first, hipStream_t s)

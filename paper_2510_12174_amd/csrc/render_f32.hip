@@ -501,12 +501,15 @@ __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(4))
 // reads its S there and overwrites it with w.  dO[f][c] = sum_p w_f[p] G_p[c]:
 // A[m = f][k] = w_f[16 (lane / 16) + ks], output D[f][c], added to the
 // semantic gradient of entry f.  MAIN passes (c0 = 0) carry every term of the
-// fragment adjoint and the 16 record slots; chunk passes (c0 > 0) only the
-// semantic share of the alpha gradient, i.e. record slots 0..5 (mean2d, conic,
-// opacity).  The record-slot sums of the tile's wavefronts meet in LDS (one
-// row of 16 per batch entry) and go to the gradient records with one atomic
-// per entry and slot when the next batch is staged; the dO rows (CCH floats
-// per entry) go straight from the matrix layout to the semantic gradients.
+// fragment adjoint and the 16 record slots (reduced over the wavefront's
+// lanes); 64-channel passes after the first (c0 > 0) only the semantic share
+// of the alpha gradient, i.e. record slots 0..5 (mean2d, conic, opacity), which
+// they take from six pixel moments of dpow = dL/d(o G) with one more product,
+// M[f][n] = sum_p dpow_f[p] phi_n(p).  The record-slot sums of the tile's
+// wavefronts meet in LDS (one row of 16 per batch entry) and go to the
+// gradient records with one atomic per entry and slot when the next batch is
+// staged; the dO rows (CCH floats per entry) go straight from the matrix
+// layout to the semantic gradients.
 template <int TW, int TH, int CCH, int DM, bool MAIN>
 __global__ void __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(CCH > 32 ? 2 : 4))) render_bwd_mm_kernel(
     const DevCam *__restrict__ cams, int V, int64_t N, const uint2 *__restrict__ ranges,

@@ -127,13 +127,13 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 // part holds ceil(n / kScanBlock) partials.
 hipError_t launch_scan_flags(const uint32_t *flags, int64_t n, uint32_t *part, uint32_t *out, uint32_t *total,
                              hipStream_t s);
+// Passes of the LSD radix sorts over `bits` key bits: digits of at most 9 bits,
+// the bits split evenly.
+inline int radix_passes(int bits) { return (bits + 8) / 9; }
 // Which record-index buffer (0: didx0, 1: didx1) holds the depth-sorted visible
-// records after launch_binsort (the depth sort flips buffers once per 8 bits).
+// records after launch_binsort (the depth sort flips buffers once per pass).
 // L.vlist holds the records that kept a tile, in (Gaussian, view) order, once
 // launch_gauss_major_list has run.
-// Passes of the LSD radix sort over `bits` key bits (digits of at most 8 bits).
-// passes of the LSD radix sorts: digits of at most 9 bits, split evenly
-inline int radix_passes(int bits) { return (bits + 8) / 9; }
 inline int depth_sort_buffer(const WsLayout &L) { return radix_passes(L.depth_bits) & 1; }
 int channel_pad(int C_o);
 
