@@ -29,6 +29,12 @@ def small_workload(kind, seed=0):
         cam = scenes.camera(200, 150, 187.5, 187.5, 100, 75,
                             np.array([[0.0, -1.0, 0.0], [0.0, 0.0, -1.0], [1.0, 0.0, 0.0]]), [0, 0, 2.5])
         return scenes.make_scene(2, r=seed, N=20000, views=[cam])
+    if kind == "w2m":
+        # the 640 x 480 view of workload 2 with 20,000 Gaussians: at 8 x 8 tiles
+        # 4,800 tiles (13 bits, a two-pass tile sort)
+        cam = scenes.camera(640, 480, 600, 600, 320, 240,
+                            np.array([[0.0, -1.0, 0.0], [0.0, 0.0, -1.0], [1.0, 0.0, 0.0]]), [0, 0, 2.5])
+        return scenes.make_scene(2, r=seed, N=20000, views=[cam])
     if kind == "w2c12":
         # 12 semantic channels: padded to 16 inside the kernels, so the padding
         # lanes of every channel block are exercised

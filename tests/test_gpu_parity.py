@@ -127,7 +127,8 @@ def test_project_stage(O):
                       & (np.abs(P["mean2d"][:, 0] - 100) < 50) & (np.abs(P["mean2d"][:, 1] - 75) < 40))
 
 
-@pytest.mark.parametrize("kind,tile", [("w1", (16, 16)), ("w4s", (16, 16)), ("w4s", (8, 8)), ("w2s", (32, 8))])
+@pytest.mark.parametrize("kind,tile", [("w1", (16, 16)), ("w4s", (16, 16)), ("w4s", (8, 8)), ("w2s", (32, 8)),
+                                       ("w2m", (8, 8))])
 def test_binsort_bit_exact(O, kind, tile):
     """The GPU's tile lists against the plain definition (section 3.4: each
     tile's list holds the Gaussians that reach one of its pixels with
