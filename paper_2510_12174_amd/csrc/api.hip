@@ -785,6 +785,10 @@ int ugs_autotune(ugs_ctx *ctx, const ugs_gaussians *g, const ugs_camera *cams, i
         // twice the default batch: fewer barriers, more LDS (at most 64 KB,
         // since the default fits in 32 KB)
         if (2 * b <= 1024) cands.push_back({t[0], t[1], 2 * b});
+        // one and a half times (a multiple of 16): the 3M-Gaussian 128-channel
+        // step takes its forward passes fastest at 96 with a default of 64
+        const int b3 = (3 * b / 2 + 15) / 16 * 16;
+        if (b3 > b && b3 < 2 * b) cands.push_back({t[0], t[1], b3});
         if (b / 2 >= 16) cands.push_back({t[0], t[1], b / 2});
         if (b / 4 >= 16) cands.push_back({t[0], t[1], b / 4});
     }
