@@ -234,8 +234,9 @@ __device__ __forceinline__ bool walk_hit(const WalkRec &k, uint32_t q, int tile_
 // The binning walk over the depth-sorted records, one wavefront per run of 64:
 // the records' rectangles are laid end to end (an inclusive scan of their
 // areas), and the wavefront walks that run 64 tiles at a time with every lane
-// busy -- each lane finds its record by binary search over the scan, reads it
-// from LDS and tests its tile against the alpha ellipse.  Per-record counts of
+// busy -- each lane finds its record in the scan (stepping through the few
+// records a chunk overlaps, else by binary search), reads it from LDS and
+// tests its tile against the alpha ellipse.  Per-record counts of
 // kept tiles live in LDS.  COUNT: writes the counts (in depth order and back to
 // the records).  EMIT: writes each kept tile's (tile, index) pair at the
 // record's offset plus the number of kept tiles before it, never past the
@@ -281,19 +282,34 @@ __global__ void __launch_bounds__(256) walk_pairs(const DevCam *__restrict__ cam
         wr[lane] = mine;
         wc[lane] = 0;
         __builtin_amdgcn_wave_barrier();
+        int kc = 0;  // first record that ends after t0 (wavefront-uniform)
         for (uint32_t t0 = 0; t0 < total; t0 += 64) {
             const uint32_t t = t0 + (uint32_t)lane;
             const bool valid = t < total;
-            // record of position t: the first k with incl[k] > t
-            int lo = 0, hi = 63;
-#pragma unroll
-            for (int it = 0; it < 6; ++it) {
-                const int mid = (lo + hi) >> 1;
-                const uint32_t v = (uint32_t)__shfl((int)incl, mid, 64);
-                if (v > t) hi = mid;
-                else lo = mid + 1;
+            // record of position t: the first k with incl[k] > t.  A chunk of
+            // 64 positions usually overlaps a few records: step through them
+            // with uniform lane reads (no LDS round trip); a chunk that
+            // overlaps more than eight takes a binary search instead.
+            while (kc < 63 && (uint32_t)__builtin_amdgcn_readlane((int)incl, kc) <= t0) ++kc;
+            int kf = kc, kk = kc;
+            uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)incl, kc);
+            for (int it = 0; it < 8 && e < t0 + 64u && kk < 63; ++it) {
+                ++kk;
+                kf = t >= e ? kk : kf;
+                e = (uint32_t)__builtin_amdgcn_readlane((int)incl, kk);
             }
-            const int k = valid ? lo : 63;
+            if (e < t0 + 64u && kk < 63) {
+                int lo = 0, hi = 63;
+#pragma unroll
+                for (int it = 0; it < 6; ++it) {
+                    const int mid = (lo + hi) >> 1;
+                    const uint32_t v = (uint32_t)__shfl((int)incl, mid, 64);
+                    if (v > t) hi = mid;
+                    else lo = mid + 1;
+                }
+                kf = lo;
+            }
+            const int k = valid ? kf : 63;
             const WalkRec kr = wr[k];
             uint32_t tile = 0;
             const bool hit = valid && walk_hit(kr, t - kr.start, tile_w, tile_h, tile);
