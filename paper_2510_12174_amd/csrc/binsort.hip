@@ -179,8 +179,6 @@ __global__ void __launch_bounds__(256) gauss_emit(int64_t N, int V, const uint32
     }
 }
 
-// Tile counts in depth order (grid-stride up to the device count R).
-
 // One depth-sorted record as the binning walk sees it: rectangle, view
 // geometry and the culling data of its FP32 projection record (96 B, so that
 // a wavefront can stage its 64 records in LDS).
