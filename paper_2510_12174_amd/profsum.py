@@ -96,8 +96,10 @@ def counters(csv_paths, kernel_sub, key, source, command, simds=1024, xcds=8):
     (medians over dispatches) and the fractions derived from them: VALU issue
     (a wave64 vector instruction holds a 16-lane SIMD for 4 cycles), FP32
     matrix-pipe busy (SQ_VALU_MFMA_BUSY_CYCLES over the SIMD cycles), LDS bank
-    conflict cycles over LDS active cycles, and the average resident wavefronts
-    per SIMD (SQ_WAVE_CYCLES counts wave-cycles in units of 4 cycles).
+    conflict cycles over LDS active cycles, the average resident wavefronts
+    per SIMD (SQ_WAVE_CYCLES counts wave-cycles in units of 4 cycles) and the
+    VALU-active fraction (SQ_ACTIVE_INST_VALU, quad-cycles, over the SIMD
+    cycles).
     GRBM_GUI_ACTIVE is summed over the XCDs.  Stored in profiles/counters.json."""
     per_k = {}
     for path in csv_paths:
@@ -128,6 +130,8 @@ def counters(csv_paths, kernel_sub, key, source, command, simds=1024, xcds=8):
                 der["mfma_busy_fraction"] = m["SQ_VALU_MFMA_BUSY_CYCLES"] / (simds * cyc)
             if "SQ_WAVE_CYCLES" in m:
                 der["waves_per_simd"] = 4.0 * m["SQ_WAVE_CYCLES"] / (simds * cyc)
+            if "SQ_ACTIVE_INST_VALU" in m:
+                der["valu_active_fraction"] = 4.0 * m["SQ_ACTIVE_INST_VALU"] / (simds * cyc)
         if m.get("SQ_ACTIVE_INST_LDS"):
             der["lds_bank_conflict_fraction"] = m.get("SQ_LDS_BANK_CONFLICT", 0.0) / m["SQ_ACTIVE_INST_LDS"]
         return der
