@@ -10,10 +10,11 @@
 // because p is linear in the pixel coordinate; D+ - D- is exact in FP32 for
 // nearby depths, which keeps the normal accurate where the depths nearly cancel.
 //
-// The backward is a gather: a first pass stores, per pixel, the adjoints of its
-// four finite-difference vectors (12 floats); a second pass lets every pixel
-// collect the terms of the up to eight stencils that read it.  No atomics, so
-// the result is deterministic.
+// The backward is a gather: the adjoints of every pixel's four finite-difference
+// vectors (12 floats) are formed first, then every pixel collects the terms of
+// the up to eight stencils that read it -- in LDS within one workgroup (tile
+// plus a halo of the larger step) for steps up to kHaloMax, else through memory
+// in two passes.  No atomics, so the result is deterministic.
 #include "ugs_internal.h"
 
 namespace ugs {
@@ -116,37 +117,29 @@ __global__ void __launch_bounds__(TW *TH) normal_fwd_kernel(const DevCam *__rest
     put_out(normal, o + 2 * HW + p, N[2], half_out);
 }
 
-// Pass 1: adjoints of (vx1, vy1, vx2, vy2) in the camera frame, planar [12][pixels].
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW *TH) normal_adj_kernel(const DevCam *__restrict__ cams, int V, uint32_t ntiles,
-                                                           const float *__restrict__ depth,
-                                                           const float *__restrict__ dnormal,
-                                                           const float *__restrict__ ntgt,
-                                                           const float *__restrict__ nscale, int64_t total_pix,
-                                                           float *__restrict__ adj, int s1, int s2, float lam,
-                                                           int orient)
+// Adjoints of pixel (u, v)'s four finite-difference vectors (vx1, vy1, vx2,
+// vy2) in the camera frame, from the upstream normal gradient of the pixel (or
+// the fused cosine seed, scale * N_target).  D, dn and nt point at the view's
+// first pixel (dn and nt: three planes of W H).
+__device__ __forceinline__ void normal_adj_at(const DevCam &cam, const float *D, const float *dn, const float *nt,
+                                              float nsc, int u, int v, int s1, int s2, float lam, int orient,
+                                              float (&out)[12])
 {
-    int view, u, v;
-    if (!pixel_of<TW, TH>(cams, V, ntiles, view, u, v)) return;
-    const DevCam &cam = cams[view];
-    const int64_t HW = (int64_t)cam.W * cam.H, p = (int64_t)v * cam.W + u, gp = cam.pix_off + p;
-    float out[12];
+    const int64_t HW = (int64_t)cam.W * cam.H, p = (int64_t)v * cam.W + u;
     for (int k = 0; k < 12; ++k) out[k] = 0.f;
     float gw[3] = {0.f, 0.f, 0.f};
-    if (dnormal) {
-        const float *dn = dnormal + 3 * cam.pix_off;
+    if (dn) {
         gw[0] = dn[p];
         gw[1] = dn[HW + p];
         gw[2] = dn[2 * HW + p];
-    } else if (ntgt) {  // fused cosine seed: scale * N_target
-        const float *nt = ntgt + 3 * cam.pix_off, sc = *nscale;
-        gw[0] = sc * nt[p];
-        gw[1] = sc * nt[HW + p];
-        gw[2] = sc * nt[2 * HW + p];
+    } else if (nt) {
+        gw[0] = nsc * nt[p];
+        gw[1] = nsc * nt[HW + p];
+        gw[2] = nsc * nt[2 * HW + p];
     }
     if (gw[0] != 0.f || gw[1] != 0.f || gw[2] != 0.f) {
         NState S;
-        normal_state(depth + cam.pix_off, cam, u, v, s1, s2, lam, orient, S);
+        normal_state(D, cam, u, v, s1, s2, lam, orient, S);
         if (S.state == 2) {
             const float *R = cam.R;
             float g[3];
@@ -164,11 +157,56 @@ __global__ void __launch_bounds__(TW *TH) normal_adj_kernel(const DevCam *__rest
             }
         }
     }
+}
+
+// The gather for pixel (u, v): the terms of the up to eight stencils that read
+// it, adj(k, du, dv) giving adjoint k of the stencil centred at (u + du, v + dv),
+// projected on dP/dD = R^T p.
+template <typename A>
+__device__ __forceinline__ float normal_gather_at(const DevCam &cam, int u, int v, int s1, int s2, A adj)
+{
+    const int W = cam.W, H = cam.H;
+    float gP[3] = {0.f, 0.f, 0.f};
+    const int gs[2] = {s1, s2};
+    for (int k = 0; k < 2; ++k) {
+        const int g = gs[k];
+        // this pixel is (u+g, v) of the stencil at (u-g, v): + d/d vx
+        if (u - g >= 0)
+            for (int c = 0; c < 3; ++c) gP[c] += adj(6 * k + c, -g, 0);
+        if (u + g < W)
+            for (int c = 0; c < 3; ++c) gP[c] -= adj(6 * k + c, g, 0);
+        if (v - g >= 0)
+            for (int c = 0; c < 3; ++c) gP[c] += adj(6 * k + 3 + c, 0, -g);
+        if (v + g < H)
+            for (int c = 0; c < 3; ++c) gP[c] -= adj(6 * k + 3 + c, 0, g);
+    }
+    const float pp[3] = {((float)u - cam.cx) / cam.fx, ((float)v - cam.cy) / cam.fy, 1.f};
+    return dot3(gP, pp);
+}
+
+// Pass 1 of the two-pass form: adjoints, planar [12][pixels].
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW *TH) normal_adj_kernel(const DevCam *__restrict__ cams, int V, uint32_t ntiles,
+                                                           const float *__restrict__ depth,
+                                                           const float *__restrict__ dnormal,
+                                                           const float *__restrict__ ntgt,
+                                                           const float *__restrict__ nscale, int64_t total_pix,
+                                                           float *__restrict__ adj, int s1, int s2, float lam,
+                                                           int orient)
+{
+    int view, u, v;
+    if (!pixel_of<TW, TH>(cams, V, ntiles, view, u, v)) return;
+    const DevCam &cam = cams[view];
+    const int64_t gp = cam.pix_off + (int64_t)v * cam.W + u;
+    float out[12];
+    normal_adj_at(cam, depth + cam.pix_off, dnormal ? dnormal + 3 * cam.pix_off : nullptr,
+                  ntgt ? ntgt + 3 * cam.pix_off : nullptr, ntgt && !dnormal ? *nscale : 0.f, u, v, s1, s2, lam,
+                  orient, out);
     for (int k = 0; k < 12; ++k) adj[k * total_pix + gp] = out[k];
 }
 
-// Pass 2: gather the stencil adjoints that reference this pixel and project on
-// dP/dD = R^T p; adds the direct depth gradient and writes G_D.
+// Pass 2 of the two-pass form: gathers the stored adjoints, adds the direct
+// depth gradient and writes G_D.
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW *TH) normal_gather_kernel(const DevCam *__restrict__ cams, int V, uint32_t ntiles,
                                                               const float *__restrict__ adj, int64_t total_pix,
@@ -178,35 +216,62 @@ __global__ void __launch_bounds__(TW *TH) normal_gather_kernel(const DevCam *__r
     int view, u, v;
     if (!pixel_of<TW, TH>(cams, V, ntiles, view, u, v)) return;
     const DevCam &cam = cams[view];
-    const int W = cam.W, H = cam.H;
-    const int64_t base = cam.pix_off;
-    const int64_t p = (int64_t)v * W + u;
-    float gP[3] = {0.f, 0.f, 0.f};
-    const int gs[2] = {s1, s2};
-    for (int k = 0; k < 2; ++k) {
-        const int g = gs[k];
-        // this pixel is (u+g, v) of the stencil at (u-g, v): + d/d vx
-        if (u - g >= 0) {
-            const int64_t q = base + p - g;
-            for (int c = 0; c < 3; ++c) gP[c] += adj[(6 * k + c) * total_pix + q];
+    const int64_t q = cam.pix_off + (int64_t)v * cam.W + u;
+    float r = normal_gather_at(cam, u, v, s1, s2, [&](int k, int du, int dv) {
+        return adj[k * total_pix + q + du + (int64_t)dv * cam.W];
+    });
+    if (ddepth) r += ddepth[q];
+    gd[q] = r;
+}
+
+// One-pass form for steps up to kHaloMax: each workgroup computes the adjoints
+// of its tile and of a halo of max(s1, s2) pixels into LDS (the halo's
+// recomputed by the neighbouring tiles too) and gathers from there, instead of
+// writing twelve planes of adjoints to memory and reading them back.
+constexpr int kHaloMax = 4;
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW *TH) normal_bwd_fused_kernel(const DevCam *__restrict__ cams, int V,
+                                                                 uint32_t ntiles, const float *__restrict__ depth,
+                                                                 const float *__restrict__ dnormal,
+                                                                 const float *__restrict__ ntgt,
+                                                                 const float *__restrict__ nscale,
+                                                                 const float *__restrict__ ddepth,
+                                                                 float *__restrict__ gd, int s1, int s2, float lam,
+                                                                 int orient)
+{
+    constexpr int NE_MAX = (TW + 2 * kHaloMax) * (TH + 2 * kHaloMax);
+    __shared__ float sadj[12][NE_MAX];
+    const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+    if (tile >= ntiles) return;
+    const int view = view_of_tile(cams, V, tile);
+    const DevCam &cam = cams[view];
+    const uint32_t lt = tile - cam.tile_base;
+    const int u0 = (int)(lt % (uint32_t)cam.tiles_x) * TW, v0 = (int)(lt / (uint32_t)cam.tiles_x) * TH;
+    const int h = s1 > s2 ? s1 : s2;  // <= kHaloMax (checked by the launcher)
+    const int EW = TW + 2 * h, NE = EW * (TH + 2 * h);
+    const float *D = depth + cam.pix_off;
+    const float *dn = dnormal ? dnormal + 3 * cam.pix_off : nullptr;
+    const float *nt = ntgt ? ntgt + 3 * cam.pix_off : nullptr;
+    const float nsc = nt && !dn ? *nscale : 0.f;
+    for (int e = threadIdx.x; e < NE; e += TW * TH) {
+        const int u = u0 - h + e % EW, v = v0 - h + e / EW;
+        float out[12];
+        if (u >= 0 && u < cam.W && v >= 0 && v < cam.H) {
+            normal_adj_at(cam, D, dn, nt, nsc, u, v, s1, s2, lam, orient, out);
+        } else {
+            for (int k = 0; k < 12; ++k) out[k] = 0.f;
         }
-        if (u + g < W) {
-            const int64_t q = base + p + g;
-            for (int c = 0; c < 3; ++c) gP[c] -= adj[(6 * k + c) * total_pix + q];
-        }
-        if (v - g >= 0) {
-            const int64_t q = base + p - (int64_t)g * W;
-            for (int c = 0; c < 3; ++c) gP[c] += adj[(6 * k + 3 + c) * total_pix + q];
-        }
-        if (v + g < H) {
-            const int64_t q = base + p + (int64_t)g * W;
-            for (int c = 0; c < 3; ++c) gP[c] -= adj[(6 * k + 3 + c) * total_pix + q];
-        }
+        for (int k = 0; k < 12; ++k) sadj[k][e] = out[k];
     }
-    const float pp[3] = {((float)u - cam.cx) / cam.fx, ((float)v - cam.cy) / cam.fy, 1.f};
-    float r = dot3(gP, pp);
-    if (ddepth) r += ddepth[base + p];
-    gd[base + p] = r;
+    __syncthreads();
+    const int u = u0 + (int)(threadIdx.x % TW), v = v0 + (int)(threadIdx.x / TW);
+    if (u >= cam.W || v >= cam.H) return;
+    const int e0 = (v - v0 + h) * EW + (u - u0 + h);
+    float r = normal_gather_at(cam, u, v, s1, s2, [&](int k, int du, int dv) { return sadj[k][e0 + du + dv * EW]; });
+    const int64_t q = cam.pix_off + (int64_t)v * cam.W + u;
+    if (ddepth) r += ddepth[q];
+    gd[q] = r;
 }
 
 template <int TW, int TH>
@@ -226,6 +291,12 @@ hipError_t nbwd(const Problem &pb, const WsLayout &L, char *ws, const ugs_output
     auto cams = (const DevCam *)(ws + L.cams);
     auto adj = (float *)(ws + L.nadj);
     auto gd = (float *)(ws + L.gd);
+    if (o.step1 <= kHaloMax && o.step2 <= kHaloMax) {
+        hipLaunchKernelGGL((normal_bwd_fused_kernel<TW, TH>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), 0, s,
+                           cams, pb.V, (uint32_t)pb.total_tiles, out.depth, up.normal, up.normal_target,
+                           up.normal_scale, up.depth, gd, o.step1, o.step2, o.lambda, o.orient_sign);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((normal_adj_kernel<TW, TH>), dim3(xcd_grid(pb.total_tiles)), dim3(TW * TH), 0, s, cams, pb.V,
                        (uint32_t)pb.total_tiles, out.depth, up.normal, up.normal_target, up.normal_scale, pb.total_pix, adj,
                        o.step1, o.step2, o.lambda, o.orient_sign);
