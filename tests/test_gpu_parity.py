@@ -231,19 +231,26 @@ def test_depth_mode_parity(O, kind, mode):
         assert e <= 1.0, (k, e)
 
 
-def test_normal_backward_stage(O):
+@pytest.mark.parametrize("steps", [(1, 2), (3, 4), (1, 5)])
+def test_normal_backward_stage(O, steps):
     """Alg. normal_gradient on the GPU's own depth: G_D = dL/dD + normal branch,
-    against the oracle evaluated at the same FP32 depth."""
+    against the oracle evaluated at the same FP32 depth.  Steps (1, 2) and
+    (3, 4) run the one-pass kernel (halo 2 and its largest, 4), (1, 5) the
+    two-pass form through memory."""
+    from paper_2510_12174_amd import unigs as U
     g, cams, opts = Hn.small_workload("w2s")
-    outs, _, rast = Hn.gpu_run(g, cams, opts)
+    opts = dict(opts, step1=steps[0], step2=steps[1])
+    rast = U.Rasterizer(prune_Tk=float(opts.get("prune_Tk", 0.0)))
+    rast.set_options(step1=steps[0], step2=steps[1])
+    outs, _, rast = Hn.gpu_run(g, cams, opts, rast=rast)
     depth = outs[0]["depth"].astype(np.float64)
     on = O.normals(depth, cams[0], opts)
     ups = Hn.scenes.upstream(cams, g["C_o"], seed=5)
-    ups[0]["normal"][:, Hn.dilate_cross(on["margin"] < Hn.DELTA, 2)] = 0
+    ups[0]["normal"][:, Hn.dilate_cross(on["margin"] < Hn.DELTA, max(steps))] = 0
     outs2, _, rast = Hn.gpu_run(g, cams, opts, ups=ups, rast=rast)
     assert np.array_equal(outs2[0]["depth"], outs[0]["depth"])
     gd = rast.debug_buffer("depth_grad").cpu().numpy().astype(np.float64).reshape(cams[0]["H"], cams[0]["W"])
-    ref = O.normal_backward(depth, cams[0], ups[0]["normal"]) + ups[0]["depth"]
+    ref = O.normal_backward(depth, cams[0], ups[0]["normal"], opts) + ups[0]["depth"]
     scale = np.sqrt(np.mean(ref ** 2))
     err = np.abs(gd - ref) / (1e-3 * np.abs(ref) + 1e-3 * scale)
     Hn.say(f"normal backward stage err/tol {err.max():.3g}")
