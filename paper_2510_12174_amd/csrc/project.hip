@@ -551,13 +551,18 @@ __global__ void __launch_bounds__(kProjThreads) project_bwd_sum_kernel(ugs_gauss
     float dsh[NC][3];
     for (int c = 0; c < NC; ++c)
         for (int ch = 0; ch < 3; ++ch) dsh[c][ch] = 0.f;
+    // The views that see this Gaussian (V <= 64): their flags are loaded
+    // without a branch between them, instead of a flag, a branch and a record
+    // per view in one dependent chain.
+    uint64_t vis = 0;
+#pragma unroll 8
+    for (int v = 0; v < V; ++v) vis |= (uint64_t)(touched[(int64_t)v * N + i] != 0u) << v;
+    if (!vis) return;
     const D mu[3] = {D(g.mean[i]), D(g.mean[N + i]), D(g.mean[2 * N + i])};
-    bool any = false;
-    for (int v = 0; v < V; ++v) {
-        const int64_t idx = (int64_t)v * N + i;
-        if (touched[idx] == 0) continue;
-        any = true;
-        const float4 *gr = grec + idx * 4;
+    while (vis) {
+        const int v = __builtin_ctzll(vis);
+        vis &= vis - 1ull;
+        const float4 *gr = grec + ((int64_t)v * N + i) * 4;
         const float4 a = gr[0], b = gr[1], c2 = gr[2], d3 = gr[3];
         const float f[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c2.x, c2.y, c2.z, c2.w};
         for (int k = 0; k < 12; ++k) acc[k] += D(f[k]);
@@ -572,7 +577,6 @@ __global__ void __launch_bounds__(kProjThreads) project_bwd_sum_kernel(ugs_gauss
             for (int c = 0; c < NC; ++c) dsh[c][ch] += dc[ch] * Y[c];
         }
     }
-    if (!any) return;
     for (int e = 0; e < 3; ++e) dg.mean[e * N + i] += acc[e];
     for (int e = 0; e < 4; ++e) dg.quat[e * N + i] += acc[3 + e];
     for (int e = 0; e < 3; ++e) dg.log_scale[e * N + i] += acc[7 + e];
