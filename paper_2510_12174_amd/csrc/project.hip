@@ -337,14 +337,14 @@ __global__ void __launch_bounds__(kProjThreads) project_bwd_rec_kernel(ugs_gauss
     const int64_t N = g.N;
     constexpr int NC = (DEG + 1) * (DEG + 1);
     using D = double;  // the chain rule runs in FP64: its terms scale like 1/s^2 and cancel
-    // the list holds the records still touched after the binning walk, which
-    // sets a record's count to its kept tiles (0 when the ellipse cull drops
-    // them all): R_gauss <= R
+    // the list holds exactly the records still touched after the binning walk,
+    // which sets a record's count to its kept tiles (0 when the ellipse cull
+    // drops them all): R_gauss <= R, and no entry needs its count re-checked
     const uint32_t Rn = cnt->R_gauss;
+    (void)touched;
     for (uint64_t rr = (uint64_t)blockIdx.x * kProjThreads + threadIdx.x; rr < Rn;
          rr += (uint64_t)gridDim.x * kProjThreads) {
         const uint32_t idx = didx[rr];
-        if (touched[idx] == 0) continue;
         const int v = (int)(idx / (uint64_t)N);
         const int64_t i = (int64_t)idx - (int64_t)v * N;
         GaussState<D> G;
